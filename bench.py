@@ -1,0 +1,164 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = H (project), H^T (backproject) and FBP once each on the
+256^3 / 2048-transducer / 1024-sample workload (0.1 mm voxels, 40 seeded
+ellipsoids, Fibonacci hemisphere of radius 40 mm, 20 MHz, FP32 storage).
+Each operator performs N*Q voxel-view updates, so a step is 3*N*Q updates.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = non-packed FP32 VALU lane-ops/s.
+VALU_PEAK = 256 * 64 * 2.4e9
+# Algorithmic FP32 VALU operations of one quadrature point of G or G^T
+# (position 6 FMA, cos/sin of the azimuth 2 transcendental = 8 issue slots,
+# floor 3, fraction 3, cell address 3, trilinear 7 lerps = 14, weighted add 2).
+OPS_PER_POINT = 39
+# Algorithmic VALU operations of one FBP voxel-view update (difference 3,
+# squared norm 3, rsqrt 4, distance/kt 2, floor 2, two coefficients 4,
+# two-term sum 2, weighted add 1).
+OPS_PER_FBP_UPDATE = 21
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def quad_points(geom):
+    """Quadrature points that one G or G^T pass evaluates: every cell of the
+    footprint [-1, n-1]^3 is crossed by dx/(c0 dt) points per transducer
+    (shell spacing c0 dt, point spacing dx on each shell)."""
+    cells = (geom.nx + 1) * (geom.ny + 1) * (geom.nz + 1)
+    return cells * geom.n_det * geom.dx / (geom.c0 * geom.dt)
+
+
+def cpu_baseline(geom, img, p_np, budget_s=20.0):
+    """Time the FP64 oracle on a bounded sample of the same workload and
+    scale to voxel-view updates per second for the 3-operator step."""
+    from oracle import ref
+    gd = geom.as_dict()
+    N, Q = geom.n_vox, geom.n_det
+    res = {}
+    rows = np.arange(0, Q, 256, dtype=np.int32)          # 8 transducers
+    t = time.perf_counter()
+    ref.project(gd, img, rows=rows)
+    t_h = (time.perf_counter() - t) * Q / rows.size
+    rows_t = rows[:2]
+    t = time.perf_counter()
+    ref.backproject(gd, p_np[rows_t], rows=rows_t)
+    t_ht = (time.perf_counter() - t) * Q / rows_t.size
+    rng = np.random.default_rng(0)
+    vox = rng.choice(N, 20000, replace=False)
+    t = time.perf_counter()
+    ref.fbp(gd, p_np, voxels=vox)
+    t_f = (time.perf_counter() - t) * N / vox.size
+    total = t_h + t_ht + t_f
+    res = dict(value=3.0 * N * Q / total, unit="voxel-view updates/s",
+               cores=ref.max_threads(), kind="oracle",
+               sample=(f"H on {rows.size} of {Q} transducers, H^T on {rows_t.size}, "
+                       f"FBP on {vox.size} of {N} voxels; times scaled linearly to the "
+                       f"full operators (extrapolated s: H {t_h:.0f}, H^T {t_ht:.0f}, "
+                       f"FBP {t_f:.0f})"))
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the operators run on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1304_2017_amd import synth
+    from paper_1304_2017_amd.oat import Plan
+
+    dev = torch.device("cuda", 0)
+    log("[bench] building 256^3 workload")
+    geom, ells, img = synth.config_large(0, dtype=np.float32)
+    plan = Plan(geom, 0)
+    x = torch.from_numpy(img).to(dev)
+    p = torch.empty(plan.data_shape, device=dev)
+    a = torch.empty(plan.image_shape, device=dev)
+    f = torch.empty(plan.image_shape, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.project(x, out=p)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.backproject(p, out=a)
+        if ev is not None:
+            ev[2].record(stream)
+        plan.fbp(p, out=f)
+        if ev is not None:
+            ev[3].record(stream)
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for s in range(args.steps):
+        step(evs[s])
+        log(f"[bench] step {s} queued")
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    t_h = np.mean([e[0].elapsed_time(e[1]) for e in evs])
+    t_ht = np.mean([e[1].elapsed_time(e[2]) for e in evs])
+    t_f = np.mean([e[2].elapsed_time(e[3]) for e in evs])
+    N, Q = geom.n_vox, geom.n_det
+    value = 3.0 * N * Q / (ms * 1e-3)
+    pts = quad_points(geom)
+    # Dominant kernel: the G or G^T brick kernel (the operator call also holds
+    # one small data-side kernel, under 1% of its time).
+    dom_name, dom_ms = ("srt_adj_kernel", t_ht) if t_ht >= t_h else ("srt_fwd_kernel", t_h)
+    achieved = OPS_PER_POINT * pts / (dom_ms * 1e-3)
+    roof = dict(bound="alu", kernel=dom_name, achieved=achieved, peak=VALU_PEAK,
+                unit="VALU lane-op/s", frac=achieved / VALU_PEAK, traffic=None,
+                ops_per_point=OPS_PER_POINT, points_per_launch=pts)
+    out = dict(metric="H/H^T voxel-view updates/s", value=value, unit="voxel-view updates/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload="256^3 image (0.1 mm), 2048 transducers on a 40 mm "
+                                    "hemisphere, 1024 samples at 20 MHz; step = H + H^T + FBP",
+                           nx=256, n_det=Q, n_t=geom.n_t, storage="f32"),
+               ops=dict(H_ms=t_h, HT_ms=t_ht, FBP_ms=t_f,
+                        H_updates_per_s=N * Q / (t_h * 1e-3),
+                        HT_updates_per_s=N * Q / (t_ht * 1e-3),
+                        FBP_updates_per_s=N * Q / (t_f * 1e-3),
+                        FBP_valu_frac=OPS_PER_FBP_UPDATE * N * Q / (t_f * 1e-3) / VALU_PEAK),
+               roofline=roof)
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline (bounded sample)")
+        p_np = p.double().cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(geom, img.astype(np.float64), p_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

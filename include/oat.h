@@ -1,0 +1,150 @@
+/*
+ * oat.h -- C ABI of the MI355X (gfx950) library for the interpolation-based
+ * imaging operators of three-dimensional optoacoustic tomography.
+ *
+ * Operators (Wang, Huang, Kao, Chou, Oraevsky, Anastasio, "Accelerating image
+ * reconstruction in three-dimensional optoacoustic tomography on graphics
+ * processing units"):
+ *
+ *   oat_project      p = H alpha = D G alpha   Sec. II.B.1: Eq. (dis_srt) then Eq. (dis_g2p),
+ *                                              point-like transducers (H^e = I)
+ *   oat_backproject  alpha' = H^T y = G^T D^T y   Sec. II.C, the exact adjoint of oat_project
+ *   oat_fbp          alpha_fbp from p          Sec. III.B, Eq. (disfbp)
+ *
+ * Units: lengths in mm, times in microseconds.
+ *
+ * Image layout: C-contiguous [nz][ny][nx] (x fastest); node (ix,iy,iz) sits at
+ * (x0 + ix*dx, y0 + iy*dx, z0 + iz*dx).  alpha_n is the value at node n
+ * (Eq. (coeffint)); between nodes the image is the trilinear expansion of
+ * Eq. (expfunI), zero outside the grid.
+ *
+ * Data layout: C-contiguous [n_det][n_t] (time fastest), sample k of
+ * transducer q at t_k = t0 + k*dt; the flat index is q*n_t + k as in
+ * Eq. (CDmodel).
+ *
+ * Discretisation of G (the Appendix, made definite):
+ *  - each shell k is the sphere of radius rho_k = c0*t_k about r_q, described
+ *    in a frame with z^tr = -r_q/|r_q| (pointing at the origin),
+ *    x^tr = unit polar vector and y^tr = minus the unit azimuthal vector of r_q;
+ *  - the polar angle is cut into bands of arc length dx starting at the pole,
+ *    [i dtheta, min((i+1) dtheta, pi)] with dtheta = dx/rho_k; ring i sits at
+ *    the mid-band angle and holds N_j = max(1, round(2 pi rho_k sin(theta_i)/dx))
+ *    points at azimuths 2 pi j / N_j, each weighted by the band area / N_j;
+ *  - g[q,k] = sum of weight * (trilinear image value) over these points.
+ * D:  s_k = g_k/t_k (0 where t_k <= 0), p_k = Gamma/(4 pi c0^2) (s_{k+1}-s_{k-1})/(2 dt),
+ *     with s_{-1} = s_{n_t} = 0 (Eq. (g2p) with beta/Cp = Gamma/c0^2).
+ *
+ * Buffers: every image/data pointer passed to oat_project, oat_backproject
+ * and oat_fbp is a DEVICE pointer on the plan's device, owned by the caller,
+ * C-contiguous, and must not overlap another argument.  Each call overwrites
+ * its whole output (nothing accumulates across calls).
+ *
+ * Streams: calls are asynchronous on `stream` (a hipStream_t; NULL = the
+ * default stream).  The caller synchronises before reading outputs.  A plan
+ * holds one workspace: calls on the same plan must not overlap in time (use
+ * one stream per plan, or one plan per stream).
+ *
+ * Errors: every function returns an oat_status; nothing aborts or throws
+ * across the ABI.  Arguments are validated before anything is launched.
+ * oat_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef OAT_H
+#define OAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OAT_OK = 0,
+    OAT_ERR_ARG = -1,       /* null pointer, bad size, unknown flag */
+    OAT_ERR_GEOMETRY = -2,  /* invalid or unsupported geometry (see oat_plan_create) */
+    OAT_ERR_DTYPE = -3,     /* unknown oat_dtype */
+    OAT_ERR_DEVICE = -4,    /* HIP runtime error; text in oat_last_error() */
+    OAT_ERR_NOMEM = -5,     /* device or host allocation failed */
+    OAT_ERR_INTERNAL = -6
+} oat_status;
+
+typedef enum {
+    OAT_F32 = 0,            /* IEEE binary32 */
+    OAT_BF16 = 1            /* bfloat16 storage; arithmetic is FP32 */
+} oat_dtype;
+
+/* Problem statement (Sec. II.B and Sec. III.A).  Host memory; copied by
+ * oat_plan_create, so the caller may free it afterwards. */
+typedef struct {
+    int32_t nx, ny, nz;         /* nodes per axis, >= 1 */
+    double dx;                  /* node spacing Delta_s (mm), > 0 */
+    double x0, y0, z0;          /* position of node (0,0,0) (mm) */
+    int32_t n_det;              /* number of transducers Q, >= 1 */
+    const double *det_xyz;      /* Q x 3 transducer positions r_q (mm), host */
+    const double *det_area;     /* Q patch areas a_q (mm^2) used by oat_fbp, host;
+                                   NULL means 4 pi |r_q|^2 / Q */
+    int32_t n_t;                /* samples per transducer K, 3 <= K <= 4096 */
+    double dt;                  /* sampling interval (us), > 0 */
+    double t0;                  /* time of sample 0 (us) */
+    double c0;                  /* speed of sound (mm/us), > 0 */
+    double gamma;               /* Grueneisen coefficient Gamma = beta c0^2 / Cp, > 0 */
+} oat_geometry;
+
+typedef struct oat_plan oat_plan;
+
+/* Expose the G or G^T stage alone: oat_project returns g = G alpha and
+ * oat_backproject returns G^T y (D and D^T are skipped). */
+#define OAT_FLAG_SRT_ONLY 1u
+
+/* Validate the geometry, build the quadrature tables in FP64 on the host,
+ * upload them and allocate the workspace on `device`.
+ * Returns OAT_ERR_GEOMETRY when a transducer lies inside the sphere that
+ * holds the image support (radius R = largest corner norm of the box
+ * [x0-dx, x0+nx*dx] x ...; Sec. III.A assumes the measurement surface lies
+ * outside it), when t_k stays <= 0, or when sizes exceed 32-bit indexing.
+ * On success *out owns device memory until oat_plan_destroy. */
+int oat_plan_create(const oat_geometry *geom, int device, oat_plan **out);
+
+/* Frees the plan's tables and workspace.  NULL is accepted.  The caller
+ * must make sure no call on the plan is still running. */
+void oat_plan_destroy(oat_plan *plan);
+
+/* data = H img  (n_det x n_t), or G img with OAT_FLAG_SRT_ONLY.
+ * img: device [nz][ny][nx] of img_dtype; data: device [n_det][n_t] of
+ * data_dtype.  G is accumulated in FP32 and D is applied before any BF16
+ * rounding of the output. */
+int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data,
+                oat_dtype data_dtype, uint32_t flags, void *stream);
+
+/* img = H^T data = G^T D^T data  (or G^T data with OAT_FLAG_SRT_ONLY).
+ * data: device [n_det][n_t] of data_dtype; img: device [nz][ny][nx] of
+ * img_dtype.  Uses exactly the quadrature points and weights of
+ * oat_project, so <H x, y> = <x, H^T y> up to FP32 rounding. */
+int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void *img,
+                    oat_dtype img_dtype, uint32_t flags, void *stream);
+
+/* Filtered backprojection, Eq. (disfbp) with the patch area a_q and 1/|r_q|
+ * of each transducer:
+ *   img_n = -1/(pi Gamma c0 dt) sum_q a_q/|r_q| { [(k+1+tau)/(kt+tau) - 1.5] p[q,k]
+ *                                              + [1.5 - (k+tau)/(kt+tau)] p[q,k+1] }
+ * with kt = (|r_n - r_q|/c0 - t0)/dt, k = floor(kt), tau = t0/dt and p = 0
+ * outside [0, n_t).  pres: device [n_det][n_t]; img: device [nz][ny][nx]. */
+int oat_fbp(oat_plan *plan, const void *pres, oat_dtype pres_dtype, void *img,
+            oat_dtype img_dtype, uint32_t flags, void *stream);
+
+/* Thread-local, NUL-terminated description of the last non-OK status
+ * returned on this thread ("" if none).  Valid until the next call. */
+const char *oat_last_error(void);
+
+/* Work accounting of a plan (host values, filled at plan creation):
+ * stats[0] = number of quadrature rings in the tables,
+ * stats[1] = number of image bricks, stats[2] = brick edge (cells),
+ * stats[3] = shell window per (brick, transducer),
+ * stats[4] = bytes of device workspace, stats[5] = bytes of device tables.
+ * n = capacity of stats; returns OAT_OK. */
+int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OAT_H */

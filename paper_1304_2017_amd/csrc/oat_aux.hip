@@ -1,0 +1,206 @@
+// Data-side kernels on gfx950: the reduction of G's brick partials fused
+// with D (Eq. (dis_g2p)), its transpose D^T (Sec. II.C), the sum of partial
+// images, and the voxel-driven filtered backprojection of Eq. (disfbp).
+#include "oat_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace oat {
+
+namespace {
+
+__device__ __forceinline__ float load_val(const void *p, size_t i, int dt)
+{
+    if (dt == 0) return ((const float *)p)[i];
+    return __uint_as_float(((unsigned)((const unsigned short *)p)[i]) << 16);
+}
+
+// Round-to-nearest-even FP32 -> BF16 (values here are finite).
+__device__ __forceinline__ unsigned short to_bf16(float v)
+{
+    unsigned u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ void store_val(void *p, size_t i, int dt, float v)
+{
+    if (dt == 0)
+        ((float *)p)[i] = v;
+    else
+        ((unsigned short *)p)[i] = to_bf16(v);
+}
+
+constexpr int RED_WAVES = 4;
+
+}  // namespace
+
+// One workgroup per transducer: sum the (brick, transducer) windows of G in
+// a fixed order (each wave keeps its own copy, the copies are added in wave
+// order), then apply D on the whole trace.  Deterministic.
+__global__ void __launch_bounds__(RED_WAVES *WAVE)
+srt_reduce_kernel(Problem P, const float *__restrict__ part, const int *__restrict__ klo,
+                  void *__restrict__ out, int out_dt, int apply_d)
+{
+    extern __shared__ float sg[];   // RED_WAVES * nt
+    const int q = blockIdx.x;
+    const int K = P.nt;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    for (int i = threadIdx.x; i < RED_WAVES * K; i += blockDim.x) sg[i] = 0.f;
+    __syncthreads();
+    const int nb = P.nbx * P.nby * P.nbz;
+    float *mine = sg + wave * K;
+    for (int b = wave; b < nb; b += RED_WAVES) {
+        const size_t row = (size_t)b * P.nq + q;
+        const int kl = klo[row];
+        const float *src = part + row * P.window;
+        for (int j = lane; j < P.window; j += WAVE) {
+            int k = kl + j;
+            if (k < K) mine[k] += src[j];
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        float s = sg[k];
+        for (int w = 1; w < RED_WAVES; ++w) s += sg[w * K + k];
+        sg[k] = s;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        float v;
+        if (apply_d) {
+            // s_k = g_k / t_k (0 where t_k <= 0); p_k = coef (s_{k+1} - s_{k-1})
+            float sp = 0.f, sm = 0.f;
+            if (k + 1 < K) {
+                float t = fmaf((float)(k + 1), P.dt, P.t0);
+                sp = t > 0.f ? sg[k + 1] / t : 0.f;
+            }
+            if (k - 1 >= 0) {
+                float t = fmaf((float)(k - 1), P.dt, P.t0);
+                sm = t > 0.f ? sg[k - 1] / t : 0.f;
+            }
+            v = P.d_coef * (sp - sm);
+        } else {
+            v = sg[k];
+        }
+        store_val(out, (size_t)q * K + k, out_dt, v);
+    }
+}
+
+// g'[q,k] = coef (y_{k-1} - y_{k+1}) / t_k  (0 where t_k <= 0; y_{-1} = y_K = 0),
+// or a plain FP32 copy of y when apply_dt == 0.
+__global__ void diff_adj_kernel(Problem P, const void *__restrict__ y, int y_dt,
+                                float *__restrict__ gp, int apply_dt)
+{
+    const size_t total = (size_t)P.nq * P.nt;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % P.nt);
+        float v;
+        if (apply_dt) {
+            float t = fmaf((float)k, P.dt, P.t0);
+            float ym = k > 0 ? load_val(y, i - 1, y_dt) : 0.f;
+            float yp = k + 1 < P.nt ? load_val(y, i + 1, y_dt) : 0.f;
+            v = t > 0.f ? P.d_coef * (ym - yp) / t : 0.f;
+        } else {
+            v = load_val(y, i, y_dt);
+        }
+        gp[i] = v;
+    }
+}
+
+__global__ void sum_parts_kernel(size_t n, const float *__restrict__ part, int nparts,
+                                 void *__restrict__ img, int img_dt)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float s = part[i];
+        for (int p = 1; p < nparts; ++p) s += part[(size_t)p * n + i];
+        store_val(img, i, img_dt, s);
+    }
+}
+
+// FBP, Eq. (disfbp): one thread per voxel, loop over transducers.  k~ is
+// formed in FP32; when its fractional part lies within the FP32 error bound
+// of an integer, floor(k~) is decided in FP64 instead, because Eq. (disfbp)
+// switches its forward difference at integer k~.
+__global__ void __launch_bounds__(256)
+fbp_kernel(Problem P, const void *__restrict__ pres, int p_dt, void *__restrict__ img, int img_dt)
+{
+    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
+    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
+    const int iz = blockIdx.z;
+    if (ix >= P.nx || iy >= P.ny) return;
+    const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+    const int K = P.nt;
+    float acc = 0.f;
+    for (int q = 0; q < P.nq; ++q) {
+        const DetRec &d = P.det[q];
+        const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
+        const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+        const float ri = rsqrtf(r2);
+        const float dist = r2 * ri;
+        const float kt = fmaf(dist, P.sigma, -P.tau);
+        float kf = floorf(kt);
+        const float fr = kt - kf;
+        const float tol = 4e-6f * fabsf(kt) + 1e-5f;
+        if (fr < tol || fr > 1.f - tol) {
+            // Near an integer: decide floor(kt) in FP64 from the problem
+            // statement in physical units (no contraction in this file).
+            const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
+            const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
+            const double dist = sqrt(wx * wx + wy * wy + wz * wz);
+            const double kt64 = (dist / P.c0d - P.t0d) / P.dtd;
+            kf = (float)floor(kt64);
+        }
+        const int k = (int)kf;
+        const float inv = ri / P.sigma;   // 1 / (kt + tau)
+        const float clo = fmaf(kf + 1.f + P.tau, inv, -1.5f);
+        const float chi = fmaf(-(kf + P.tau), inv, 1.5f);
+        const size_t row = (size_t)q * K;
+        const float p0 = (k >= 0 && k < K) ? load_val(pres, row + k, p_dt) : 0.f;
+        const float p1 = (k + 1 >= 0 && k + 1 < K) ? load_val(pres, row + k + 1, p_dt) : 0.f;
+        acc = fmaf(d.fbp_w, fmaf(clo, p0, chi * p1), acc);
+    }
+    store_val(img, ((size_t)iz * P.ny + iy) * P.nx + ix, img_dt, P.fbp_scale * acc);
+}
+
+hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo, void *out,
+                             int out_dtype, int apply_d, hipStream_t s)
+{
+    size_t shm = (size_t)RED_WAVES * P.nt * sizeof(float);
+    hipLaunchKernelGGL(srt_reduce_kernel, dim3(P.nq), dim3(RED_WAVES * WAVE), shm, s, P, part, klo,
+                       out, out_dtype, apply_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp, int apply_dt,
+                           hipStream_t s)
+{
+    size_t total = (size_t)P.nq * P.nt;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(diff_adj_kernel, dim3(blocks), dim3(256), 0, s, P, y, y_dtype, gp, apply_dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const Problem &P, const float *img_part, int nparts, void *img,
+                            int img_dtype, hipStream_t s)
+{
+    size_t n = (size_t)P.nx * P.ny * P.nz;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks), dim3(256), 0, s, n, img_part, nparts, img,
+                       img_dtype);
+    return hipGetLastError();
+}
+
+hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img, int img_dtype,
+                      hipStream_t s)
+{
+    dim3 grid((P.nx + 15) / 16, (P.ny + 15) / 16, P.nz);
+    hipLaunchKernelGGL(fbp_kernel, grid, dim3(256), 0, s, P, p, p_dtype, img, img_dtype);
+    return hipGetLastError();
+}
+
+}  // namespace oat

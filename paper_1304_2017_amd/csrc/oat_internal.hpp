@@ -1,0 +1,86 @@
+// Internal tables and launch interfaces shared by the host plan and the
+// gfx950 kernels of liboat.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oat {
+
+// Edge of an image brick in cells.  One workgroup owns one brick and keeps
+// its (BRICK+2)^3 nodes in LDS.
+constexpr int BRICK = 20;
+constexpr int BOX = BRICK + 2;                // LDS nodes per axis
+constexpr int BOX_SY = BOX + 1;               // LDS row pitch (dwords), odd
+constexpr int BOX_SZ = BOX_SY * BOX + 5;      // LDS slice pitch (dwords)
+constexpr int BOX_WORDS = BOX_SZ * BOX;
+constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
+constexpr int WAVE = 64;
+constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
+
+// Per-transducer record (grid units: positions are (r - r_0)/dx).
+struct alignas(16) DetRec {
+    double uq[3];      // transducer position
+    double e3[3];      // unit vector to the origin (z of the local frame)
+    float e1[3];       // x of the local frame
+    float e2[3];       // y of the local frame
+    float dist;        // |r_q| / dx
+    float fbp_w;       // a_q / |r_q|  (mm)
+    float uqf[3];      // transducer position rounded to FP32
+    float pad;
+    double r[3];       // transducer position in mm
+    double pad2;
+};
+
+// Per-shell record: shell k holds rings [ring_base, ring_base + n_rings).
+struct alignas(16) ShellRec {
+    int32_t ring_base;
+    int32_t n_rings;
+    float rho;         // rho_k / dx
+    float inv_rho;     // dx / rho_k  (= band width in theta)
+};
+
+// Per-ring record (shell k, band i).
+struct alignas(8) RingRec {
+    double rc;         // rho cos(theta_i) / dx
+    float rs;          // rho sin(theta_i) / dx
+    int32_t nj;        // points on the ring
+    float w;           // band area / nj  (mm^2)
+    float delta;       // 2 pi / nj
+};
+
+// Everything a kernel needs about the problem (passed by value).
+struct Problem {
+    int nx, ny, nz;
+    int nq, nt;
+    int nbx, nby, nbz;     // bricks per axis
+    int window;            // shells per (brick, transducer) window
+    float rho0, rho_step;  // rho_k/dx = rho0 + k * rho_step
+    float t0, dt;
+    float d_coef;          // Gamma / (4 pi c0^2) / (2 dt)
+    float fbp_scale;       // -1 / (pi Gamma c0 dt)
+    float sigma;           // dx / (c0 dt)
+    float tau;             // t0 / dt
+    // FP64 problem statement for FBP's floor decisions (same formula as the
+    // problem statement: kt = (|r_n - r_q| / c0 - t0) / dt, r_n = r_0 + dx * n)
+    double x0, y0, z0, dxd, c0d, t0d, dtd;
+    const DetRec *det;
+    const ShellRec *shell;
+    const RingRec *ring;
+};
+
+// Launchers (defined in the .hip files); dtype: 0 = f32, 1 = bf16.
+hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part,
+                          int *klo, int qsplit, hipStream_t s);
+hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo,
+                             void *out, int out_dtype, int apply_d, hipStream_t s);
+hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp,
+                           int apply_dt, hipStream_t s);
+hipError_t launch_srt_adj(const Problem &P, const float *gp, float *img_part,
+                          void *img, int img_dtype, int qsplit, hipStream_t s);
+hipError_t launch_sum_parts(const Problem &P, const float *img_part, int nparts,
+                            void *img, int img_dtype, hipStream_t s);
+hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img,
+                      int img_dtype, hipStream_t s);
+
+}  // namespace oat

@@ -1,0 +1,378 @@
+// Host side of liboat: geometry validation, FP64 quadrature tables, device
+// workspace and the C-ABI entry points declared in include/oat.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "oat.h"
+#include "oat_internal.hpp"
+
+using namespace oat;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *where)
+{
+    g_last_error = std::string(where) + ": " + hipGetErrorName(e) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? OAT_ERR_NOMEM : OAT_ERR_DEVICE;
+}
+
+// Transducer local frame (Appendix, Fig. geo(b)): z^tr from r_q to the origin.
+void frame(const double *r, double e1[3], double e2[3], double e3[3], double *dist)
+{
+    double d = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double th = std::acos(r[2] / d);
+    double ph = std::atan2(r[1], r[0]);
+    e3[0] = -r[0] / d;
+    e3[1] = -r[1] / d;
+    e3[2] = -r[2] / d;
+    e1[0] = std::cos(th) * std::cos(ph);
+    e1[1] = std::cos(th) * std::sin(ph);
+    e1[2] = -std::sin(th);
+    e2[0] = std::sin(ph);
+    e2[1] = -std::cos(ph);
+    e2[2] = 0.0;
+    *dist = d;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct oat_plan {
+    int device = 0;
+    int nx = 0, ny = 0, nz = 0, nq = 0, nt = 0;
+    Problem P{};
+    DetRec *d_det = nullptr;
+    ShellRec *d_shell = nullptr;
+    RingRec *d_ring = nullptr;
+    float *d_part = nullptr;     // G windows [bricks][Q][window]
+    int *d_klo = nullptr;        // [bricks][Q]
+    float *d_gp = nullptr;       // D^T y  [Q][K]
+    float *d_img_part = nullptr; // G^T partial images [adj_split][N]
+    int adj_split = 1;
+    int64_t n_rings = 0;
+    int64_t ws_bytes = 0, table_bytes = 0;
+};
+
+extern "C" {
+
+const char *oat_last_error(void) { return g_last_error.c_str(); }
+
+void oat_plan_destroy(oat_plan *plan)
+{
+    if (!plan) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(plan->device);
+    void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
+                    plan->d_klo, plan->d_gp, plan->d_img_part};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    (void)hipSetDevice(prev);
+    delete plan;
+}
+
+int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
+{
+    g_last_error.clear();
+    if (!g || !out) return fail(OAT_ERR_ARG, "oat_plan_create: null argument");
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(OAT_ERR_GEOMETRY, "grid sizes must be >= 1");
+    if (!(g->dx > 0.0) || !is_fin(g->dx)) return fail(OAT_ERR_GEOMETRY, "dx must be > 0");
+    if (!is_fin(g->x0) || !is_fin(g->y0) || !is_fin(g->z0))
+        return fail(OAT_ERR_GEOMETRY, "grid origin must be finite");
+    if (g->n_det < 1 || !g->det_xyz) return fail(OAT_ERR_ARG, "need n_det >= 1 and det_xyz");
+    if (g->n_t < 3) return fail(OAT_ERR_GEOMETRY, "n_t must be >= 3");
+    if (!(g->dt > 0.0) || !is_fin(g->dt)) return fail(OAT_ERR_GEOMETRY, "dt must be > 0");
+    if (!is_fin(g->t0)) return fail(OAT_ERR_GEOMETRY, "t0 must be finite");
+    if (!(g->c0 > 0.0) || !is_fin(g->c0)) return fail(OAT_ERR_GEOMETRY, "c0 must be > 0");
+    if (!(g->gamma > 0.0) || !is_fin(g->gamma)) return fail(OAT_ERR_GEOMETRY, "gamma must be > 0");
+    const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+    if (N >= (1ll << 31) || (int64_t)g->n_det * g->n_t >= (1ll << 31))
+        return fail(OAT_ERR_GEOMETRY, "image or data larger than 2^31 elements");
+    if (g->n_t > 4096)
+        return fail(OAT_ERR_GEOMETRY, "n_t must be <= 4096");
+    if (g->t0 + (g->n_t - 1) * g->dt <= 0.0)
+        return fail(OAT_ERR_GEOMETRY, "all sample times are <= 0");
+
+    const int Q = g->n_det, K = g->n_t;
+    const double dx = g->dx;
+    // Support radius: farthest corner of [x0-dx, x0+nx*dx] x ... (Sec. III.A).
+    double lo[3] = {g->x0 - dx, g->y0 - dx, g->z0 - dx};
+    double hi[3] = {g->x0 + g->nx * dx, g->y0 + g->ny * dx, g->z0 + g->nz * dx};
+    double R2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double m = std::fmax(std::fabs(lo[a]), std::fabs(hi[a]));
+        R2 += m * m;
+    }
+    const double R = std::sqrt(R2);
+
+    std::vector<DetRec> det(Q);
+    double dmin = 1e300, dmax = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const double *r = g->det_xyz + 3 * (size_t)q;
+        if (!is_fin(r[0]) || !is_fin(r[1]) || !is_fin(r[2]))
+            return fail(OAT_ERR_GEOMETRY, "transducer position not finite");
+        double e1[3], e2[3], e3[3], d;
+        frame(r, e1, e2, e3, &d);
+        if (!(d > R)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf,
+                          "transducer %d at distance %.6g mm lies inside the support sphere "
+                          "(radius %.6g mm)", q, d, R);
+            return fail(OAT_ERR_GEOMETRY, buf);
+        }
+        if (g->det_area && !(g->det_area[q] >= 0.0 && is_fin(g->det_area[q])))
+            return fail(OAT_ERR_GEOMETRY, "patch areas must be finite and >= 0");
+        dmin = std::fmin(dmin, d);
+        dmax = std::fmax(dmax, d);
+        DetRec &D = det[q];
+        D.uq[0] = (r[0] - g->x0) / dx;
+        D.uq[1] = (r[1] - g->y0) / dx;
+        D.uq[2] = (r[2] - g->z0) / dx;
+        for (int a = 0; a < 3; ++a) {
+            D.e3[a] = e3[a];
+            D.e1[a] = (float)e1[a];
+            D.e2[a] = (float)e2[a];
+            D.uqf[a] = (float)D.uq[a];
+        }
+        D.dist = (float)(d / dx);
+        double area = g->det_area ? g->det_area[q] : 4.0 * M_PI * d * d / Q;
+        D.fbp_w = (float)(area / d);
+        D.pad = 0.f;
+        D.r[0] = r[0];
+        D.r[1] = r[1];
+        D.r[2] = r[2];
+        D.pad2 = 0.0;
+    }
+
+    // Quadrature tables in FP64 (Appendix; bands of arc length dx from the pole).
+    std::vector<ShellRec> shell(K);
+    std::vector<RingRec> ring;
+    for (int k = 0; k < K; ++k) {
+        double rho = g->c0 * (g->t0 + k * g->dt);
+        ShellRec &S = shell[k];
+        S.ring_base = (int32_t)ring.size();
+        S.n_rings = 0;
+        S.rho = (float)(rho / dx);
+        S.inv_rho = rho > 0.0 ? (float)(dx / rho) : 0.f;
+        if (!(rho > 0.0) || rho < dmin - R || rho > dmax + R) continue;
+        double dth = dx / rho;
+        long nring = (long)std::ceil(M_PI / dth);
+        if ((int64_t)ring.size() + nring >= (1ll << 31))
+            return fail(OAT_ERR_GEOMETRY, "quadrature tables exceed 2^31 rings");
+        S.n_rings = (int32_t)nring;
+        for (long i = 0; i < nring; ++i) {
+            double tlo = i * dth;
+            double thi = (i + 1) * dth;
+            if (thi > M_PI) thi = M_PI;
+            double th = 0.5 * (tlo + thi);
+            double area = 2.0 * M_PI * rho * rho * (std::cos(tlo) - std::cos(thi));
+            long nj = (long)std::floor(2.0 * M_PI * rho * std::sin(th) / dx + 0.5);
+            if (nj < 1) nj = 1;
+            RingRec rr;
+            rr.rc = rho * std::cos(th) / dx;
+            rr.rs = (float)(rho * std::sin(th) / dx);
+            rr.nj = (int32_t)nj;
+            rr.w = (float)(area / (double)nj);
+            rr.delta = (float)(2.0 * M_PI / (double)nj);
+            ring.push_back(rr);
+        }
+    }
+    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f});
+
+    oat_plan *plan = new (std::nothrow) oat_plan();
+    if (!plan) return fail(OAT_ERR_NOMEM, "host allocation failed");
+    plan->device = device;
+    plan->nx = g->nx;
+    plan->ny = g->ny;
+    plan->nz = g->nz;
+    plan->nq = Q;
+    plan->nt = K;
+    plan->n_rings = (int64_t)ring.size();
+
+    Problem &P = plan->P;
+    P.nx = g->nx;
+    P.ny = g->ny;
+    P.nz = g->nz;
+    P.nq = Q;
+    P.nt = K;
+    P.nbx = (g->nx + BRICK - 1) / BRICK;
+    P.nby = (g->ny + BRICK - 1) / BRICK;
+    P.nbz = (g->nz + BRICK - 1) / BRICK;
+    P.rho0 = (float)(g->c0 * g->t0 / dx);
+    P.rho_step = (float)(g->c0 * g->dt / dx);
+    {
+        // Widest shell range seen by a brick: the cell box spans BRICK+1 cells.
+        double diag = std::sqrt(3.0) * (BRICK + 1) + 0.2;
+        int w = (int)std::ceil(diag / (g->c0 * g->dt / dx)) + 3;
+        if (w > K) w = K;
+        if (w > WMAX) {
+            delete plan;
+            return fail(OAT_ERR_GEOMETRY, "c0*dt/dx too small: shell window exceeds the kernel limit");
+        }
+        P.window = w;
+    }
+    P.t0 = (float)g->t0;
+    P.dt = (float)g->dt;
+    P.d_coef = (float)(g->gamma / (4.0 * M_PI * g->c0 * g->c0) / (2.0 * g->dt));
+    P.fbp_scale = (float)(-1.0 / (M_PI * g->gamma * g->c0 * g->dt));
+    P.sigma = (float)(dx / (g->c0 * g->dt));
+    P.tau = (float)(g->t0 / g->dt);
+    P.x0 = g->x0;
+    P.y0 = g->y0;
+    P.z0 = g->z0;
+    P.dxd = dx;
+    P.c0d = g->c0;
+    P.t0d = g->t0;
+    P.dtd = g->dt;
+
+    const int nbricks = P.nbx * P.nby * P.nbz;
+    plan->adj_split = 1;
+
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        delete plan;
+        return fail_hip(e, "hipSetDevice");
+    }
+    auto alloc = [&](void **p, size_t bytes, const char *what) -> hipError_t {
+        hipError_t err = hipMalloc(p, bytes < 16 ? 16 : bytes);
+        if (err != hipSuccess) g_last_error = std::string("hipMalloc ") + what;
+        return err;
+    };
+    size_t det_b = sizeof(DetRec) * Q, sh_b = sizeof(ShellRec) * K,
+           ring_b = sizeof(RingRec) * ring.size();
+    size_t part_b = sizeof(float) * (size_t)nbricks * Q * P.window;
+    size_t klo_b = sizeof(int) * (size_t)nbricks * Q;
+    size_t gp_b = sizeof(float) * (size_t)Q * K;
+    size_t imgp_b = plan->adj_split > 1 ? sizeof(float) * (size_t)plan->adj_split * N : 0;
+    if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_part, part_b, "partials")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_klo, klo_b, "klo")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
+        (imgp_b && (e = alloc((void **)&plan->d_img_part, imgp_b, "img_part")) != hipSuccess)) {
+        int code = fail_hip(e, "oat_plan_create: hipMalloc");
+        oat_plan_destroy(plan);
+        (void)hipSetDevice(prev);
+        return code;
+    }
+    if ((e = hipMemcpy(plan->d_det, det.data(), det_b, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(plan->d_shell, shell.data(), sh_b, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(plan->d_ring, ring.data(), ring_b, hipMemcpyHostToDevice)) != hipSuccess) {
+        int code = fail_hip(e, "oat_plan_create: hipMemcpy");
+        oat_plan_destroy(plan);
+        (void)hipSetDevice(prev);
+        return code;
+    }
+    (void)hipSetDevice(prev);
+    P.det = plan->d_det;
+    P.shell = plan->d_shell;
+    P.ring = plan->d_ring;
+    plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + imgp_b);
+    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b);
+    *out = plan;
+    return OAT_OK;
+}
+
+int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n)
+{
+    if (!plan || !stats || n < 0) return fail(OAT_ERR_ARG, "oat_plan_stats: null argument");
+    int64_t v[6] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
+                    plan->P.window, plan->ws_bytes, plan->table_bytes};
+    for (int i = 0; i < n && i < 6; ++i) stats[i] = v[i];
+    return OAT_OK;
+}
+
+static int check_common(oat_plan *plan, const void *a, int adt, const void *b, int bdt,
+                        uint32_t flags, uint32_t allowed, const char *who)
+{
+    if (!plan) return fail(OAT_ERR_ARG, std::string(who) + ": null plan");
+    if (!a || !b) return fail(OAT_ERR_ARG, std::string(who) + ": null buffer");
+    if (a == b) return fail(OAT_ERR_ARG, std::string(who) + ": input and output alias");
+    if ((adt != OAT_F32 && adt != OAT_BF16) || (bdt != OAT_F32 && bdt != OAT_BF16))
+        return fail(OAT_ERR_DTYPE, std::string(who) + ": unknown dtype");
+    if (flags & ~allowed) return fail(OAT_ERR_ARG, std::string(who) + ": unknown flag");
+    return OAT_OK;
+}
+
+static int with_device(oat_plan *plan, int &prev)
+{
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(plan->device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    return OAT_OK;
+}
+
+int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data,
+                oat_dtype data_dtype, uint32_t flags, void *stream)
+{
+    int rc = check_common(plan, img, img_dtype, data, data_dtype, flags, OAT_FLAG_SRT_ONLY,
+                          "oat_project");
+    if (rc) return rc;
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_srt_fwd(plan->P, img, (int)img_dtype, plan->d_part, plan->d_klo, 1, s);
+    if (e == hipSuccess)
+        e = launch_srt_reduce(plan->P, plan->d_part, plan->d_klo, data, (int)data_dtype,
+                              (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_project: launch");
+    return OAT_OK;
+}
+
+int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void *img,
+                    oat_dtype img_dtype, uint32_t flags, void *stream)
+{
+    int rc = check_common(plan, data, data_dtype, img, img_dtype, flags, OAT_FLAG_SRT_ONLY,
+                          "oat_backproject");
+    if (rc) return rc;
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_diff_adj(plan->P, data, (int)data_dtype, plan->d_gp,
+                                   (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
+    if (e == hipSuccess)
+        e = launch_srt_adj(plan->P, plan->d_gp, plan->d_img_part, img, (int)img_dtype,
+                           plan->adj_split, s);
+    if (e == hipSuccess && plan->adj_split > 1)
+        e = launch_sum_parts(plan->P, plan->d_img_part, plan->adj_split, img, (int)img_dtype, s);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_backproject: launch");
+    return OAT_OK;
+}
+
+int oat_fbp(oat_plan *plan, const void *pres, oat_dtype pres_dtype, void *img, oat_dtype img_dtype,
+            uint32_t flags, void *stream)
+{
+    int rc = check_common(plan, pres, pres_dtype, img, img_dtype, flags, 0u, "oat_fbp");
+    if (rc) return rc;
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    hipError_t e = launch_fbp(plan->P, pres, (int)pres_dtype, img, (int)img_dtype,
+                              (hipStream_t)stream);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_fbp: launch");
+    return OAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,498 @@
+// Brick-driven spherical Radon transform G and its exact adjoint G^T on
+// gfx950 (CDNA4, wave64).
+//
+// G  (Eq. (dis_srt)): g[q,k] = sum_{i,j} w_{k,i} Psi(alpha; x_{q,k,i,j})
+// G^T (adjoint, Sec. II.C): alpha'_n = sum_{q,k,i,j} w_{k,i} g'[q,k] psi_n(x_{q,k,i,j})
+//
+// The image is cut into bricks of BRICK^3 cells.  A workgroup owns one brick
+// and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, an FP32
+// accumulator for G^T.  Each wave takes one transducer at a time and
+// enumerates exactly the quadrature points whose trilinear cell lies in the
+// brick, in three wave-wide expansions:
+//   shells k -> candidate rings (k, i) -> ring segments -> points.
+// Every point's position is a deterministic function of (q, k, i, j) and
+// the same code evaluates it in both kernels, so each point belongs to
+// exactly one brick of G and the adjoint uses the identical point set.
+#include "oat_internal.hpp"
+#include "oat_geom.hpp"
+
+#pragma clang fp contract(off)
+
+namespace oat {
+
+namespace {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int bperm_i(int src, int v)
+{
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+__device__ __forceinline__ float bperm_f(int src, float v)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ int incl_scan(int v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(v, o, WAVE);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t mask_below() { return (1ull << lane_id()) - 1ull; }
+
+// One level of wave-wide expansion: producer lanes hold counts, consumers
+// walk the concatenation 64 items at a time.  Head bits mark where each
+// producer's run starts; a ballot plus popcount turns them into a rank and a
+// rank -> lane table gives the producer.
+struct Level {
+    unsigned *bits;
+    unsigned char *prod;
+    int excl, total, base;
+};
+
+__device__ __forceinline__ void level_begin(Level &L, int cnt)
+{
+    int incl = incl_scan(cnt);
+    L.total = __shfl(incl, WAVE - 1, WAVE);
+    L.excl = incl - cnt;
+    L.base = 0;
+    int nw = (L.total + 31) >> 5;
+    for (int w = lane_id(); w < nw; w += WAVE) L.bits[w] = 0u;
+    uint64_t nz = __ballot(cnt > 0);
+    int rank = __popcll(nz & mask_below());
+    wave_sync();
+    if (cnt > 0) {
+        atomicOr(&L.bits[L.excl >> 5], 1u << (L.excl & 31));
+        L.prod[rank] = (unsigned char)lane_id();
+    }
+    wave_sync();
+}
+
+// Consumer side of a window starting at F (uniform control flow).
+__device__ __forceinline__ bool level_item(Level &L, int F, int &src, int &local)
+{
+    int idx = F + lane_id();
+    bool valid = idx < L.total;
+    unsigned word = L.bits[(valid ? idx : 0) >> 5];
+    bool head = valid && ((word >> (idx & 31)) & 1u);
+    uint64_t hm = __ballot(head);
+    int rank = L.base + __popcll(hm & (mask_below() | (1ull << lane_id()))) - 1;
+    L.base += __popcll(hm);
+    rank = min(max(rank, 0), WAVE - 1);
+    src = valid ? (int)L.prod[rank] : 0;
+    int se = bperm_i(src, L.excl);
+    local = idx - se;
+    return valid;
+}
+
+constexpr int CAP1 = 64;   // candidate rings per shell per pass (64 * 64 bits)
+constexpr int CAP2 = 16;   // segments per ring per pass (64 * 16 bits)
+
+// Per-wave LDS scratch.
+struct WaveLds {
+    unsigned bits1[128];
+    unsigned bits2[32];
+    unsigned bits3[64];
+    unsigned char prod1[64];
+    unsigned char prod2[64];
+    unsigned char prod3[64];
+    float gwin[WMAX];
+};
+
+// Cell box of brick b for G (owner cells) or G^T (cells touching owned nodes).
+__device__ __forceinline__ void brick_box(const Problem &P, int b, bool adj, int lo[3], int hi[3],
+                                          int n0[3], int n1[3])
+{
+    int bx = b % P.nbx, by = (b / P.nbx) % P.nby, bz = b / (P.nbx * P.nby);
+    const int bi[3] = {bx, by, bz};
+    const int nb[3] = {P.nbx, P.nby, P.nbz};
+    const int n[3] = {P.nx, P.ny, P.nz};
+    for (int a = 0; a < 3; ++a) {
+        n0[a] = bi[a] * BRICK;
+        n1[a] = min(n0[a] + BRICK, n[a]);
+        lo[a] = n0[a] - 1;
+        if (adj)
+            hi[a] = n1[a];                                   // cells n0-1 .. n1-1
+        else
+            hi[a] = (bi[a] == nb[a] - 1) ? n[a] : n1[a] - 1; // cells partition [-1, n)
+    }
+}
+
+// Walk all points of transducer q owned by the brick.  Fn is called per
+// window of 64 points with (valid&owned, cell index relative to the box,
+// fractions, item value, shell index).
+template <bool ADJ, class Fn>
+__device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[3], const int hi[3],
+                                          WaveLds &W, const float *gp, int &klo_out, Fn &&fn)
+{
+    const DetRec &d = P.det[q];
+    const double uq[3] = {d.uq[0], d.uq[1], d.uq[2]};
+    const double e3[3] = {d.e3[0], d.e3[1], d.e3[2]};
+    const float e1[3] = {d.e1[0], d.e1[1], d.e1[2]};
+    const float e2[3] = {d.e2[0], d.e2[1], d.e2[2]};
+    ArcUnit U;
+    arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
+
+    // Shells that can reach the box.
+    float dmin2 = 0.f, dmax2 = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        float u = (float)uq[a];
+        float dl = (float)lo[a] - u, dh = u - (float)hi[a];
+        float dm = fmaxf(fmaxf(dl, dh), 0.f);
+        dmin2 += dm * dm;
+        float e = fmaxf(fabsf(u - (float)lo[a]), fabsf(u - (float)hi[a]));
+        dmax2 += e * e;
+    }
+    float dmin = sqrtf(dmin2) - 0.1f, dmax = sqrtf(dmax2) + 0.1f;
+    int klo = max(0, (int)ceilf((dmin - P.rho0) / P.rho_step));
+    int khi = min(P.nt - 1, (int)floorf((dmax - P.rho0) / P.rho_step));
+    khi = min(khi, klo + P.window - 1);
+    klo_out = klo;
+
+    const float D = sqrtf(U.rhov2 + U.V3 * U.V3);
+    const float thb = acos_approx(U.V3 / D);
+    const float h2 = U.h2;
+
+    Level L1{W.bits1, W.prod1, 0, 0, 0};
+    Level L2{W.bits2, W.prod2, 0, 0, 0};
+    Level L3{W.bits3, W.prod3, 0, 0, 0};
+
+    for (int kc = klo; kc <= khi; kc += WAVE) {
+        // Level 1 producers: one shell per lane -> candidate ring range.
+        int k = kc + lane_id();
+        int cnt_all = 0, ilo_all = 0, rbase = 0;
+        if (k <= khi) {
+            ShellRec sh = P.shell[k];
+            if (sh.n_rings > 0) {
+                float rho = sh.rho;
+                float om = (h2 - (rho - D) * (rho - D)) / (2.f * rho * D);   // 1 - cos(delta)
+                if (om > 0.f) {
+                    float delta = om >= 2.f ? kPi : acos_approx(1.f - om);
+                    float tlo = (thb - delta) * rho - 0.5f;
+                    float thi = (thb + delta) * rho - 0.5f;
+                    int i0 = max(0, (int)floorf(tlo) - 2);
+                    int i1 = min(sh.n_rings - 1, (int)ceilf(thi) + 2);
+                    if (i1 >= i0) {
+                        cnt_all = i1 - i0 + 1;
+                        ilo_all = i0;
+                        rbase = sh.ring_base;
+                    }
+                }
+            }
+        }
+        // Candidate rings are taken CAP1 per shell per pass so the head
+        // bitmap never exceeds 64 * CAP1 bits.
+        for (int pass1 = 0; __ballot(cnt_all - pass1 * CAP1 > 0) != 0ull; ++pass1) {
+        const int cnt1 = min(max(cnt_all - pass1 * CAP1, 0), CAP1);
+        const int ilo = ilo_all + pass1 * CAP1;
+        level_begin(L1, cnt1);
+        for (int F1 = 0; F1 < L1.total; F1 += WAVE) {
+            int s1, loc1;
+            bool v1 = level_item(L1, F1, s1, loc1);
+            int kr = bperm_i(s1, k);
+            int ir = bperm_i(s1, ilo) + loc1;
+            int rb = bperm_i(s1, rbase);
+            // Ring (kr, ir): centre in FP64, arc of indices inside the box.
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, r = 0.f, w = 0.f, dlt = 0.f;
+            int nj = 1, jlo = 0, jcnt = 0, L = 1, n1 = 0, items_all = 0;
+            if (v1) {
+                const RingRec rr = P.ring[rb + ir];
+                C0 = (float)fma(rr.rc, e3[0], uq[0]);
+                C1 = (float)fma(rr.rc, e3[1], uq[1]);
+                C2 = (float)fma(rr.rc, e3[2], uq[2]);
+                r = rr.rs;
+                nj = rr.nj;
+                w = rr.w;
+                dlt = rr.delta;
+                const float C[3] = {C0, C1, C2};
+                ring_arc(U, C, r, (float)rr.rc, nj, jlo, jcnt);
+                if (jcnt > 0) {
+                    L = seg_len(nj);
+                    int jend = jlo + jcnt;
+                    if (jend <= nj) {
+                        n1 = (jend - 1) / L - jlo / L + 1;
+                        items_all = n1;
+                    } else {
+                        n1 = (nj - 1) / L - jlo / L + 1;
+                        items_all = n1 + (jend - nj - 1) / L + 1;
+                    }
+                }
+            }
+            if (ADJ && v1 && items_all > 0) w = w * gp[(size_t)q * P.nt + kr];
+            for (int pass2 = 0; __ballot(items_all - pass2 * CAP2 > 0) != 0ull; ++pass2) {
+            const int nitems = min(max(items_all - pass2 * CAP2, 0), CAP2);
+            level_begin(L2, nitems);
+            for (int F2 = 0; F2 < L2.total; F2 += WAVE) {
+                int s2, m;
+                bool v2 = level_item(L2, F2, s2, m);
+                m += pass2 * CAP2;
+                const float c0 = bperm_f(s2, C0), c1 = bperm_f(s2, C1), c2 = bperm_f(s2, C2);
+                const float rr2 = bperm_f(s2, r), w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
+                const int nj2 = bperm_i(s2, nj), jlo2 = bperm_i(s2, jlo), jc2 = bperm_i(s2, jcnt);
+                const int L2s = bperm_i(s2, L), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
+                // Segment of this item and its index range.
+                int s, jb, je;
+                if (m < n12) {
+                    s = jlo2 / L2s + m;
+                    jb = max(s * L2s, jlo2);
+                    je = min(min((s + 1) * L2s, nj2), jlo2 + jc2);
+                } else {
+                    s = m - n12;
+                    jb = s * L2s;
+                    je = min(min((s + 1) * L2s, nj2), jlo2 + jc2 - nj2);
+                }
+                const int sb = s * L2s, se = min(sb + L2s, nj2);
+                const int jref = sb + ((se - sb - 1) >> 1);
+                float cr, sr;
+                sincos_turns((float)jref / (float)nj2, cr, sr);
+                const float a0 = rr2 * e1[0], a1 = rr2 * e1[1], a2 = rr2 * e1[2];
+                const float b0 = rr2 * e2[0], b1 = rr2 * e2[1], b2 = rr2 * e2[2];
+                const float A0 = fmaf(a0, cr, b0 * sr), A1 = fmaf(a1, cr, b1 * sr), A2 = fmaf(a2, cr, b2 * sr);
+                const float B0 = fmaf(b0, cr, -(a0 * sr)), B1 = fmaf(b1, cr, -(a1 * sr)),
+                            B2 = fmaf(b2, cr, -(a2 * sr));
+                const float P0 = c0 + A0, P1 = c1 + A1, P2 = c2 + A2;
+                const int dj0 = jb - jref;
+                const int npts = v2 ? max(je - jb, 0) : 0;
+                level_begin(L3, npts);
+                for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
+                    int s3, loc3;
+                    bool v3 = level_item(L3, F3, s3, loc3);
+                    const float p0 = bperm_f(s3, P0), p1 = bperm_f(s3, P1), p2 = bperm_f(s3, P2);
+                    const float x0 = bperm_f(s3, A0), x1 = bperm_f(s3, A1), x2 = bperm_f(s3, A2);
+                    const float y0 = bperm_f(s3, B0), y1 = bperm_f(s3, B1), y2 = bperm_f(s3, B2);
+                    const float dd = bperm_f(s3, dl2), wv = bperm_f(s3, w2);
+                    const int dj = bperm_i(s3, dj0) + loc3;
+                    const int kk = bperm_i(s3, k2);
+                    float cm1, sn;
+                    small_rot((float)dj * dd, cm1, sn);
+                    const float ux = fmaf(y0, sn, fmaf(x0, cm1, p0));
+                    const float uy = fmaf(y1, sn, fmaf(x1, cm1, p1));
+                    const float uz = fmaf(y2, sn, fmaf(x2, cm1, p2));
+                    const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+                    const int cx = (int)fx0 - lo[0], cy = (int)fy0 - lo[1], cz = (int)fz0 - lo[2];
+                    const bool own = v3 && (unsigned)cx < (unsigned)(hi[0] - lo[0]) &&
+                                     (unsigned)cy < (unsigned)(hi[1] - lo[1]) &&
+                                     (unsigned)cz < (unsigned)(hi[2] - lo[2]);
+                    fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
+                }
+            }
+            }  // pass2
+        }
+        }  // pass1
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// G: partial sums per (brick, transducer) window.
+// ---------------------------------------------------------------------------
+template <int IMG_DT>
+__global__ void __launch_bounds__(WAVES *WAVE)
+srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
+               int *__restrict__ klo_out, int qsplit)
+{
+    __shared__ float box[BOX_WORDS];
+    __shared__ WaveLds wl[WAVES];
+    const int b = blockIdx.x;
+    int lo[3], hi[3], n0[3], n1[3];
+    brick_box(P, b, false, lo, hi, n0, n1);
+
+    // Stage nodes lo .. lo+BOX-1 (zero outside the grid).
+    for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
+        int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
+        int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
+        float v = 0.f;
+        if (gx >= 0 && gx < P.nx && gy >= 0 && gy < P.ny && gz >= 0 && gz < P.nz) {
+            size_t n = ((size_t)gz * P.ny + gy) * P.nx + gx;
+            if (IMG_DT == 0)
+                v = ((const float *)img)[n];
+            else
+                v = __uint_as_float(((unsigned)((const unsigned short *)img)[n]) << 16);
+        }
+        box[z * BOX_SZ + y * BOX_SY + x] = v;
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    WaveLds &W = wl[wave];
+    const int qper = (P.nq + qsplit - 1) / qsplit;
+    const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
+    for (int q = qb + wave; q < qe; q += WAVES) {
+        for (int j = lane; j < P.window; j += WAVE) W.gwin[j] = 0.f;
+        wave_sync();
+        int klo = 0;
+        auto gather = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz, float wv,
+                          int kk, int kbase) {
+            float val = 0.f;
+            if (own) {
+                const float *pb = box + cz * BOX_SZ + cy * BOX_SY + cx;
+                float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
+                float v100 = pb[BOX_SZ], v101 = pb[BOX_SZ + 1], v110 = pb[BOX_SZ + BOX_SY],
+                      v111 = pb[BOX_SZ + BOX_SY + 1];
+                float c00 = fmaf(fx, v001 - v000, v000), c01 = fmaf(fx, v011 - v010, v010);
+                float c10 = fmaf(fx, v101 - v100, v100), c11 = fmaf(fx, v111 - v110, v110);
+                float c0 = fmaf(fy, c01 - c00, c00), c1 = fmaf(fy, c11 - c10, c10);
+                val = fmaf(fz, c1 - c0, c0) * wv;
+            }
+            // Sum the window's values per shell (shells are non-decreasing across lanes).
+            uint64_t act = __ballot(own);
+            while (act) {
+                int first = __ffsll((unsigned long long)act) - 1;
+                int k0 = __shfl(kk, first, WAVE);
+                bool in = own && kk == k0;
+                float s = wave_sum(in ? val : 0.f);
+                if (lane_id() == 0) W.gwin[k0 - kbase] += s;
+                act &= ~__ballot(in);
+            }
+        };
+        walk_unit<false>(P, q, lo, hi, W, nullptr, klo, gather);
+        wave_sync();
+        float *dst = part + ((size_t)b * P.nq + q) * P.window;
+        for (int j = lane; j < P.window; j += WAVE) dst[j] = W.gwin[j];
+        if (lane == 0) klo_out[(size_t)b * P.nq + q] = klo;
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// G^T: accumulate each brick's nodes in LDS, flush to registers every few
+// transducer rounds, write owned nodes once.
+// ---------------------------------------------------------------------------
+constexpr int ADJ_FLUSH_ROUNDS = 8;
+constexpr int ADJ_REGS = (BRICK * BRICK * BRICK + WAVES * WAVE - 1) / (WAVES * WAVE);
+
+template <int OUT_DT>
+__global__ void __launch_bounds__(WAVES *WAVE)
+srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ img_part,
+               void *__restrict__ img, int qsplit)
+{
+    __shared__ float box[BOX_WORDS];
+    __shared__ WaveLds wl[WAVES];
+    const int b = blockIdx.x;
+    int lo[3], hi[3], n0[3], n1[3];
+    brick_box(P, b, true, lo, hi, n0, n1);
+    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0.f;
+
+    const int ox = n1[0] - n0[0], oy = n1[1] - n0[1], oz = n1[2] - n0[2];
+    const int nown = ox * oy * oz;
+    float acc[ADJ_REGS];
+#pragma unroll
+    for (int r = 0; r < ADJ_REGS; ++r) acc[r] = 0.f;
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < ADJ_REGS; ++r) {
+            int t = threadIdx.x + r * WAVES * WAVE;
+            if (t < nown) {
+                int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
+                float *pb = box + (z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1);
+                acc[r] += *pb;
+                *pb = 0.f;
+            }
+        }
+    };
+    __syncthreads();
+
+    const int wave = threadIdx.x / WAVE;
+    WaveLds &W = wl[wave];
+    const int qper = (P.nq + qsplit - 1) / qsplit;
+    const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
+    const int rounds = (qe - qb + WAVES - 1) / WAVES;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int q = qb + rd * WAVES + wave;
+        if (q < qe) {
+            int klo = 0;
+            auto scatter = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz,
+                               float wv, int kk, int kbase) {
+                (void)kk;
+                (void)kbase;
+                if (own) {
+                    float *pb = box + cz * BOX_SZ + cy * BOX_SY + cx;
+                    float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
+                    float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv, w11 = fy * fz * wv;
+                    atomicAdd(pb, gx * w00);
+                    atomicAdd(pb + 1, fx * w00);
+                    atomicAdd(pb + BOX_SY, gx * w01);
+                    atomicAdd(pb + BOX_SY + 1, fx * w01);
+                    atomicAdd(pb + BOX_SZ, gx * w10);
+                    atomicAdd(pb + BOX_SZ + 1, fx * w10);
+                    atomicAdd(pb + BOX_SZ + BOX_SY, gx * w11);
+                    atomicAdd(pb + BOX_SZ + BOX_SY + 1, fx * w11);
+                }
+            };
+            walk_unit<true>(P, q, lo, hi, W, gp, klo, scatter);
+        }
+        if ((rd + 1) % ADJ_FLUSH_ROUNDS == 0 || rd + 1 == rounds) {
+            __syncthreads();
+            flush();
+            __syncthreads();
+        }
+    }
+    if (rounds == 0) {
+        __syncthreads();
+        flush();
+    }
+#pragma unroll
+    for (int r = 0; r < ADJ_REGS; ++r) {
+        int t = threadIdx.x + r * WAVES * WAVE;
+        if (t < nown) {
+            int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
+            size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
+            if (qsplit > 1) {
+                img_part[(size_t)blockIdx.y * P.nx * P.ny * P.nz + n] = acc[r];
+            } else if (OUT_DT == 0) {
+                ((float *)img)[n] = acc[r];
+            } else {
+                unsigned u = __float_as_uint(acc[r]);
+                u += 0x7fffu + ((u >> 16) & 1u);
+                ((unsigned short *)img)[n] = (unsigned short)(u >> 16);
+            }
+        }
+    }
+}
+
+hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
+                          int qsplit, hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz, qsplit), block(WAVES * WAVE);
+    if (img_dtype == 0)
+        hipLaunchKernelGGL(srt_fwd_kernel<0>, grid, block, 0, s, P, img, part, klo, qsplit);
+    else
+        hipLaunchKernelGGL(srt_fwd_kernel<1>, grid, block, 0, s, P, img, part, klo, qsplit);
+    return hipGetLastError();
+}
+
+hipError_t launch_srt_adj(const Problem &P, const float *gp, float *img_part, void *img,
+                          int img_dtype, int qsplit, hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz, qsplit), block(WAVES * WAVE);
+    if (img_dtype == 0)
+        hipLaunchKernelGGL(srt_adj_kernel<0>, grid, block, 0, s, P, gp, img_part, img, qsplit);
+    else
+        hipLaunchKernelGGL(srt_adj_kernel<1>, grid, block, 0, s, P, gp, img_part, img, qsplit);
+    return hipGetLastError();
+}
+
+}  // namespace oat

@@ -1,0 +1,196 @@
+"""Python binding of liboat (include/oat.h): argument marshalling only.
+
+Every operator runs in the library's HIP kernels on the GPU; this module
+never computes any part of H, H^T or FBP itself and has no CPU fallback.
+torch is used for device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .synth import Geometry
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liboat.so")
+
+OAT_OK = 0
+OAT_ERR_ARG = -1
+OAT_ERR_GEOMETRY = -2
+OAT_ERR_DTYPE = -3
+OAT_ERR_DEVICE = -4
+OAT_ERR_NOMEM = -5
+OAT_ERR_INTERNAL = -6
+OAT_F32 = 0
+OAT_BF16 = 1
+OAT_FLAG_SRT_ONLY = 1
+
+EXPORTED = ("oat_plan_create", "oat_plan_destroy", "oat_project", "oat_backproject",
+            "oat_fbp", "oat_last_error", "oat_plan_stats")
+
+
+class OatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oat status {code}: {msg}")
+        self.code = code
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("z0", ctypes.c_double), ("n_det", ctypes.c_int32),
+                ("det_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("det_area", ctypes.POINTER(ctypes.c_double)),
+                ("n_t", ctypes.c_int32), ("dt", ctypes.c_double), ("t0", ctypes.c_double),
+                ("c0", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load liboat.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(
+                f"{_LIB_PATH} is missing: build it with `python -m paper_1304_2017_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp = ctypes.c_void_p
+        L.oat_plan_create.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.POINTER(vp)]
+        L.oat_plan_create.restype = ctypes.c_int
+        L.oat_plan_destroy.argtypes = [vp]
+        L.oat_plan_destroy.restype = None
+        for name in ("oat_project", "oat_backproject", "oat_fbp"):
+            f = getattr(L, name)
+            f.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_uint32, vp]
+            f.restype = ctypes.c_int
+        L.oat_last_error.argtypes = []
+        L.oat_last_error.restype = ctypes.c_char_p
+        L.oat_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.oat_plan_stats.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().oat_last_error().decode()
+
+
+def _check(code: int):
+    if code != OAT_OK:
+        raise OatError(code, last_error())
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return OAT_F32
+    if t.dtype == torch.bfloat16:
+        return OAT_BF16
+    raise TypeError(f"unsupported dtype {t.dtype}: use float32 or bfloat16")
+
+
+class Plan:
+    """Tables and workspace for one geometry on one device (oat_plan)."""
+
+    def __init__(self, geom: Geometry, device: int = 0):
+        self.geom = geom
+        self.device = int(device)
+        self._xyz = np.ascontiguousarray(geom.det_xyz, dtype=np.float64).reshape(-1, 3)
+        self._area = (None if geom.det_area is None
+                      else np.ascontiguousarray(geom.det_area, dtype=np.float64))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._g = _Geom(geom.nx, geom.ny, geom.nz, geom.dx, geom.x0, geom.y0, geom.z0,
+                        self._xyz.shape[0], self._xyz.ctypes.data_as(dp),
+                        self._area.ctypes.data_as(dp) if self._area is not None else dp(),
+                        geom.n_t, geom.dt, geom.t0, geom.c0, geom.gamma)
+        h = ctypes.c_void_p()
+        _check(lib().oat_plan_create(ctypes.byref(self._g), self.device, ctypes.byref(h)))
+        self._h = h
+
+    # -- plumbing ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().oat_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        v = (ctypes.c_int64 * 6)()
+        _check(lib().oat_plan_stats(self._h, v, 6))
+        keys = ("rings", "bricks", "brick", "window", "workspace_bytes", "table_bytes")
+        return dict(zip(keys, [int(x) for x in v]))
+
+    def _prep(self, t, shape):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("expected a torch tensor on the GPU")
+        if t.device.index != self.device:
+            raise ValueError(f"tensor on cuda:{t.device.index}, plan on device {self.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return t
+
+    def _stream(self, stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def _out(self, out, shape, dtype, like):
+        import torch
+        if out is None:
+            out = torch.empty(shape, dtype=dtype or like.dtype, device=like.device)
+        return self._prep(out, shape)
+
+    @property
+    def image_shape(self):
+        return (self.geom.nz, self.geom.ny, self.geom.nx)
+
+    @property
+    def data_shape(self):
+        return (self.geom.n_det, self.geom.n_t)
+
+    # -- operators ----------------------------------------------------------
+    def project(self, img, out=None, out_dtype=None, srt_only: bool = False, stream=None):
+        """p = H img  (Eq. (dis_srt) then Eq. (dis_g2p)); srt_only gives g = G img."""
+        img = self._prep(img, self.image_shape)
+        out = self._out(out, self.data_shape, out_dtype, img)
+        flags = OAT_FLAG_SRT_ONLY if srt_only else 0
+        _check(lib().oat_project(self._h, ctypes.c_void_p(img.data_ptr()), _dtype_code(img),
+                                 ctypes.c_void_p(out.data_ptr()), _dtype_code(out), flags,
+                                 self._stream(stream)))
+        return out
+
+    def backproject(self, data, out=None, out_dtype=None, srt_only: bool = False, stream=None):
+        """img = H^T data = G^T D^T data; srt_only gives G^T data."""
+        data = self._prep(data, self.data_shape)
+        out = self._out(out, self.image_shape, out_dtype, data)
+        flags = OAT_FLAG_SRT_ONLY if srt_only else 0
+        _check(lib().oat_backproject(self._h, ctypes.c_void_p(data.data_ptr()),
+                                     _dtype_code(data), ctypes.c_void_p(out.data_ptr()),
+                                     _dtype_code(out), flags, self._stream(stream)))
+        return out
+
+    def fbp(self, pres, out=None, out_dtype=None, stream=None):
+        """Filtered backprojection of pressure data, Eq. (disfbp)."""
+        pres = self._prep(pres, self.data_shape)
+        out = self._out(out, self.image_shape, out_dtype, pres)
+        _check(lib().oat_fbp(self._h, ctypes.c_void_p(pres.data_ptr()), _dtype_code(pres),
+                             ctypes.c_void_p(out.data_ptr()), _dtype_code(out), 0,
+                             self._stream(stream)))
+        return out

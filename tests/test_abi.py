@@ -1,0 +1,89 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/oat.h declares, and rejects bad arguments on the host before
+touching a device.  Also runs the host check of the ring/brick arc geometry
+used by the G kernels."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1304_2017_amd import oat, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "oat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(oat_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = oat.lib()
+    names = _declared()
+    assert set(names) == set(oat.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", oat.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (oat_\w+)", out))
+    assert set(names) <= exported
+
+
+def _geom(**kw):
+    g, _, _ = synth.config_small(0)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+def _create(geom):
+    p = oat._Geom()
+    xyz = np.ascontiguousarray(geom.det_xyz, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = oat._Geom(geom.nx, geom.ny, geom.nz, geom.dx, geom.x0, geom.y0, geom.z0,
+                  xyz.shape[0], xyz.ctypes.data_as(dp), dp(), geom.n_t, geom.dt, geom.t0,
+                  geom.c0, geom.gamma)
+    h = ctypes.c_void_p()
+    rc = oat.lib().oat_plan_create(ctypes.byref(p), 0, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw", [
+    dict(det_xyz=np.array([[5.0, 0.0, 0.0]])),    # transducer inside the support sphere
+    dict(dx=0.0), dict(dx=-1.0), dict(n_t=2), dict(n_t=5000), dict(dt=0.0),
+    dict(c0=0.0), dict(gamma=0.0), dict(nx=0), dict(dx=float("nan")),
+])
+def test_invalid_geometry_is_rejected_before_launch(kw):
+    rc, h = _create(_geom(**kw))
+    assert rc == oat.OAT_ERR_GEOMETRY
+    assert not h.value
+    assert oat.last_error() != ""
+
+
+def test_null_arguments():
+    L = oat.lib()
+    assert L.oat_plan_create(None, 0, None) == oat.OAT_ERR_ARG
+    assert L.oat_project(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
+    assert L.oat_backproject(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
+    assert L.oat_fbp(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
+    assert "null" in oat.last_error()
+    L.oat_plan_destroy(None)
+
+
+def test_host_arc_geometry_is_a_superset(tmp_path):
+    exe = tmp_path / "arc_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1304_2017_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "arc_check.cpp"), "-o", str(exe)],
+                   check=True)
+    for seed in (3, 4):
+        r = subprocess.run([str(exe), "600", str(seed)], capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stdout + r.stderr
+        assert r.stdout.startswith("OK"), r.stdout
+        rings, inside = map(int, r.stdout.split()[1:3])
+        assert inside > 10000

@@ -1,0 +1,211 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (relative L2 over the whole output): FP32 storage 1e-5 for H,
+H^T and FBP; G alone 1e-6 (D amplifies G's error); BF16 storage 2e-3, with
+the oracle fed the same BF16-rounded inputs.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1304_2017_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from oracle import ref  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+def _t(x, dtype=torch.float32):
+    return torch.tensor(np.asarray(x), dtype=torch.float64).to(dtype).to(_dev())
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _bf16_round(x):
+    return torch.tensor(np.asarray(x)).to(torch.bfloat16).double().numpy()
+
+
+@pytest.fixture(scope="module")
+def Plan():
+    from paper_1304_2017_amd.oat import Plan as P
+    return P
+
+
+@pytest.fixture(scope="module", params=[0, 1, 2, 3, 4])
+def small(request, Plan):
+    geom, balls, img = synth.config_small(request.param)
+    return geom, balls, img, Plan(geom, 0), request.param
+
+
+def test_srt_only_matches_oracle(small):
+    geom, _, img, plan, seed = small
+    _say(f"[gpu] G 32^3 seed {seed}")
+    g = _np(plan.project(_t(img), srt_only=True))
+    e = rel(g, ref.srt(geom.as_dict(), img))
+    _say(f"  rel {e:.3e}")
+    assert e < 1e-6
+
+
+def test_project_matches_oracle(small):
+    geom, _, img, plan, seed = small
+    _say(f"[gpu] H 32^3 seed {seed}")
+    p = _np(plan.project(_t(img)))
+    e = rel(p, ref.project(geom.as_dict(), img))
+    _say(f"  rel {e:.3e}")
+    assert e < 1e-5
+
+
+def test_backproject_matches_oracle(small):
+    geom, _, _, plan, seed = small
+    _say(f"[gpu] H^T 32^3 seed {seed}")
+    rng = np.random.default_rng(100 + seed)
+    y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
+    a = _np(plan.backproject(_t(y)))
+    e = rel(a, ref.backproject(geom.as_dict(), y))
+    _say(f"  rel {e:.3e}")
+    assert e < 1e-5
+    b = _np(plan.backproject(_t(y), srt_only=True))
+    e2 = rel(b, ref.srt_adj(geom.as_dict(), y))
+    _say(f"  G^T rel {e2:.3e}")
+    assert e2 < 1e-5
+
+
+def test_fbp_matches_oracle(small):
+    geom, balls, img, plan, seed = small
+    _say(f"[gpu] FBP 32^3 seed {seed}")
+    p = synth.nwave_balls(geom, balls).astype(np.float32).astype(np.float64)
+    f = _np(plan.fbp(_t(p)))
+    e = rel(f, ref.fbp(geom.as_dict(), p))
+    _say(f"  rel {e:.3e}")
+    assert e < 1e-5
+
+
+def test_adjoint_identity_on_gpu(small):
+    geom, _, _, plan, seed = small
+    _say(f"[gpu] adjoint 32^3 seed {seed}")
+    rng = np.random.default_rng(200 + seed)
+    x = _t(rng.normal(size=geom.shape))
+    y = _t(rng.normal(size=(geom.n_det, geom.n_t)))
+    Hx = plan.project(x)
+    HTy = plan.backproject(y)
+    torch.cuda.synchronize()
+    lhs = float(torch.dot(Hx.double().ravel(), y.double().ravel()))
+    rhs = float(torch.dot(x.double().ravel(), HTy.double().ravel()))
+    scale = float(Hx.double().norm() * y.double().norm())
+    _say(f"  |<Hx,y>-<x,H^T y>| / (|Hx||y|) = {abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_bf16_storage(small):
+    geom, balls, img, plan, seed = small
+    if seed > 1:
+        pytest.skip("two seeds suffice for BF16")
+    _say(f"[gpu] BF16 32^3 seed {seed}")
+    gd = geom.as_dict()
+    img_b = _bf16_round(img)
+    p = _np(plan.project(_t(img, torch.bfloat16), out_dtype=torch.bfloat16))
+    assert rel(p, ref.project(gd, img_b)) < 2e-3
+    rng = np.random.default_rng(300 + seed)
+    y_b = _bf16_round(rng.normal(size=(geom.n_det, geom.n_t)))
+    a = _np(plan.backproject(_t(y_b, torch.bfloat16), out_dtype=torch.bfloat16))
+    assert rel(a, ref.backproject(gd, y_b)) < 2e-3
+    pn = _bf16_round(synth.nwave_balls(geom, balls))
+    f = _np(plan.fbp(_t(pn, torch.bfloat16), out_dtype=torch.bfloat16))
+    assert rel(f, ref.fbp(gd, pn)) < 2e-3
+    # mixed: BF16 image in, FP32 data out
+    p2 = _np(plan.project(_t(img, torch.bfloat16), out_dtype=torch.float32))
+    assert rel(p2, ref.project(gd, img_b)) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Ragged grids, off-centre origins, t0 > 0, grids smaller than one brick.
+# ---------------------------------------------------------------------------
+RAGGED = [
+    dict(n=(37, 29, 23), dx=0.45, off=(0.3, -0.7, 0.2), Q=24, Rs=21.0, K=300, dt=0.08, t0=0.0),
+    dict(n=(7, 5, 9), dx=0.8, off=(0.0, 0.0, 0.0), Q=10, Rs=15.0, K=200, dt=0.1, t0=2.0),
+    dict(n=(41, 22, 3), dx=0.3, off=(-1.0, 0.5, 0.0), Q=16, Rs=18.0, K=400, dt=0.05, t0=5.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RAGGED)))
+def test_ragged_grids(case, Plan):
+    c = RAGGED[case]
+    nx, ny, nz = c["n"]
+    det = synth.fibonacci_sphere(c["Q"], c["Rs"])
+    geom = synth.Geometry(nx, ny, nz, c["dx"], synth.centred_origin(nx, c["dx"]) + c["off"][0],
+                          synth.centred_origin(ny, c["dx"]) + c["off"][1],
+                          synth.centred_origin(nz, c["dx"]) + c["off"][2], det, c["K"], c["dt"],
+                          c["t0"], 1.5, 1.3)
+    _say(f"[gpu] ragged case {case} {c}")
+    gd = geom.as_dict()
+    rng = np.random.default_rng(case)
+    img = rng.uniform(0, 1, size=geom.shape)
+    img = img.astype(np.float32).astype(np.float64)
+    plan = Plan(geom, 0)
+    g = _np(plan.project(_t(img), srt_only=True))
+    assert rel(g, ref.srt(gd, img)) < 1e-6
+    p = _np(plan.project(_t(img)))
+    assert rel(p, ref.project(gd, img)) < 1e-5
+    y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
+    a = _np(plan.backproject(_t(y)))
+    assert rel(a, ref.backproject(gd, y)) < 1e-5
+    f = _np(plan.fbp(_t(y)))
+    assert rel(f, ref.fbp(gd, y)) < 1e-5
+
+
+def test_zero_inputs_and_overwrite(Plan):
+    geom = synth.config_small(0)[0]
+    plan = Plan(geom, 0)
+    _say("[gpu] zero inputs")
+    z_img = torch.zeros(geom.shape, device=_dev())
+    z_dat = torch.zeros((geom.n_det, geom.n_t), device=_dev())
+    out_d = torch.full((geom.n_det, geom.n_t), 7.0, device=_dev())
+    out_i = torch.full(geom.shape, 7.0, device=_dev())
+    plan.project(z_img, out=out_d)
+    plan.backproject(z_dat, out=out_i)
+    torch.cuda.synchronize()
+    assert float(out_d.abs().max()) == 0.0
+    assert float(out_i.abs().max()) == 0.0
+    plan.fbp(z_dat, out=out_i)
+    torch.cuda.synchronize()
+    assert float(out_i.abs().max()) == 0.0
+
+
+def test_repeat_runs(small):
+    """H sums its brick partials in a fixed order: bit-stable.  H^T adds in
+    LDS with atomics from several waves, so repeats may differ in the last
+    bits only."""
+    geom, _, img, plan, seed = small
+    if seed:
+        pytest.skip("one seed suffices")
+    _say("[gpu] repeat runs")
+    x = _t(img)
+    a = plan.project(x).clone()
+    b = plan.project(x).clone()
+    y = torch.randn((geom.n_det, geom.n_t), device=_dev())
+    c = plan.backproject(y).clone()
+    d = plan.backproject(y).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert rel(_np(c), _np(d)) < 1e-6
