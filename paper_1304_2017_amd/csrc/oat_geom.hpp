@@ -27,6 +27,26 @@ constexpr float kInvTwoPi = 0.15915494309189533577f;
 OAT_HD float fminf_(float a, float b) { return a < b ? a : b; }
 OAT_HD float fmaxf_(float a, float b) { return a > b ? a : b; }
 
+// Reciprocal and square root for the conservative range code (results carry
+// margins): the hardware approximations on the GPU, libm on the host.
+OAT_HD float rcp_approx(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+OAT_HD float sqrt_approx(float x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
 // arccos with absolute error below 1e-4 (Abramowitz & Stegun 4.4.45 form);
 // used only for conservative ranges that carry margins of their own.
 OAT_HD float acos_approx(float x)
@@ -34,7 +54,7 @@ OAT_HD float acos_approx(float x)
     x = fminf_(1.0f, fmaxf_(-1.0f, x));
     float ax = fabsf(x);
     float p = 1.5707288f + ax * (-0.2121144f + ax * (0.0742610f - 0.0187293f * ax));
-    float r = sqrtf(1.0f - ax) * p;
+    float r = sqrt_approx(1.0f - ax) * p;
     return x >= 0.0f ? r : kPi - r;
 }
 
@@ -105,7 +125,7 @@ OAT_HD void ring_arc(const ArcUnit &U, const float C[3], float r, float rc, int 
         cnt = nj;                     // ring inside the ball: take it whole
         return;
     }
-    float kappa = num / den;
+    float kappa = num * rcp_approx(den);
     if (kappa >= 1.0f) return;
     if (kappa <= 0.0f) { cnt = nj; return; }   // wide window: whole ring
     psiw = acos_approx(kappa) + 2e-4f;
@@ -117,7 +137,7 @@ OAT_HD void ring_arc(const ArcUnit &U, const float C[3], float r, float rc, int 
             if (Ca[a] + m < U.lo[a] || Ca[a] - m > U.hi[a]) return;
             continue;
         }
-        float inv = 1.0f / m;
+        float inv = rcp_approx(m);
         float x1 = (U.lo[a] - Ca[a]) * inv;
         float x2 = (U.hi[a] - Ca[a]) * inv;
         if (x1 > 1.0f || x2 < -1.0f) return;

@@ -11,8 +11,9 @@ namespace oat {
 // its (BRICK+2)^3 nodes in LDS.
 constexpr int BRICK = 20;
 constexpr int BOX = BRICK + 2;                // LDS nodes per axis
-constexpr int BOX_SY = BOX + 1;               // LDS row pitch (dwords), odd
-constexpr int BOX_SZ = BOX_SY * BOX + 5;      // LDS slice pitch (dwords)
+constexpr int BOX_SY = BOX + 2;               // LDS row pitch (dwords)
+constexpr int BOX_SZ = BOX_SY * BOX + 38;     // LDS slice pitch (dwords); pitches chosen
+                                              // to spread arcs of any direction over banks
 constexpr int BOX_WORDS = BOX_SZ * BOX;
 constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
 constexpr int WAVE = 64;
@@ -41,12 +42,14 @@ struct alignas(16) ShellRec {
 };
 
 // Per-ring record (shell k, band i).
-struct alignas(8) RingRec {
+struct alignas(16) RingRec {
     double rc;         // rho cos(theta_i) / dx
     float rs;          // rho sin(theta_i) / dx
     int32_t nj;        // points on the ring
     float w;           // band area / nj  (mm^2)
     float delta;       // 2 pi / nj
+    float inv_nj;      // 1 / nj
+    float pad;
 };
 
 // Everything a kernel needs about the problem (passed by value).

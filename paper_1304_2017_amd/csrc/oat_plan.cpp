@@ -191,10 +191,12 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
             rr.nj = (int32_t)nj;
             rr.w = (float)(area / (double)nj);
             rr.delta = (float)(2.0 * M_PI / (double)nj);
+            rr.inv_nj = (float)(1.0 / (double)nj);
+            rr.pad = 0.f;
             ring.push_back(rr);
         }
     }
-    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f});
+    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f, 1.f, 0.f});
 
     oat_plan *plan = new (std::nothrow) oat_plan();
     if (!plan) return fail(OAT_ERR_NOMEM, "host allocation failed");
@@ -262,14 +264,14 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
     size_t part_b = sizeof(float) * (size_t)nbricks * Q * P.window;
     size_t klo_b = sizeof(int) * (size_t)nbricks * Q;
     size_t gp_b = sizeof(float) * (size_t)Q * K;
-    size_t imgp_b = plan->adj_split > 1 ? sizeof(float) * (size_t)plan->adj_split * N : 0;
+    size_t imgp_b = sizeof(float) * (size_t)plan->adj_split * N;   // G^T FP32 accumulator
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
         (e = alloc((void **)&plan->d_part, part_b, "partials")) != hipSuccess ||
         (e = alloc((void **)&plan->d_klo, klo_b, "klo")) != hipSuccess ||
         (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
-        (imgp_b && (e = alloc((void **)&plan->d_img_part, imgp_b, "img_part")) != hipSuccess)) {
+        (e = alloc((void **)&plan->d_img_part, imgp_b, "img_part")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);

@@ -41,50 +41,95 @@ __device__ __forceinline__ float bperm_f(int src, float v)
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
-__device__ __forceinline__ int incl_scan(int v)
+// Exclusive prefix sum over the wave of values below 2^BITS, and the total,
+// from one ballot per bit (no cross-lane data movement).
+template <int BITS>
+__device__ __forceinline__ int excl_scan_ballot(int v, int &total)
 {
-    const int l = lane_id();
+    const uint64_t below = (1ull << lane_id()) - 1ull;
+    int ex = 0, tot = 0;
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int t = __shfl_up(v, o, WAVE);
-        if (l >= o) v += t;
+    for (int b = 0; b < BITS; ++b) {
+        uint64_t m = __ballot((v >> b) & 1);
+        ex += __popcll(m & below) << b;
+        tot += __popcll(m) << b;
     }
-    return v;
+    total = tot;
+    return ex;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum over the 64 lanes with DPP row operations (no LDS traffic); the result
+// is returned to every lane through lane 63.
+__device__ __forceinline__ float wave_sum_dpp(float v)
+{
+    v += dpp_f<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xF>(v);   // row_half_mirror
+    v += dpp_f<0x140, 0xF>(v);   // row_mirror: every lane holds its row sum
+    v += dpp_f<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ uint64_t mask_below() { return (1ull << lane_id()) - 1ull; }
 
+// Add v[c] to the 8 trilinear corners of the cell at pb in LDS.  The FP32
+// atomic add of LDS (ds_add_f32) measured about 30x slower than a 32-bit
+// compare-and-swap on this part, so each add is a CAS on the float's bits:
+// all 8 old values are read first, all 8 swaps issued, and only swaps that
+// lost a race are retried.  The result is an FP32 sum in some order, as
+// with a native atomic add.
+__device__ __forceinline__ void lds_add8(float *pb, const float v[8])
+{
+    unsigned *u = reinterpret_cast<unsigned *>(pb);
+    const int off[8] = {0, 1, BOX_SY, BOX_SY + 1, BOX_SZ, BOX_SZ + 1, BOX_SZ + BOX_SY,
+                        BOX_SZ + BOX_SY + 1};
+    unsigned old[8], prev[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) old[c] = u[off[c]];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        prev[c] = atomicCAS(u + off[c], old[c], __float_as_uint(__uint_as_float(old[c]) + v[c]));
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        while (prev[c] != old[c]) {
+            old[c] = prev[c];
+            prev[c] = atomicCAS(u + off[c], old[c], __float_as_uint(__uint_as_float(old[c]) + v[c]));
+        }
+    }
+}
+
 // One level of wave-wide expansion: producer lanes hold counts, consumers
 // walk the concatenation 64 items at a time.  Head bits mark where each
-// producer's run starts; a ballot plus popcount turns them into a rank and a
-// rank -> lane table gives the producer.
+// producer's run starts; a ballot plus popcount turns them into a rank, and a
+// rank -> (lane, offset) table gives the producer and the local index.
 struct Level {
     unsigned *bits;
-    unsigned char *prod;
-    int excl, total, base;
+    int *prod;
+    int total, base;
 };
 
+template <int BITS>
 __device__ __forceinline__ void level_begin(Level &L, int cnt)
 {
-    int incl = incl_scan(cnt);
-    L.total = __shfl(incl, WAVE - 1, WAVE);
-    L.excl = incl - cnt;
+    int total;
+    int excl = excl_scan_ballot<BITS>(cnt, total);
+    L.total = total;
     L.base = 0;
-    int nw = (L.total + 31) >> 5;
+    int nw = (total + 31) >> 5;
     for (int w = lane_id(); w < nw; w += WAVE) L.bits[w] = 0u;
     uint64_t nz = __ballot(cnt > 0);
     int rank = __popcll(nz & mask_below());
     wave_sync();
     if (cnt > 0) {
-        atomicOr(&L.bits[L.excl >> 5], 1u << (L.excl & 31));
-        L.prod[rank] = (unsigned char)lane_id();
+        atomicOr(&L.bits[excl >> 5], 1u << (excl & 31));
+        L.prod[rank] = lane_id() | (excl << 8);
     }
     wave_sync();
 }
@@ -100,9 +145,9 @@ __device__ __forceinline__ bool level_item(Level &L, int F, int &src, int &local
     int rank = L.base + __popcll(hm & (mask_below() | (1ull << lane_id()))) - 1;
     L.base += __popcll(hm);
     rank = min(max(rank, 0), WAVE - 1);
-    src = valid ? (int)L.prod[rank] : 0;
-    int se = bperm_i(src, L.excl);
-    local = idx - se;
+    int pe = L.prod[rank];
+    src = valid ? (pe & 63) : 0;
+    local = idx - (pe >> 8);
     return valid;
 }
 
@@ -114,9 +159,9 @@ struct WaveLds {
     unsigned bits1[128];
     unsigned bits2[32];
     unsigned bits3[64];
-    unsigned char prod1[64];
-    unsigned char prod2[64];
-    unsigned char prod3[64];
+    int prod1[64];
+    int prod2[64];
+    int prod3[64];
     float gwin[WMAX];
 };
 
@@ -144,7 +189,8 @@ __device__ __forceinline__ void brick_box(const Problem &P, int b, bool adj, int
 // fractions, item value, shell index).
 template <bool ADJ, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[3], const int hi[3],
-                                          WaveLds &W, const float *gp, int &klo_out, Fn &&fn)
+                                          WaveLds &W, const float *gp, float gscale, int &klo_out,
+                                          Fn &&fn)
 {
     const DetRec &d = P.det[q];
     const double uq[3] = {d.uq[0], d.uq[1], d.uq[2]};
@@ -171,12 +217,12 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
     klo_out = klo;
 
     const float D = sqrtf(U.rhov2 + U.V3 * U.V3);
-    const float thb = acos_approx(U.V3 / D);
+    const float thb = acos_approx(U.V3 * rcp_approx(D));
     const float h2 = U.h2;
 
-    Level L1{W.bits1, W.prod1, 0, 0, 0};
-    Level L2{W.bits2, W.prod2, 0, 0, 0};
-    Level L3{W.bits3, W.prod3, 0, 0, 0};
+    Level L1{W.bits1, W.prod1, 0, 0};
+    Level L2{W.bits2, W.prod2, 0, 0};
+    Level L3{W.bits3, W.prod3, 0, 0};
 
     for (int kc = klo; kc <= khi; kc += WAVE) {
         // Level 1 producers: one shell per lane -> candidate ring range.
@@ -186,7 +232,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
             ShellRec sh = P.shell[k];
             if (sh.n_rings > 0) {
                 float rho = sh.rho;
-                float om = (h2 - (rho - D) * (rho - D)) / (2.f * rho * D);   // 1 - cos(delta)
+                float om = (h2 - (rho - D) * (rho - D)) * rcp_approx(2.f * rho * D);   // 1 - cos(delta)
                 if (om > 0.f) {
                     float delta = om >= 2.f ? kPi : acos_approx(1.f - om);
                     float tlo = (thb - delta) * rho - 0.5f;
@@ -206,7 +252,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
         for (int pass1 = 0; __ballot(cnt_all - pass1 * CAP1 > 0) != 0ull; ++pass1) {
         const int cnt1 = min(max(cnt_all - pass1 * CAP1, 0), CAP1);
         const int ilo = ilo_all + pass1 * CAP1;
-        level_begin(L1, cnt1);
+        level_begin<7>(L1, cnt1);
         for (int F1 = 0; F1 < L1.total; F1 += WAVE) {
             int s1, loc1;
             bool v1 = level_item(L1, F1, s1, loc1);
@@ -214,7 +260,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
             int ir = bperm_i(s1, ilo) + loc1;
             int rb = bperm_i(s1, rbase);
             // Ring (kr, ir): centre in FP64, arc of indices inside the box.
-            float C0 = 0.f, C1 = 0.f, C2 = 0.f, r = 0.f, w = 0.f, dlt = 0.f;
+            float C0 = 0.f, C1 = 0.f, C2 = 0.f, r = 0.f, w = 0.f, dlt = 0.f, invn = 0.f;
             int nj = 1, jlo = 0, jcnt = 0, L = 1, n1 = 0, items_all = 0;
             if (v1) {
                 const RingRec rr = P.ring[rb + ir];
@@ -225,6 +271,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 nj = rr.nj;
                 w = rr.w;
                 dlt = rr.delta;
+                invn = rr.inv_nj;
                 const float C[3] = {C0, C1, C2};
                 ring_arc(U, C, r, (float)rr.rc, nj, jlo, jcnt);
                 if (jcnt > 0) {
@@ -239,16 +286,17 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                     }
                 }
             }
-            if (ADJ && v1 && items_all > 0) w = w * gp[(size_t)q * P.nt + kr];
+            if (ADJ && v1 && items_all > 0) w = w * (gp[(size_t)q * P.nt + kr] * gscale);
             for (int pass2 = 0; __ballot(items_all - pass2 * CAP2 > 0) != 0ull; ++pass2) {
             const int nitems = min(max(items_all - pass2 * CAP2, 0), CAP2);
-            level_begin(L2, nitems);
+            level_begin<5>(L2, nitems);
             for (int F2 = 0; F2 < L2.total; F2 += WAVE) {
                 int s2, m;
                 bool v2 = level_item(L2, F2, s2, m);
                 m += pass2 * CAP2;
                 const float c0 = bperm_f(s2, C0), c1 = bperm_f(s2, C1), c2 = bperm_f(s2, C2);
                 const float rr2 = bperm_f(s2, r), w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
+                const float in2 = bperm_f(s2, invn);
                 const int nj2 = bperm_i(s2, nj), jlo2 = bperm_i(s2, jlo), jc2 = bperm_i(s2, jcnt);
                 const int L2s = bperm_i(s2, L), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
                 // Segment of this item and its index range.
@@ -265,7 +313,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 const int sb = s * L2s, se = min(sb + L2s, nj2);
                 const int jref = sb + ((se - sb - 1) >> 1);
                 float cr, sr;
-                sincos_turns((float)jref / (float)nj2, cr, sr);
+                sincos_turns((float)jref * in2, cr, sr);
                 const float a0 = rr2 * e1[0], a1 = rr2 * e1[1], a2 = rr2 * e1[2];
                 const float b0 = rr2 * e2[0], b1 = rr2 * e2[1], b2 = rr2 * e2[2];
                 const float A0 = fmaf(a0, cr, b0 * sr), A1 = fmaf(a1, cr, b1 * sr), A2 = fmaf(a2, cr, b2 * sr);
@@ -274,7 +322,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 const float P0 = c0 + A0, P1 = c1 + A1, P2 = c2 + A2;
                 const int dj0 = jb - jref;
                 const int npts = v2 ? max(je - jb, 0) : 0;
-                level_begin(L3, npts);
+                level_begin<6>(L3, npts);
                 for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
                     int s3, loc3;
                     bool v3 = level_item(L3, F3, s3, loc3);
@@ -309,7 +357,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
 // G: partial sums per (brick, transducer) window.
 // ---------------------------------------------------------------------------
 template <int IMG_DT>
-__global__ void __launch_bounds__(WAVES *WAVE)
+__global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
                int *__restrict__ klo_out, int qsplit)
 {
@@ -348,7 +396,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                           int kk, int kbase) {
             float val = 0.f;
             if (own) {
-                const float *pb = box + cz * BOX_SZ + cy * BOX_SY + cx;
+                const float *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
                 float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
                 float v100 = pb[BOX_SZ], v101 = pb[BOX_SZ + 1], v110 = pb[BOX_SZ + BOX_SY],
                       v111 = pb[BOX_SZ + BOX_SY + 1];
@@ -361,14 +409,14 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
             uint64_t act = __ballot(own);
             while (act) {
                 int first = __ffsll((unsigned long long)act) - 1;
-                int k0 = __shfl(kk, first, WAVE);
+                int k0 = __builtin_amdgcn_readlane(kk, first);
                 bool in = own && kk == k0;
-                float s = wave_sum(in ? val : 0.f);
+                float s = wave_sum_dpp(in ? val : 0.f);
                 if (lane_id() == 0) W.gwin[k0 - kbase] += s;
                 act &= ~__ballot(in);
             }
         };
-        walk_unit<false>(P, q, lo, hi, W, nullptr, klo, gather);
+        walk_unit<false>(P, q, lo, hi, W, nullptr, 1.f, klo, gather);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
         for (int j = lane; j < P.window; j += WAVE) dst[j] = W.gwin[j];
@@ -378,15 +426,16 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 }
 
 // ---------------------------------------------------------------------------
-// G^T: accumulate each brick's nodes in LDS, flush to registers every few
-// transducer rounds, write owned nodes once.
+// G^T: each brick accumulates its nodes in an FP32 LDS box; every
+// ADJ_FLUSH_ROUNDS rounds (WAVES transducers per round) the owned nodes are
+// added into an FP32 image the brick owns alone (no global atomics) and
+// cleared, which keeps each LDS partial sum short.
 // ---------------------------------------------------------------------------
 constexpr int ADJ_FLUSH_ROUNDS = 8;
-constexpr int ADJ_REGS = (BRICK * BRICK * BRICK + WAVES * WAVE - 1) / (WAVES * WAVE);
 
 template <int OUT_DT>
-__global__ void __launch_bounds__(WAVES *WAVE)
-srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ img_part,
+__global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
+srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ acc_img,
                void *__restrict__ img, int qsplit)
 {
     __shared__ float box[BOX_WORDS];
@@ -398,19 +447,16 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ img_
 
     const int ox = n1[0] - n0[0], oy = n1[1] - n0[1], oz = n1[2] - n0[2];
     const int nown = ox * oy * oz;
-    float acc[ADJ_REGS];
-#pragma unroll
-    for (int r = 0; r < ADJ_REGS; ++r) acc[r] = 0.f;
-    auto flush = [&]() {
-#pragma unroll
-        for (int r = 0; r < ADJ_REGS; ++r) {
-            int t = threadIdx.x + r * WAVES * WAVE;
-            if (t < nown) {
-                int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
-                float *pb = box + (z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1);
-                acc[r] += *pb;
-                *pb = 0.f;
-            }
+    float *acc = acc_img + (size_t)blockIdx.y * P.nx * P.ny * P.nz;
+    // first == true: store instead of add (the accumulator is not cleared beforehand)
+    auto flush = [&](bool first) {
+        for (int t = threadIdx.x; t < nown; t += blockDim.x) {
+            int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
+            float *pb = box + (z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1);
+            size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
+            float v = *pb;
+            *pb = 0.f;
+            acc[n] = first ? v : acc[n] + v;
         }
     };
     __syncthreads();
@@ -420,6 +466,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ img_
     const int qper = (P.nq + qsplit - 1) / qsplit;
     const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
     const int rounds = (qe - qb + WAVES - 1) / WAVES;
+    bool first = true;
     for (int rd = 0; rd < rounds; ++rd) {
         const int q = qb + rd * WAVES + wave;
         if (q < qe) {
@@ -429,43 +476,37 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ img_
                 (void)kk;
                 (void)kbase;
                 if (own) {
-                    float *pb = box + cz * BOX_SZ + cy * BOX_SY + cx;
+                    float *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
                     float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
                     float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv, w11 = fy * fz * wv;
-                    atomicAdd(pb, gx * w00);
-                    atomicAdd(pb + 1, fx * w00);
-                    atomicAdd(pb + BOX_SY, gx * w01);
-                    atomicAdd(pb + BOX_SY + 1, fx * w01);
-                    atomicAdd(pb + BOX_SZ, gx * w10);
-                    atomicAdd(pb + BOX_SZ + 1, fx * w10);
-                    atomicAdd(pb + BOX_SZ + BOX_SY, gx * w11);
-                    atomicAdd(pb + BOX_SZ + BOX_SY + 1, fx * w11);
+                    const float add[8] = {gx * w00, fx * w00, gx * w01, fx * w01,
+                                          gx * w10, fx * w10, gx * w11, fx * w11};
+                    lds_add8(pb, add);
                 }
             };
-            walk_unit<true>(P, q, lo, hi, W, gp, klo, scatter);
+            walk_unit<true>(P, q, lo, hi, W, gp, 1.f, klo, scatter);
         }
         if ((rd + 1) % ADJ_FLUSH_ROUNDS == 0 || rd + 1 == rounds) {
             __syncthreads();
-            flush();
+            flush(first);
+            first = false;
             __syncthreads();
         }
     }
     if (rounds == 0) {
         __syncthreads();
-        flush();
+        flush(true);
+        __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < ADJ_REGS; ++r) {
-        int t = threadIdx.x + r * WAVES * WAVE;
-        if (t < nown) {
+    if (qsplit == 1) {
+        for (int t = threadIdx.x; t < nown; t += blockDim.x) {
             int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
             size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
-            if (qsplit > 1) {
-                img_part[(size_t)blockIdx.y * P.nx * P.ny * P.nz + n] = acc[r];
-            } else if (OUT_DT == 0) {
-                ((float *)img)[n] = acc[r];
+            float v = acc[n];
+            if (OUT_DT == 0) {
+                ((float *)img)[n] = v;
             } else {
-                unsigned u = __float_as_uint(acc[r]);
+                unsigned u = __float_as_uint(v);
                 u += 0x7fffu + ((u >> 16) & 1u);
                 ((unsigned short *)img)[n] = (unsigned short)(u >> 16);
             }
