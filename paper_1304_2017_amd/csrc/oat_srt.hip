@@ -79,32 +79,6 @@ __device__ __forceinline__ float wave_sum_dpp(float v)
 
 __device__ __forceinline__ uint64_t mask_below() { return (1ull << lane_id()) - 1ull; }
 
-// Add v[c] to the 8 trilinear corners of the cell at pb in LDS.  The FP32
-// atomic add of LDS (ds_add_f32) measured about 30x slower than a 32-bit
-// compare-and-swap on this part, so each add is a CAS on the float's bits:
-// all 8 old values are read first, all 8 swaps issued, and only swaps that
-// lost a race are retried.  The result is an FP32 sum in some order, as
-// with a native atomic add.
-__device__ __forceinline__ void lds_add8(float *pb, const float v[8])
-{
-    unsigned *u = reinterpret_cast<unsigned *>(pb);
-    const int off[8] = {0, 1, BOX_SY, BOX_SY + 1, BOX_SZ, BOX_SZ + 1, BOX_SZ + BOX_SY,
-                        BOX_SZ + BOX_SY + 1};
-    unsigned old[8], prev[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) old[c] = u[off[c]];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        prev[c] = atomicCAS(u + off[c], old[c], __float_as_uint(__uint_as_float(old[c]) + v[c]));
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        while (prev[c] != old[c]) {
-            old[c] = prev[c];
-            prev[c] = atomicCAS(u + off[c], old[c], __float_as_uint(__uint_as_float(old[c]) + v[c]));
-        }
-    }
-}
-
 // One level of wave-wide expansion: producer lanes hold counts, consumers
 // walk the concatenation 64 items at a time.  Head bits mark where each
 // producer's run starts; a ballot plus popcount turns them into a rank, and a
@@ -162,7 +136,6 @@ struct WaveLds {
     int prod1[64];
     int prod2[64];
     int prod3[64];
-    float gwin[WMAX];
 };
 
 // Cell box of brick b for G (owner cells) or G^T (cells touching owned nodes).
@@ -363,6 +336,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 {
     __shared__ float box[BOX_WORDS];
     __shared__ WaveLds wl[WAVES];
+    __shared__ double gwin[WAVES][WMAX];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, false, lo, hi, n0, n1);
@@ -386,15 +360,20 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     const int wave = threadIdx.x / WAVE;
     const int lane = lane_id();
     WaveLds &W = wl[wave];
+    double *gw = gwin[wave];
     const int qper = (P.nq + qsplit - 1) / qsplit;
     const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
     for (int q = qb + wave; q < qe; q += WAVES) {
-        for (int j = lane; j < P.window; j += WAVE) W.gwin[j] = 0.f;
+        for (int j = lane; j < P.window; j += WAVE) gw[j] = 0.0;
         wave_sync();
         int klo = 0;
+        // Each lane keeps a running FP32 sum for its current shell (a lane's
+        // points arrive in shell order) and adds it to the wave's FP64 shell
+        // window with the native LDS FP64 atomic when the shell changes.
+        float racc = 0.f;
+        int rk = -1, rbase = 0;
         auto gather = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz, float wv,
                           int kk, int kbase) {
-            float val = 0.f;
             if (own) {
                 const float *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
                 float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
@@ -403,113 +382,83 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                 float c00 = fmaf(fx, v001 - v000, v000), c01 = fmaf(fx, v011 - v010, v010);
                 float c10 = fmaf(fx, v101 - v100, v100), c11 = fmaf(fx, v111 - v110, v110);
                 float c0 = fmaf(fy, c01 - c00, c00), c1 = fmaf(fy, c11 - c10, c10);
-                val = fmaf(fz, c1 - c0, c0) * wv;
-            }
-            // Sum the window's values per shell (shells are non-decreasing across lanes).
-            uint64_t act = __ballot(own);
-            while (act) {
-                int first = __ffsll((unsigned long long)act) - 1;
-                int k0 = __builtin_amdgcn_readlane(kk, first);
-                bool in = own && kk == k0;
-                float s = wave_sum_dpp(in ? val : 0.f);
-                if (lane_id() == 0) W.gwin[k0 - kbase] += s;
-                act &= ~__ballot(in);
+                float val = fmaf(fz, c1 - c0, c0) * wv;
+                if (kk != rk) {
+                    if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
+                    rk = kk;
+                    rbase = kbase;
+                    racc = 0.f;
+                }
+                racc += val;
             }
         };
         walk_unit<false>(P, q, lo, hi, W, nullptr, 1.f, klo, gather);
+        if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
-        for (int j = lane; j < P.window; j += WAVE) dst[j] = W.gwin[j];
+        for (int j = lane; j < P.window; j += WAVE) dst[j] = (float)gw[j];
         if (lane == 0) klo_out[(size_t)b * P.nq + q] = klo;
         wave_sync();
     }
 }
 
 // ---------------------------------------------------------------------------
-// G^T: each brick accumulates its nodes in an FP32 LDS box; every
-// ADJ_FLUSH_ROUNDS rounds (WAVES transducers per round) the owned nodes are
-// added into an FP32 image the brick owns alone (no global atomics) and
-// cleared, which keeps each LDS partial sum short.
+// G^T: each brick accumulates its nodes in an FP64 LDS box with the native
+// FP64 LDS atomic add (ds_add_f64; the FP32 one is microcoded on this part
+// and ~20x slower), so no partial flushes are needed; the owned nodes are
+// rounded once to the output type at the end.  16 waves share the box.
 // ---------------------------------------------------------------------------
-constexpr int ADJ_FLUSH_ROUNDS = 8;
+constexpr int ADJ_WAVES = 16;
 
 template <int OUT_DT>
-__global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
-srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ acc_img,
-               void *__restrict__ img, int qsplit)
+__global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
+srt_adj_kernel(Problem P, const float *__restrict__ gp, void *__restrict__ img)
 {
-    __shared__ float box[BOX_WORDS];
-    __shared__ WaveLds wl[WAVES];
+    __shared__ double box[BOX_WORDS];
+    __shared__ WaveLds wl[ADJ_WAVES];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, true, lo, hi, n0, n1);
-    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0.f;
-
-    const int ox = n1[0] - n0[0], oy = n1[1] - n0[1], oz = n1[2] - n0[2];
-    const int nown = ox * oy * oz;
-    float *acc = acc_img + (size_t)blockIdx.y * P.nx * P.ny * P.nz;
-    // first == true: store instead of add (the accumulator is not cleared beforehand)
-    auto flush = [&](bool first) {
-        for (int t = threadIdx.x; t < nown; t += blockDim.x) {
-            int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
-            float *pb = box + (z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1);
-            size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
-            float v = *pb;
-            *pb = 0.f;
-            acc[n] = first ? v : acc[n] + v;
-        }
-    };
+    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0.0;
     __syncthreads();
 
     const int wave = threadIdx.x / WAVE;
     WaveLds &W = wl[wave];
-    const int qper = (P.nq + qsplit - 1) / qsplit;
-    const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
-    const int rounds = (qe - qb + WAVES - 1) / WAVES;
-    bool first = true;
-    for (int rd = 0; rd < rounds; ++rd) {
-        const int q = qb + rd * WAVES + wave;
-        if (q < qe) {
-            int klo = 0;
-            auto scatter = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz,
-                               float wv, int kk, int kbase) {
-                (void)kk;
-                (void)kbase;
-                if (own) {
-                    float *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
-                    float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
-                    float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv, w11 = fy * fz * wv;
-                    const float add[8] = {gx * w00, fx * w00, gx * w01, fx * w01,
-                                          gx * w10, fx * w10, gx * w11, fx * w11};
-                    lds_add8(pb, add);
-                }
-            };
-            walk_unit<true>(P, q, lo, hi, W, gp, 1.f, klo, scatter);
-        }
-        if ((rd + 1) % ADJ_FLUSH_ROUNDS == 0 || rd + 1 == rounds) {
-            __syncthreads();
-            flush(first);
-            first = false;
-            __syncthreads();
-        }
-    }
-    if (rounds == 0) {
-        __syncthreads();
-        flush(true);
-        __syncthreads();
-    }
-    if (qsplit == 1) {
-        for (int t = threadIdx.x; t < nown; t += blockDim.x) {
-            int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
-            size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
-            float v = acc[n];
-            if (OUT_DT == 0) {
-                ((float *)img)[n] = v;
-            } else {
-                unsigned u = __float_as_uint(v);
-                u += 0x7fffu + ((u >> 16) & 1u);
-                ((unsigned short *)img)[n] = (unsigned short)(u >> 16);
+    for (int q = wave; q < P.nq; q += ADJ_WAVES) {
+        int klo = 0;
+        auto scatter = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz,
+                           float wv, int kk, int kbase) {
+            (void)kk;
+            (void)kbase;
+            if (own) {
+                double *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
+                float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
+                float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv, w11 = fy * fz * wv;
+                atomicAdd(pb, (double)(gx * w00));
+                atomicAdd(pb + 1, (double)(fx * w00));
+                atomicAdd(pb + BOX_SY, (double)(gx * w01));
+                atomicAdd(pb + BOX_SY + 1, (double)(fx * w01));
+                atomicAdd(pb + BOX_SZ, (double)(gx * w10));
+                atomicAdd(pb + BOX_SZ + 1, (double)(fx * w10));
+                atomicAdd(pb + BOX_SZ + BOX_SY, (double)(gx * w11));
+                atomicAdd(pb + BOX_SZ + BOX_SY + 1, (double)(fx * w11));
             }
+        };
+        walk_unit<true>(P, q, lo, hi, W, gp, 1.f, klo, scatter);
+    }
+    __syncthreads();
+    const int ox = n1[0] - n0[0], oy = n1[1] - n0[1], oz = n1[2] - n0[2];
+    const int nown = ox * oy * oz;
+    for (int t = threadIdx.x; t < nown; t += blockDim.x) {
+        int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
+        size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
+        float v = (float)box[(z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1)];
+        if (OUT_DT == 0) {
+            ((float *)img)[n] = v;
+        } else {
+            unsigned u = __float_as_uint(v);
+            u += 0x7fffu + ((u >> 16) & 1u);
+            ((unsigned short *)img)[n] = (unsigned short)(u >> 16);
         }
     }
 }
@@ -528,11 +477,13 @@ hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, floa
 hipError_t launch_srt_adj(const Problem &P, const float *gp, float *img_part, void *img,
                           int img_dtype, int qsplit, hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz, qsplit), block(WAVES * WAVE);
+    (void)img_part;
+    (void)qsplit;
+    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
     if (img_dtype == 0)
-        hipLaunchKernelGGL(srt_adj_kernel<0>, grid, block, 0, s, P, gp, img_part, img, qsplit);
+        hipLaunchKernelGGL(srt_adj_kernel<0>, grid, block, 0, s, P, gp, img);
     else
-        hipLaunchKernelGGL(srt_adj_kernel<1>, grid, block, 0, s, P, gp, img_part, img, qsplit);
+        hipLaunchKernelGGL(srt_adj_kernel<1>, grid, block, 0, s, P, gp, img);
     return hipGetLastError();
 }
 
