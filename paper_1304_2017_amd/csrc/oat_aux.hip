@@ -120,49 +120,90 @@ __global__ void sum_parts_kernel(size_t n, const float *__restrict__ part, int n
     }
 }
 
-// FBP, Eq. (disfbp): one thread per voxel, loop over transducers.  k~ is
-// formed in FP32; when its fractional part lies within the FP32 error bound
-// of an integer, floor(k~) is decided in FP64 instead, because Eq. (disfbp)
-// switches its forward difference at integer k~.
-__global__ void __launch_bounds__(256)
-fbp_kernel(Problem P, const void *__restrict__ pres, int p_dt, void *__restrict__ img, int img_dt)
+// FBP, Eq. (disfbp): one thread per voxel of a 16 x 16 x 1 tile, loop over
+// transducers in chunks.  For each chunk the samples a tile can touch,
+// k in [k_lo, k_lo + FBP_WIN), are staged in LDS per transducer (zero
+// outside [0, K)), so each update reads p_k and p_{k+1} with one LDS
+// access.  k~ is formed in FP32; when its fractional part lies within the
+// FP32 error bound of an integer, floor(k~) is decided in FP64 with the
+// problem statement's own formula, because Eq. (disfbp) switches its forward
+// difference at integer k~.
+constexpr int FBP_TX = 16, FBP_TY = 16;
+constexpr int FBP_LDS = 8192;   // floats of staged samples per chunk
+
+template <int P_DT, int IMG_DT>
+__global__ void __launch_bounds__(FBP_TX *FBP_TY)
+fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int win, int chunk)
 {
-    const int ix = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int iy = blockIdx.y * 16 + (threadIdx.x >> 4);
-    const int iz = blockIdx.z;
-    if (ix >= P.nx || iy >= P.ny) return;
+    __shared__ float sp[FBP_LDS];
+    __shared__ int sklo[FBP_LDS / 8];
+    const int tx = threadIdx.x % FBP_TX, ty = threadIdx.x / FBP_TX;
+    const int ix = blockIdx.x * FBP_TX + tx, iy = blockIdx.y * FBP_TY + ty, iz = blockIdx.z;
+    const bool in = ix < P.nx && iy < P.ny;
     const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+    // tile centre and half-diagonal (grid units)
+    const float cx = blockIdx.x * FBP_TX + 0.5f * (FBP_TX - 1), cy = blockIdx.y * FBP_TY + 0.5f * (FBP_TY - 1);
+    const float hd = 0.5f * sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1)));
     const int K = P.nt;
     float acc = 0.f;
-    for (int q = 0; q < P.nq; ++q) {
-        const DetRec &d = P.det[q];
-        const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
-        const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
-        const float ri = rsqrtf(r2);
-        const float dist = r2 * ri;
-        const float kt = fmaf(dist, P.sigma, -P.tau);
-        float kf = floorf(kt);
-        const float fr = kt - kf;
-        const float tol = 4e-6f * fabsf(kt) + 1e-5f;
-        if (fr < tol || fr > 1.f - tol) {
-            // Near an integer: decide floor(kt) in FP64 from the problem
-            // statement in physical units (no contraction in this file).
-            const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
-            const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
-            const double dist = sqrt(wx * wx + wy * wy + wz * wz);
-            const double kt64 = (dist / P.c0d - P.t0d) / P.dtd;
-            kf = (float)floor(kt64);
+    for (int q0 = 0; q0 < P.nq; q0 += chunk) {
+        const int nq = min(chunk, P.nq - q0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < nq; j += blockDim.x) {
+            const DetRec &d = P.det[q0 + j];
+            const float vx = cx - d.uqf[0], vy = cy - d.uqf[1], vz = fz - d.uqf[2];
+            const float dc = sqrtf(vx * vx + vy * vy + vz * vz);
+            sklo[j] = (int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2;
         }
-        const int k = (int)kf;
-        const float inv = ri / P.sigma;   // 1 / (kt + tau)
-        const float clo = fmaf(kf + 1.f + P.tau, inv, -1.5f);
-        const float chi = fmaf(-(kf + P.tau), inv, 1.5f);
-        const size_t row = (size_t)q * K;
-        const float p0 = (k >= 0 && k < K) ? load_val(pres, row + k, p_dt) : 0.f;
-        const float p1 = (k + 1 >= 0 && k + 1 < K) ? load_val(pres, row + k + 1, p_dt) : 0.f;
-        acc = fmaf(d.fbp_w, fmaf(clo, p0, chi * p1), acc);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nq * win; t += blockDim.x) {
+            const int j = t / win, i = t % win;
+            const int k = sklo[j] + i;
+            float v = 0.f;
+            if (k >= 0 && k < K) {
+                const size_t idx = (size_t)(q0 + j) * K + k;
+                v = P_DT == 0 ? ((const float *)pres)[idx]
+                              : __uint_as_float(((unsigned)((const unsigned short *)pres)[idx]) << 16);
+            }
+            sp[t] = v;
+        }
+        __syncthreads();
+        for (int j = 0; j < nq; ++j) {
+            const DetRec &d = P.det[q0 + j];
+            const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
+            const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+            const float ri = rsqrtf(r2);
+            const float dist = r2 * ri;
+            const float kt = fmaf(dist, P.sigma, -P.tau);
+            float kf = floorf(kt);
+            const float fr = kt - kf;
+            const float tol = 4e-6f * fabsf(kt) + 1e-5f;
+            if (fr < tol || fr > 1.f - tol) {
+                // Near an integer: decide floor(kt) in FP64 from the problem
+                // statement in physical units (no contraction in this file).
+                const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
+                const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
+                const double dd = sqrt(wx * wx + wy * wy + wz * wz);
+                const double kt64 = (dd / P.c0d - P.t0d) / P.dtd;
+                kf = (float)floor(kt64);
+            }
+            const float inv = ri / P.sigma;   // 1 / (kt + tau)
+            const float clo = fmaf(kf + 1.f + P.tau, inv, -1.5f);
+            const float chi = fmaf(-(kf + P.tau), inv, 1.5f);
+            int li = (int)kf - sklo[j];
+            li = min(max(li, 0), win - 2);
+            const float *pr = sp + j * win + li;
+            acc = fmaf(d.fbp_w, fmaf(clo, pr[0], chi * pr[1]), acc);
+        }
     }
-    store_val(img, ((size_t)iz * P.ny + iy) * P.nx + ix, img_dt, P.fbp_scale * acc);
+    if (in) {
+        const size_t n = ((size_t)iz * P.ny + iy) * P.nx + ix;
+        const float v = P.fbp_scale * acc;
+        if (IMG_DT == 0)
+            ((float *)img)[n] = v;
+        else
+            ((unsigned short *)img)[n] = to_bf16(v);
+    }
 }
 
 hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo, void *out,
@@ -198,8 +239,22 @@ hipError_t launch_sum_parts(const Problem &P, const float *img_part, int nparts,
 hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img, int img_dtype,
                       hipStream_t s)
 {
-    dim3 grid((P.nx + 15) / 16, (P.ny + 15) / 16, P.nz);
-    hipLaunchKernelGGL(fbp_kernel, grid, dim3(256), 0, s, P, p, p_dtype, img, img_dtype);
+    // Samples a tile can touch per transducer: its diagonal in shells plus margins.
+    const float diag = sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1)));
+    int win = (int)ceilf(diag * P.sigma) + 6;
+    int chunk = FBP_LDS / win;
+    if (chunk > FBP_LDS / 8) chunk = FBP_LDS / 8;
+    if (chunk < 1) return hipErrorInvalidValue;
+    dim3 grid((P.nx + FBP_TX - 1) / FBP_TX, (P.ny + FBP_TY - 1) / FBP_TY, P.nz);
+    dim3 block(FBP_TX * FBP_TY);
+    if (p_dtype == 0 && img_dtype == 0)
+        hipLaunchKernelGGL((fbp_kernel<0, 0>), grid, block, 0, s, P, p, img, win, chunk);
+    else if (p_dtype == 0)
+        hipLaunchKernelGGL((fbp_kernel<0, 1>), grid, block, 0, s, P, p, img, win, chunk);
+    else if (img_dtype == 0)
+        hipLaunchKernelGGL((fbp_kernel<1, 0>), grid, block, 0, s, P, p, img, win, chunk);
+    else
+        hipLaunchKernelGGL((fbp_kernel<1, 1>), grid, block, 0, s, P, p, img, win, chunk);
     return hipGetLastError();
 }
 

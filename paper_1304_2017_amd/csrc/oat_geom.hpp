@@ -58,6 +58,34 @@ OAT_HD float acos_approx(float x)
     return x >= 0.0f ? r : kPi - r;
 }
 
+// atan2 with absolute error below 2e-5 rad (odd minimax polynomial for
+// atan on [-1, 1] plus octant reduction); conservative-range use only.
+OAT_HD float atan2_approx(float y, float x)
+{
+    float ax = fabsf(x), ay = fabsf(y);
+    float mx = fmaxf_(ax, ay), mn = fminf_(ax, ay);
+    float a = mx > 0.0f ? mn * rcp_approx(mx) : 0.0f;
+    float s = a * a;
+    float r = ((((-0.0117212f * s + 0.05265332f) * s - 0.11643287f) * s + 0.19354346f) * s
+               - 0.33262347f) * s * a + 0.99997726f * a;
+    if (ay > ax) r = 1.57079632679f - r;
+    if (x < 0.0f) r = kPi - r;
+    return y < 0.0f ? -r : r;
+}
+
+// cos/sin to about 1e-6 (hardware on the GPU, libm on the host); used only
+// where the arc margins absorb the error.
+OAT_HD void sincos_approx(float a, float &c, float &s)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    c = __cosf(a);
+    s = __sinf(a);
+#else
+    c = cosf(a);
+    s = sinf(a);
+#endif
+}
+
 // Per (brick, transducer) constants for the ring/box arc test.  All in grid
 // units.  The box is the set of points whose cell floor(u) lies in
 // [lo, hi) per axis, widened by a small margin.
@@ -94,13 +122,14 @@ OAT_HD void arc_unit_setup(ArcUnit &U, const int lo[3], const int hi[3], const d
     U.V3 = (float)(V[0] * e3[0] + V[1] * e3[1] + V[2] * e3[2]);
     U.rhov2 = V1 * V1 + V2 * V2;
     U.rhov = sqrtf(U.rhov2);
-    U.phic = atan2f(V2, V1);
-    float c = cosf(U.phic), s = sinf(U.phic);
+    U.phic = atan2_approx(V2, V1);
+    float c, s;
+    sincos_approx(U.phic, c, s);
     for (int a = 0; a < 3; ++a) {
         float E1 = c * e1[a] + s * e2[a];
         float E2 = -s * e1[a] + c * e2[a];
         U.nrm[a] = sqrtf(E1 * E1 + E2 * E2);
-        U.gam[a] = atan2f(E2, E1);
+        U.gam[a] = atan2_approx(E2, E1);
     }
 }
 
@@ -112,71 +141,71 @@ OAT_HD void arc_unit_setup(ArcUnit &U, const int lo[3], const int hi[3], const d
 OAT_HD void ring_arc(const ArcUnit &U, const float C[3], float r, float rc, int nj,
                      int &jlo, int &cnt)
 {
-    jlo = 0;
-    cnt = 0;
     // Window of the ring inside the ball around the box: |p - cb|^2 =
-    // rhov^2 + v3^2 + r^2 - 2 r rhov cos(psi), psi = phi - phic.
-    float v3 = U.V3 - rc;
-    float num = U.rhov2 + v3 * v3 + r * r - U.h2;
-    float den = 2.0f * r * U.rhov;
-    float psiw;
-    if (den <= 1e-6f) {
-        if (num > 0.0f) return;       // every ring point is farther than h
-        cnt = nj;                     // ring inside the ball: take it whole
-        return;
-    }
-    float kappa = num * rcp_approx(den);
-    if (kappa >= 1.0f) return;
-    if (kappa <= 0.0f) { cnt = nj; return; }   // wide window: whole ring
-    psiw = acos_approx(kappa) + 2e-4f;
+    // rhov^2 + v3^2 + r^2 - 2 r rhov cos(psi), psi = phi - phic.  Written
+    // without data-dependent branches (all lanes of a wave take one path).
+    const float v3 = U.V3 - rc;
+    const float num = U.rhov2 + v3 * v3 + r * r - U.h2;
+    const float den = 2.0f * r * U.rhov;
+    const bool tiny = den <= 1e-6f;
+    const float kappa = tiny ? (num > 0.0f ? 2.0f : -2.0f) : num * rcp_approx(den);
+    bool empty = kappa >= 1.0f;
+    bool full = kappa <= 0.0f;
+    const float psiw = acos_approx(kappa) + 2e-4f;
     float plo = -psiw, phi = psiw;
-    const float Ca[3] = {C[0], C[1], C[2]};
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float m = r * U.nrm[a];
-        if (m < 1e-4f) {
-            if (Ca[a] + m < U.lo[a] || Ca[a] - m > U.hi[a]) return;
-            continue;
-        }
-        float inv = rcp_approx(m);
-        float x1 = (U.lo[a] - Ca[a]) * inv;
-        float x2 = (U.hi[a] - Ca[a]) * inv;
-        if (x1 > 1.0f || x2 < -1.0f) return;
-        if (x1 <= -1.0f && x2 >= 1.0f) continue;
-        float A1 = acos_approx(x2);   // smaller angle
-        float A2 = acos_approx(x1);   // larger angle
-        float g = U.gam[a];
+        const float m = r * U.nrm[a];
+        const bool degen = m < 1e-4f;
+        const float inv = rcp_approx(fmaxf_(m, 1e-4f));
+        const float x1 = (U.lo[a] - C[a]) * inv;
+        const float x2 = (U.hi[a] - C[a]) * inv;
+        const bool out = degen ? (C[a] + m < U.lo[a] || C[a] - m > U.hi[a])
+                               : (x1 > 1.0f || x2 < -1.0f);
+        const bool nocon = degen || (x1 <= -1.0f && x2 >= 1.0f);
+        const float A1 = acos_approx(x2);   // smaller angle
+        const float A2 = acos_approx(x1);   // larger angle
+        const float g = U.gam[a];
         float lo_a = 1e30f, hi_a = -1e30f;
         // allowed psi - g in [A1, A2] U [-A2, -A1] (mod 2 pi), clipped to the window
+#pragma unroll
         for (int sh = -1; sh <= 1; ++sh) {
-            float off = g + (float)sh * kTwoPi;
-            float a0 = fmaxf_(off + A1 - 2e-4f, plo), b0 = fminf_(off + A2 + 2e-4f, phi);
-            if (a0 <= b0) { lo_a = fminf_(lo_a, a0); hi_a = fmaxf_(hi_a, b0); }
-            float a1 = fmaxf_(off - A2 - 2e-4f, plo), b1 = fminf_(off - A1 + 2e-4f, phi);
-            if (a1 <= b1) { lo_a = fminf_(lo_a, a1); hi_a = fmaxf_(hi_a, b1); }
+            const float off = g + (float)sh * kTwoPi;
+            const float a0 = fmaxf_(off + A1 - 2e-4f, plo), b0 = fminf_(off + A2 + 2e-4f, phi);
+            const bool k0 = a0 <= b0;
+            lo_a = k0 ? fminf_(lo_a, a0) : lo_a;
+            hi_a = k0 ? fmaxf_(hi_a, b0) : hi_a;
+            const float a1 = fmaxf_(off - A2 - 2e-4f, plo), b1 = fminf_(off - A1 + 2e-4f, phi);
+            const bool k1 = a1 <= b1;
+            lo_a = k1 ? fminf_(lo_a, a1) : lo_a;
+            hi_a = k1 ? fmaxf_(hi_a, b1) : hi_a;
         }
-        if (lo_a > hi_a) return;
-        plo = fmaxf_(plo, lo_a);
-        phi = fminf_(phi, hi_a);
-        if (plo > phi) return;
+        empty = empty || out || (!nocon && lo_a > hi_a);
+        plo = nocon ? plo : fmaxf_(plo, lo_a);
+        phi = nocon ? phi : fminf_(phi, hi_a);
     }
-    float f = (float)nj * kInvTwoPi;
-    int j0 = (int)floorf((U.phic + plo) * f) - 1;
-    int j1 = (int)ceilf((U.phic + phi) * f) + 1;
-    int c = j1 - j0 + 1;
-    if (c >= nj) { cnt = nj; return; }
+    empty = empty || (!full && plo > phi);
+    const float f = (float)nj * kInvTwoPi;
+    const int j0 = (int)floorf((U.phic + plo) * f) - 1;
+    const int j1 = (int)ceilf((U.phic + phi) * f) + 1;
+    const int c = j1 - j0 + 1;
     int m = j0 % nj;
-    if (m < 0) m += nj;
-    jlo = m;
-    cnt = c;
+    m = m < 0 ? m + nj : m;
+    const bool whole = full || c >= nj;
+    jlo = (empty || whole) ? 0 : m;
+    cnt = empty ? 0 : (whole ? nj : c);
 }
 
 // Points of a ring are split into fixed segments of L consecutive indices;
 // every point is evaluated relative to its segment's reference index, so a
 // point's position is a function of (transducer, shell, ring, j) only.
-OAT_HD int seg_len(int nj)
+OAT_HD int seg_shift(int nj)
 {
-    int L = nj >> 3;
-    return L < 1 ? 1 : (L > 32 ? 32 : L);
+    // L = 2^shift is the largest power of two <= nj/8 (at least 1, at most 32),
+    // so a segment spans at most pi/8 of the ring about its reference.
+    int e = nj >> 3, sh = 0;
+    while (sh < 5 && (2 << sh) <= e) ++sh;
+    return sh;
 }
 
 // cos and sin of 2 pi x for x in [0, 1), about 1 ulp: quarter-turn reduction

@@ -49,7 +49,7 @@ struct alignas(16) RingRec {
     float w;           // band area / nj  (mm^2)
     float delta;       // 2 pi / nj
     float inv_nj;      // 1 / nj
-    float pad;
+    int32_t lshift;    // ring segments hold 2^lshift consecutive points
 };
 
 // Everything a kernel needs about the problem (passed by value).

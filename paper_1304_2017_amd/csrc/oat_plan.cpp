@@ -11,6 +11,7 @@
 
 #include "oat.h"
 #include "oat_internal.hpp"
+#include "oat_geom.hpp"
 
 using namespace oat;
 
@@ -192,11 +193,11 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
             rr.w = (float)(area / (double)nj);
             rr.delta = (float)(2.0 * M_PI / (double)nj);
             rr.inv_nj = (float)(1.0 / (double)nj);
-            rr.pad = 0.f;
+            rr.lshift = seg_shift((int)nj);
             ring.push_back(rr);
         }
     }
-    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f, 1.f, 0.f});
+    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f, 1.f, 0});
 
     oat_plan *plan = new (std::nothrow) oat_plan();
     if (!plan) return fail(OAT_ERR_NOMEM, "host allocation failed");

@@ -234,7 +234,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
             int rb = bperm_i(s1, rbase);
             // Ring (kr, ir): centre in FP64, arc of indices inside the box.
             float C0 = 0.f, C1 = 0.f, C2 = 0.f, r = 0.f, w = 0.f, dlt = 0.f, invn = 0.f;
-            int nj = 1, jlo = 0, jcnt = 0, L = 1, n1 = 0, items_all = 0;
+            int nj = 1, jlo = 0, jcnt = 0, ls = 0, n1 = 0, items_all = 0;
             if (v1) {
                 const RingRec rr = P.ring[rb + ir];
                 C0 = (float)fma(rr.rc, e3[0], uq[0]);
@@ -247,15 +247,15 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 invn = rr.inv_nj;
                 const float C[3] = {C0, C1, C2};
                 ring_arc(U, C, r, (float)rr.rc, nj, jlo, jcnt);
+                ls = rr.lshift;
                 if (jcnt > 0) {
-                    L = seg_len(nj);
                     int jend = jlo + jcnt;
                     if (jend <= nj) {
-                        n1 = (jend - 1) / L - jlo / L + 1;
+                        n1 = ((jend - 1) >> ls) - (jlo >> ls) + 1;
                         items_all = n1;
                     } else {
-                        n1 = (nj - 1) / L - jlo / L + 1;
-                        items_all = n1 + (jend - nj - 1) / L + 1;
+                        n1 = ((nj - 1) >> ls) - (jlo >> ls) + 1;
+                        items_all = n1 + ((jend - nj - 1) >> ls) + 1;
                     }
                 }
             }
@@ -271,19 +271,13 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 const float rr2 = bperm_f(s2, r), w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
                 const float in2 = bperm_f(s2, invn);
                 const int nj2 = bperm_i(s2, nj), jlo2 = bperm_i(s2, jlo), jc2 = bperm_i(s2, jcnt);
-                const int L2s = bperm_i(s2, L), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
+                const int ls2 = bperm_i(s2, ls), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
                 // Segment of this item and its index range.
-                int s, jb, je;
-                if (m < n12) {
-                    s = jlo2 / L2s + m;
-                    jb = max(s * L2s, jlo2);
-                    je = min(min((s + 1) * L2s, nj2), jlo2 + jc2);
-                } else {
-                    s = m - n12;
-                    jb = s * L2s;
-                    je = min(min((s + 1) * L2s, nj2), jlo2 + jc2 - nj2);
-                }
-                const int sb = s * L2s, se = min(sb + L2s, nj2);
+                const bool wrap = m >= n12;
+                const int s = wrap ? m - n12 : (jlo2 >> ls2) + m;
+                const int sb = s << ls2, se = min(sb + (1 << ls2), nj2);
+                const int jb = wrap ? sb : max(sb, jlo2);
+                const int je = min(se, wrap ? jlo2 + jc2 - nj2 : jlo2 + jc2);
                 const int jref = sb + ((se - sb - 1) >> 1);
                 float cr, sr;
                 sincos_turns((float)jref * in2, cr, sr);
