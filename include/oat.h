@@ -104,6 +104,32 @@ typedef struct oat_plan oat_plan;
  * On success *out owns device memory until oat_plan_destroy. */
 int oat_plan_create(const oat_geometry *geom, int device, oat_plan **out);
 
+/* Plan options for oat_plan_create_ex.
+ *
+ * arc_table_bytes: device memory the plan may spend on its arc table.  The
+ * table lists, for every (image brick, transducer) pair, the quadrature rings
+ * that hold points of the brick and the exact index range of those points on
+ * each ring; with it oat_project and oat_backproject skip their per-ring
+ * bound computations and evaluate no points outside the brick.  It is built
+ * on the device at plan creation (two passes as costly as one oat_project)
+ * and takes about 4 bytes per (brick, transducer, ring) triple: 15 GB for a
+ * 256^3 image at 2048 transducers and 1024 samples.  Results are identical
+ * with or without it up to FP32 summation order.
+ *   -1  automatic: build it if it fits in 40% of the device memory free at
+ *       plan creation (the default of oat_plan_create);
+ *    0  never build it;
+ *  > 0  build it if it fits in this many bytes.
+ * Without a table, or when the geometry has rings of more than 65535 points
+ * or shells of more than 65535 rings, the kernels bound the arcs themselves. */
+typedef struct {
+    int64_t arc_table_bytes;
+} oat_plan_options;
+
+/* oat_plan_create with options (NULL = defaults).  OAT_ERR_ARG when
+ * arc_table_bytes < -1. */
+int oat_plan_create_ex(const oat_geometry *geom, int device, const oat_plan_options *opt,
+                       oat_plan **out);
+
 /* Frees the plan's tables and workspace.  NULL is accepted.  The caller
  * must make sure no call on the plan is still running. */
 void oat_plan_destroy(oat_plan *plan);
@@ -139,8 +165,10 @@ const char *oat_last_error(void);
  * stats[0] = number of quadrature rings in the tables,
  * stats[1] = number of image bricks, stats[2] = brick edge (cells),
  * stats[3] = shell window per (brick, transducer),
- * stats[4] = bytes of device workspace, stats[5] = bytes of device tables.
- * n = capacity of stats; returns OAT_OK. */
+ * stats[4] = bytes of device workspace, stats[5] = bytes of device tables,
+ * stats[6] = bytes of the arc table (0: none), stats[7] = its ring entries,
+ * stats[8] = its build time in microseconds.
+ * n = capacity of stats (at most 9 are written); returns OAT_OK. */
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n);
 
 #ifdef __cplusplus

@@ -1,6 +1,7 @@
 // Data-side kernels on gfx950: the reduction of G's brick partials fused
-// with D (Eq. (dis_g2p)), its transpose D^T (Sec. II.C), the sum of partial
-// images, and the voxel-driven filtered backprojection of Eq. (disfbp).
+// with D (Eq. (dis_g2p)), its transpose D^T (Sec. II.C), the gather of G^T's
+// brick boxes into the image, and the voxel-driven filtered backprojection
+// of Eq. (disfbp).
 #include "oat_internal.hpp"
 
 #pragma clang fp contract(off)
@@ -109,15 +110,40 @@ __global__ void diff_adj_kernel(Problem P, const void *__restrict__ y, int y_dt,
     }
 }
 
-__global__ void sum_parts_kernel(size_t n, const float *__restrict__ part, int nparts,
-                                 void *__restrict__ img, int img_dt)
+// G^T output.  A brick's box holds the nodes of its cells, one node below
+// its first owned node through its last owned node, so node c (per axis)
+// receives the box of its owner brick c / BRICK and, when c is the last node
+// of that brick, the box of the next brick, where c is box node 0.  The at
+// most 8 contributions are added in a fixed order: the result is
+// deterministic.
+template <int IMG_DT>
+__global__ void __launch_bounds__(256)
+adj_gather_kernel(Problem P, const float *__restrict__ bbuf, void *__restrict__ img)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        float s = part[i];
-        for (int p = 1; p < nparts; ++p) s += part[(size_t)p * n + i];
-        store_val(img, i, img_dt, s);
+    const int x = blockIdx.x * 64 + threadIdx.x % 64;
+    const int y = blockIdx.y * 4 + threadIdx.x / 64;
+    const int z = blockIdx.z;
+    if (x >= P.nx || y >= P.ny) return;
+    const int c[3] = {x, y, z};
+    const int nb[3] = {P.nbx, P.nby, P.nbz};
+    int bi[3][2], off[3][2], cnt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int b0 = c[a] / BRICK, r = c[a] - b0 * BRICK;
+        bi[a][0] = b0;
+        off[a][0] = r + 1;
+        bi[a][1] = b0 + 1;
+        off[a][1] = 0;
+        cnt[a] = (r == BRICK - 1 && b0 + 1 < nb[a]) ? 2 : 1;
     }
+    double acc = 0.0;
+    for (int iz = 0; iz < cnt[2]; ++iz)
+        for (int iy = 0; iy < cnt[1]; ++iy)
+            for (int ix = 0; ix < cnt[0]; ++ix) {
+                const size_t b = ((size_t)bi[2][iz] * P.nby + bi[1][iy]) * P.nbx + bi[0][ix];
+                acc += (double)bbuf[b * BOX3 + (off[2][iz] * BOX + off[1][iy]) * BOX + off[0][ix]];
+            }
+    store_val(img, ((size_t)z * P.ny + y) * P.nx + x, IMG_DT, (float)acc);
 }
 
 // FBP, Eq. (disfbp): one thread per voxel of a 16 x 16 x 1 tile, loop over
@@ -225,14 +251,14 @@ hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *
     return hipGetLastError();
 }
 
-hipError_t launch_sum_parts(const Problem &P, const float *img_part, int nparts, void *img,
-                            int img_dtype, hipStream_t s)
+hipError_t launch_adj_gather(const Problem &P, const float *bbuf, void *img, int img_dtype,
+                             hipStream_t s)
 {
-    size_t n = (size_t)P.nx * P.ny * P.nz;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(blocks), dim3(256), 0, s, n, img_part, nparts, img,
-                       img_dtype);
+    dim3 grid((P.nx + 63) / 64, (P.ny + 3) / 4, P.nz), block(256);
+    if (img_dtype == 0)
+        hipLaunchKernelGGL(adj_gather_kernel<0>, grid, block, 0, s, P, bbuf, img);
+    else
+        hipLaunchKernelGGL(adj_gather_kernel<1>, grid, block, 0, s, P, bbuf, img);
     return hipGetLastError();
 }
 

@@ -233,6 +233,43 @@ OAT_HD void sincos_turns(float x, float &c, float &s)
     s = ss;
 }
 
+// FP64 cos and sin of 2 pi x for x in [0, 1), to a few units in the last
+// place: exact quarter-turn reduction, then Taylor series on [-pi/4, pi/4]
+// through z^15 (sin) and z^16 (cos); the first omitted terms are below 5e-17.
+OAT_HD void sincos_turns_d(double x, double &c, double &s)
+{
+    double t = x * 4.0;
+    double qf = rint(t);
+    double y = t - qf;
+    int q = ((int)qf) & 3;
+    double z = y * 1.5707963267948966;
+    double z2 = z * z;
+    double sp = fma(z2, -7.6471637318198165e-13, 1.6059043836821613e-10);
+    sp = fma(z2, sp, -2.5052108385441720e-08);
+    sp = fma(z2, sp, 2.7557319223985891e-06);
+    sp = fma(z2, sp, -1.9841269841269841e-04);
+    sp = fma(z2, sp, 8.3333333333333333e-03);
+    sp = fma(z2, sp, -1.6666666666666667e-01);
+    sp = fma(z2 * z, sp, z);
+    double cp = fma(z2, 4.7794773323873853e-14, -1.1470745597729725e-11);
+    cp = fma(z2, cp, 2.0876756987868099e-09);
+    cp = fma(z2, cp, -2.7557319223985891e-07);
+    cp = fma(z2, cp, 2.4801587301587302e-05);
+    cp = fma(z2, cp, -1.3888888888888889e-03);
+    cp = fma(z2, cp, 4.1666666666666667e-02);
+    cp = fma(z2, cp, -0.5);
+    cp = fma(z2, cp, 1.0);
+    double cc, ss;
+    switch (q) {
+        case 0: cc = cp; ss = sp; break;
+        case 1: cc = -sp; ss = cp; break;
+        case 2: cc = -cp; ss = -sp; break;
+        default: cc = sp; ss = -cp; break;
+    }
+    c = cc;
+    s = ss;
+}
+
 // Taylor parts of a small rotation d (|d| <= pi/8): cm1 = cos d - 1, sn = sin d.
 OAT_HD void small_rot(float d, float &cm1, float &sn)
 {

@@ -15,6 +15,7 @@ constexpr int BOX_SY = BOX + 2;               // LDS row pitch (dwords)
 constexpr int BOX_SZ = BOX_SY * BOX + 38;     // LDS slice pitch (dwords); pitches chosen
                                               // to spread arcs of any direction over banks
 constexpr int BOX_WORDS = BOX_SZ * BOX;
+constexpr int BOX3 = BOX * BOX * BOX;          // dense box in HBM (G^T brick output)
 constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
 constexpr int WAVE = 64;
 constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
@@ -23,8 +24,10 @@ constexpr int WMAX = 256;                    // largest shell window per (brick,
 struct alignas(16) DetRec {
     double uq[3];      // transducer position
     double e3[3];      // unit vector to the origin (z of the local frame)
-    float e1[3];       // x of the local frame
-    float e2[3];       // y of the local frame
+    double e1d[3];     // x of the local frame
+    double e2d[3];     // y of the local frame
+    float e1[3];       // e1d rounded to FP32 (arc bounds)
+    float e2[3];       // e2d rounded to FP32 (arc bounds)
     float dist;        // |r_q| / dx
     float fbp_w;       // a_q / |r_q|  (mm)
     float uqf[3];      // transducer position rounded to FP32
@@ -44,12 +47,14 @@ struct alignas(16) ShellRec {
 // Per-ring record (shell k, band i).
 struct alignas(16) RingRec {
     double rc;         // rho cos(theta_i) / dx
-    float rs;          // rho sin(theta_i) / dx
+    double rs;         // rho sin(theta_i) / dx
+    double inv_nj;     // 1 / nj
+    float rsf;         // rs rounded to FP32 (arc bounds)
     int32_t nj;        // points on the ring
     float w;           // band area / nj  (mm^2)
     float delta;       // 2 pi / nj
-    float inv_nj;      // 1 / nj
     int32_t lshift;    // ring segments hold 2^lshift consecutive points
+    int32_t pad;
 };
 
 // Everything a kernel needs about the problem (passed by value).
@@ -70,19 +75,32 @@ struct Problem {
     const DetRec *det;
     const ShellRec *shell;
     const RingRec *ring;
+    // Arc table (null when the plan has none).  Unit u = brick * nq + q:
+    // tab_run[u * window + s] = i0 | n << 16, the rings i0 .. i0+n-1 of shell
+    // klo(u) + s that may hold points owned by the brick; their entries
+    // tab_arc[tab_off[u] + (entries of the unit's earlier shells) + i - i0]
+    // = jlo | jcnt << 16, the tight arc of the ring's owned points (jcnt = 0:
+    // none).  tab_cnt[u] = entries of unit u (written by the count pass).
+    const long long *tab_off;
+    unsigned *tab_run;
+    unsigned *tab_arc;
+    int *tab_cnt;
 };
 
 // Launchers (defined in the .hip files); dtype: 0 = f32, 1 = bf16.
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part,
-                          int *klo, int qsplit, hipStream_t s);
+                          int *klo, hipStream_t s);
+// Arc-table passes: fill = 0 writes tab_run and tab_cnt (tab_run zeroed
+// beforehand), fill = 1 writes tab_arc (tab_off set).
+hipError_t launch_arc_build(const Problem &P, int fill, hipStream_t s);
 hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo,
                              void *out, int out_dtype, int apply_d, hipStream_t s);
 hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp,
                            int apply_dt, hipStream_t s);
-hipError_t launch_srt_adj(const Problem &P, const float *gp, float *img_part,
-                          void *img, int img_dtype, int qsplit, hipStream_t s);
-hipError_t launch_sum_parts(const Problem &P, const float *img_part, int nparts,
-                            void *img, int img_dtype, hipStream_t s);
+hipError_t launch_srt_adj(const Problem &P, const float *gp, float *bbuf, void *img,
+                          int img_dtype, hipStream_t s);
+hipError_t launch_adj_gather(const Problem &P, const float *bbuf, void *img, int img_dtype,
+                             hipStream_t s);
 hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img,
                       int img_dtype, hipStream_t s);
 

@@ -2,6 +2,7 @@
 // workspace and the C-ABI entry points declared in include/oat.h.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -63,11 +64,109 @@ struct oat_plan {
     float *d_part = nullptr;     // G windows [bricks][Q][window]
     int *d_klo = nullptr;        // [bricks][Q]
     float *d_gp = nullptr;       // D^T y  [Q][K]
-    float *d_img_part = nullptr; // G^T partial images [adj_split][N]
-    int adj_split = 1;
+    float *d_bbuf = nullptr;     // G^T brick boxes [bricks][BOX^3]
+    long long *d_tab_off = nullptr;   // arc table (see Problem)
+    unsigned *d_tab_run = nullptr;
+    unsigned *d_tab_arc = nullptr;
+    int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0;
+    int max_nj = 0, max_rings = 0;
     int64_t n_rings = 0;
     int64_t ws_bytes = 0, table_bytes = 0;
 };
+
+namespace {
+
+// Arc table of a plan (see Problem): the count pass, an exclusive prefix sum
+// of the per-unit counts on the host, the fill pass.  budget < 0: up to 40%
+// of the device memory free now.  A table that does not fit, or a geometry
+// whose ring indices exceed 16 bits, leaves the plan without one (kernels
+// then bound the arcs themselves); a failing launch fails the plan.
+int build_arc_table(oat_plan *plan, int64_t budget)
+{
+    Problem &P = plan->P;
+    if (plan->max_nj > 65535 || plan->max_rings > 65535) return OAT_OK;
+    if (budget < 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return OAT_OK;
+        budget = (int64_t)(0.4 * (double)fr);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t units = (int64_t)P.nbx * P.nby * P.nbz * P.nq;
+    const size_t run_b = sizeof(unsigned) * (size_t)units * P.window;
+    const size_t off_b = sizeof(long long) * (size_t)units;
+    const size_t cnt_b = sizeof(int) * (size_t)units;
+    if ((int64_t)(run_b + off_b + cnt_b) > budget) return OAT_OK;
+    unsigned *run = nullptr;
+    long long *off = nullptr;
+    int *cnt = nullptr;
+    unsigned *arc = nullptr;
+    auto release = [&]() {
+        if (run) (void)hipFree(run);
+        if (off) (void)hipFree(off);
+        if (cnt) (void)hipFree(cnt);
+        if (arc) (void)hipFree(arc);
+        run = nullptr;
+        off = nullptr;
+        cnt = nullptr;
+        arc = nullptr;
+    };
+    if (hipMalloc((void **)&run, run_b) != hipSuccess || hipMalloc((void **)&off, off_b) != hipSuccess ||
+        hipMalloc((void **)&cnt, cnt_b) != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return OAT_OK;
+    }
+    hipError_t e = hipMemset(run, 0, run_b);
+    Problem Pc = P;
+    Pc.tab_run = run;
+    Pc.tab_cnt = cnt;
+    if (e == hipSuccess) e = launch_arc_build(Pc, 0, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    std::vector<int> hcnt(units);
+    if (e == hipSuccess) e = hipMemcpy(hcnt.data(), cnt, cnt_b, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        release();
+        return fail_hip(e, "oat_plan_create: arc table count pass");
+    }
+    std::vector<long long> hoff(units);
+    long long total = 0;
+    for (int64_t u = 0; u < units; ++u) {
+        hoff[u] = total;
+        total += hcnt[u];
+    }
+    const size_t arc_b = sizeof(unsigned) * (size_t)(total > 0 ? total : 1);
+    if ((int64_t)(run_b + off_b + arc_b) > budget || hipMalloc((void **)&arc, arc_b) != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return OAT_OK;
+    }
+    (void)hipFree(cnt);
+    cnt = nullptr;
+    e = hipMemcpy(off, hoff.data(), off_b, hipMemcpyHostToDevice);
+    Pc.tab_cnt = nullptr;
+    Pc.tab_off = off;
+    Pc.tab_arc = arc;
+    if (e == hipSuccess) e = launch_arc_build(Pc, 1, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release();
+        return fail_hip(e, "oat_plan_create: arc table fill pass");
+    }
+    plan->d_tab_run = run;
+    plan->d_tab_off = off;
+    plan->d_tab_arc = arc;
+    P.tab_run = run;
+    P.tab_off = off;
+    P.tab_arc = arc;
+    P.tab_cnt = nullptr;
+    plan->tab_bytes = (int64_t)(run_b + off_b + arc_b);
+    plan->tab_entries = total;
+    plan->tab_build_us = (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(
+                             std::chrono::steady_clock::now() - t0).count();
+    return OAT_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -80,7 +179,8 @@ void oat_plan_destroy(oat_plan *plan)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(plan->device);
     void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
-                    plan->d_klo, plan->d_gp, plan->d_img_part};
+                    plan->d_klo, plan->d_gp, plan->d_bbuf, plan->d_tab_off,
+                    plan->d_tab_run, plan->d_tab_arc};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -89,8 +189,16 @@ void oat_plan_destroy(oat_plan *plan)
 
 int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
 {
+    return oat_plan_create_ex(g, device, nullptr, out);
+}
+
+int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options *opt,
+                       oat_plan **out)
+{
     g_last_error.clear();
     if (!g || !out) return fail(OAT_ERR_ARG, "oat_plan_create: null argument");
+    const int64_t table_budget = opt ? opt->arc_table_bytes : -1;
+    if (table_budget < -1) return fail(OAT_ERR_ARG, "arc_table_bytes must be >= -1");
     *out = nullptr;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1)
         return fail(OAT_ERR_GEOMETRY, "grid sizes must be >= 1");
@@ -148,6 +256,8 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
         D.uq[2] = (r[2] - g->z0) / dx;
         for (int a = 0; a < 3; ++a) {
             D.e3[a] = e3[a];
+            D.e1d[a] = e1[a];
+            D.e2d[a] = e2[a];
             D.e1[a] = (float)e1[a];
             D.e2[a] = (float)e2[a];
             D.uqf[a] = (float)D.uq[a];
@@ -165,6 +275,7 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
     // Quadrature tables in FP64 (Appendix; bands of arc length dx from the pole).
     std::vector<ShellRec> shell(K);
     std::vector<RingRec> ring;
+    int max_nj = 0, max_rings = 0;
     for (int k = 0; k < K; ++k) {
         double rho = g->c0 * (g->t0 + k * g->dt);
         ShellRec &S = shell[k];
@@ -178,6 +289,7 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
         if ((int64_t)ring.size() + nring >= (1ll << 31))
             return fail(OAT_ERR_GEOMETRY, "quadrature tables exceed 2^31 rings");
         S.n_rings = (int32_t)nring;
+        if (nring > max_rings) max_rings = (int)nring;
         for (long i = 0; i < nring; ++i) {
             double tlo = i * dth;
             double thi = (i + 1) * dth;
@@ -188,16 +300,19 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
             if (nj < 1) nj = 1;
             RingRec rr;
             rr.rc = rho * std::cos(th) / dx;
-            rr.rs = (float)(rho * std::sin(th) / dx);
+            rr.rs = rho * std::sin(th) / dx;
+            rr.inv_nj = 1.0 / (double)nj;
+            rr.rsf = (float)rr.rs;
             rr.nj = (int32_t)nj;
             rr.w = (float)(area / (double)nj);
             rr.delta = (float)(2.0 * M_PI / (double)nj);
-            rr.inv_nj = (float)(1.0 / (double)nj);
             rr.lshift = seg_shift((int)nj);
+            rr.pad = 0;
+            if (nj > max_nj) max_nj = (int)nj;
             ring.push_back(rr);
         }
     }
-    if (ring.empty()) ring.push_back(RingRec{0.0, 0.f, 1, 0.f, 0.f, 1.f, 0});
+    if (ring.empty()) ring.push_back(RingRec{0.0, 0.0, 1.0, 0.f, 1, 0.f, 0.f, 0, 0});
 
     oat_plan *plan = new (std::nothrow) oat_plan();
     if (!plan) return fail(OAT_ERR_NOMEM, "host allocation failed");
@@ -208,6 +323,8 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
     plan->nq = Q;
     plan->nt = K;
     plan->n_rings = (int64_t)ring.size();
+    plan->max_nj = max_nj;
+    plan->max_rings = max_rings;
 
     Problem &P = plan->P;
     P.nx = g->nx;
@@ -246,7 +363,6 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
     P.dtd = g->dt;
 
     const int nbricks = P.nbx * P.nby * P.nbz;
-    plan->adj_split = 1;
 
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -265,14 +381,14 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
     size_t part_b = sizeof(float) * (size_t)nbricks * Q * P.window;
     size_t klo_b = sizeof(int) * (size_t)nbricks * Q;
     size_t gp_b = sizeof(float) * (size_t)Q * K;
-    size_t imgp_b = sizeof(float) * (size_t)plan->adj_split * N;   // G^T FP32 accumulator
+    size_t bbuf_b = sizeof(float) * (size_t)nbricks * BOX3;        // G^T brick boxes
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
         (e = alloc((void **)&plan->d_part, part_b, "partials")) != hipSuccess ||
         (e = alloc((void **)&plan->d_klo, klo_b, "klo")) != hipSuccess ||
         (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_img_part, imgp_b, "img_part")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_bbuf, bbuf_b, "brick boxes")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -286,12 +402,24 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
         (void)hipSetDevice(prev);
         return code;
     }
-    (void)hipSetDevice(prev);
     P.det = plan->d_det;
     P.shell = plan->d_shell;
     P.ring = plan->d_ring;
-    plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + imgp_b);
+    P.tab_off = nullptr;
+    P.tab_run = nullptr;
+    P.tab_arc = nullptr;
+    P.tab_cnt = nullptr;
+    plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + bbuf_b);
     plan->table_bytes = (int64_t)(det_b + sh_b + ring_b);
+    if (table_budget != 0) {
+        int code = build_arc_table(plan, table_budget);
+        if (code != OAT_OK) {
+            oat_plan_destroy(plan);
+            (void)hipSetDevice(prev);
+            return code;
+        }
+    }
+    (void)hipSetDevice(prev);
     *out = plan;
     return OAT_OK;
 }
@@ -299,9 +427,10 @@ int oat_plan_create(const oat_geometry *g, int device, oat_plan **out)
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n)
 {
     if (!plan || !stats || n < 0) return fail(OAT_ERR_ARG, "oat_plan_stats: null argument");
-    int64_t v[6] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
-                    plan->P.window, plan->ws_bytes, plan->table_bytes};
-    for (int i = 0; i < n && i < 6; ++i) stats[i] = v[i];
+    int64_t v[9] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
+                    plan->P.window, plan->ws_bytes, plan->table_bytes, plan->tab_bytes,
+                    plan->tab_entries, plan->tab_build_us};
+    for (int i = 0; i < n && i < 9; ++i) stats[i] = v[i];
     return OAT_OK;
 }
 
@@ -334,7 +463,7 @@ int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_srt_fwd(plan->P, img, (int)img_dtype, plan->d_part, plan->d_klo, 1, s);
+    hipError_t e = launch_srt_fwd(plan->P, img, (int)img_dtype, plan->d_part, plan->d_klo, s);
     if (e == hipSuccess)
         e = launch_srt_reduce(plan->P, plan->d_part, plan->d_klo, data, (int)data_dtype,
                               (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
@@ -355,10 +484,7 @@ int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void
     hipError_t e = launch_diff_adj(plan->P, data, (int)data_dtype, plan->d_gp,
                                    (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
     if (e == hipSuccess)
-        e = launch_srt_adj(plan->P, plan->d_gp, plan->d_img_part, img, (int)img_dtype,
-                           plan->adj_split, s);
-    if (e == hipSuccess && plan->adj_split > 1)
-        e = launch_sum_parts(plan->P, plan->d_img_part, plan->adj_split, img, (int)img_dtype, s);
+        e = launch_srt_adj(plan->P, plan->d_gp, plan->d_bbuf, img, (int)img_dtype, s);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_backproject: launch");
     return OAT_OK;

@@ -5,7 +5,7 @@
 // G^T (adjoint, Sec. II.C): alpha'_n = sum_{q,k,i,j} w_{k,i} g'[q,k] psi_n(x_{q,k,i,j})
 //
 // The image is cut into bricks of BRICK^3 cells.  A workgroup owns one brick
-// and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, an FP32
+// and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, an FP64
 // accumulator for G^T.  Each wave takes one transducer at a time and
 // enumerates exactly the quadrature points whose trilinear cell lies in the
 // brick, in three wave-wide expansions:
@@ -39,6 +39,14 @@ __device__ __forceinline__ int bperm_i(int src, int v)
 __device__ __forceinline__ float bperm_f(int src, float v)
 {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ double bperm_d(int src, double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // Exclusive prefix sum over the wave of values below 2^BITS, and the total,
@@ -138,8 +146,11 @@ struct WaveLds {
     int prod3[64];
 };
 
-// Cell box of brick b for G (owner cells) or G^T (cells touching owned nodes).
-__device__ __forceinline__ void brick_box(const Problem &P, int b, bool adj, int lo[3], int hi[3],
+// Cell box of brick b: cells lo .. hi-1 per axis.  The bricks partition the
+// cells [-1, n) that can hold a quadrature point with a nonzero trilinear
+// weight: brick i owns cells 20i-1 .. 20i+18, the last one up to n-1.  n0 ..
+// n1-1 are the nodes the brick owns.
+__device__ __forceinline__ void brick_box(const Problem &P, int b, int lo[3], int hi[3],
                                           int n0[3], int n1[3])
 {
     int bx = b % P.nbx, by = (b / P.nbx) % P.nby, bz = b / (P.nbx * P.nby);
@@ -150,28 +161,45 @@ __device__ __forceinline__ void brick_box(const Problem &P, int b, bool adj, int
         n0[a] = bi[a] * BRICK;
         n1[a] = min(n0[a] + BRICK, n[a]);
         lo[a] = n0[a] - 1;
-        if (adj)
-            hi[a] = n1[a];                                   // cells n0-1 .. n1-1
-        else
-            hi[a] = (bi[a] == nb[a] - 1) ? n[a] : n1[a] - 1; // cells partition [-1, n)
+        hi[a] = (bi[a] == nb[a] - 1) ? n[a] : n1[a] - 1;
     }
 }
 
-// Walk all points of transducer q owned by the brick.  Fn is called per
-// window of 64 points with (valid&owned, cell index relative to the box,
-// fractions, item value, shell index).
-template <bool ADJ, class Fn>
-__device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[3], const int hi[3],
-                                          WaveLds &W, const float *gp, float gscale, int &klo_out,
-                                          Fn &&fn)
+// What walk_unit does with the points it enumerates.
+enum WalkMode {
+    WALK_POINTS = 0,   // call fn on every window of points (G, G^T)
+    WALK_COUNT = 1,    // arc table, first pass: runs of rings with owned points
+    WALK_FILL = 2      // arc table, second pass: tight arc of every ring in a run
+};
+
+// Per-wave LDS of the arc-table passes: owned-index span (in arc order) per
+// ring of the current level-1 window, owned-ring span per shell of the chunk.
+struct BuildLds {
+    int rmin[64], rmax[64];
+    int smin[64], smax[64];
+};
+
+// Walk all points of transducer q owned by the brick (unit = brick * nq + q).
+// Ring arcs come from the ball/slab bounds (TAB = false) or from the plan's
+// arc table (TAB = true, tight arcs of exactly the rings that hold owned
+// points); both give the same owned points.  In WALK_POINTS mode fn is called
+// per window of 64 points with (valid&owned, cell index relative to the box,
+// fractions, item value, shell index, first shell of the unit).
+template <bool ADJ, bool TAB, int MODE, class Fn>
+__device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
+                                          const int hi[3], WaveLds &W, BuildLds *B,
+                                          const float *gp, int &klo_out, Fn &&fn)
 {
+    constexpr bool READ_RUNS = TAB || MODE == WALK_FILL;
     const DetRec &d = P.det[q];
     const double uq[3] = {d.uq[0], d.uq[1], d.uq[2]};
     const double e3[3] = {d.e3[0], d.e3[1], d.e3[2]};
+    const double e1d[3] = {d.e1d[0], d.e1d[1], d.e1d[2]};
+    const double e2d[3] = {d.e2d[0], d.e2d[1], d.e2d[2]};
     const float e1[3] = {d.e1[0], d.e1[1], d.e1[2]};
     const float e2[3] = {d.e2[0], d.e2[1], d.e2[2]};
     ArcUnit U;
-    arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
+    if (!TAB) arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
 
     // Shells that can reach the box.
     float dmin2 = 0.f, dmax2 = 0.f;
@@ -189,19 +217,41 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
     khi = min(khi, klo + P.window - 1);
     klo_out = klo;
 
-    const float D = sqrtf(U.rhov2 + U.V3 * U.V3);
-    const float thb = acos_approx(U.V3 * rcp_approx(D));
+    const float D = TAB ? 0.f : sqrtf(U.rhov2 + U.V3 * U.V3);
+    const float thb = TAB ? 0.f : acos_approx(U.V3 * rcp_approx(D));
     const float h2 = U.h2;
 
     Level L1{W.bits1, W.prod1, 0, 0};
     Level L2{W.bits2, W.prod2, 0, 0};
     Level L3{W.bits3, W.prod3, 0, 0};
 
+    const long long ebase = READ_RUNS ? P.tab_off[unit] : 0ll;
+    int run_base = 0;   // table entries of the earlier shell chunks
+    int ucount = 0;     // WALK_COUNT: table entries of the unit (per shell lane)
+    const int lane = lane_id();
+
     for (int kc = klo; kc <= khi; kc += WAVE) {
         // Level 1 producers: one shell per lane -> candidate ring range.
-        int k = kc + lane_id();
+        int k = kc + lane;
         int cnt_all = 0, ilo_all = 0, rbase = 0;
-        if (k <= khi) {
+        int r_i0 = 0, r_n = 0, r_ex = 0;   // run of table rings of this shell
+        if (READ_RUNS) {
+            if (k <= khi) {
+                const unsigned run = P.tab_run[unit * P.window + (k - klo)];
+                r_i0 = (int)(run & 0xffffu);
+                r_n = (int)(run >> 16);
+            }
+            int tot;
+            r_ex = excl_scan_ballot<16>(r_n, tot) + run_base;
+            run_base += tot;
+        }
+        if (TAB) {
+            if (r_n > 0) {
+                cnt_all = r_n;
+                ilo_all = r_i0;
+                rbase = P.shell[k].ring_base;
+            }
+        } else if (k <= khi) {
             ShellRec sh = P.shell[k];
             if (sh.n_rings > 0) {
                 float rho = sh.rho;
@@ -220,6 +270,11 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 }
             }
         }
+        if (MODE == WALK_COUNT) {
+            B->smin[lane] = 0x7fffffff;
+            B->smax[lane] = -1;
+            wave_sync();
+        }
         // Candidate rings are taken CAP1 per shell per pass so the head
         // bitmap never exceeds 64 * CAP1 bits.
         for (int pass1 = 0; __ballot(cnt_all - pass1 * CAP1 > 0) != 0ull; ++pass1) {
@@ -232,21 +287,31 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
             int kr = bperm_i(s1, k);
             int ir = bperm_i(s1, ilo) + loc1;
             int rb = bperm_i(s1, rbase);
-            // Ring (kr, ir): centre in FP64, arc of indices inside the box.
-            float C0 = 0.f, C1 = 0.f, C2 = 0.f, r = 0.f, w = 0.f, dlt = 0.f, invn = 0.f;
+            const int run_i0 = READ_RUNS ? bperm_i(s1, r_i0) : 0;
+            const int run_n = READ_RUNS ? bperm_i(s1, r_n) : 0;
+            const int run_ex = READ_RUNS ? bperm_i(s1, r_ex) : 0;
+            // Ring (kr, ir): arc of indices that holds every owned point.
+            double rcd = 0.0, rsd = 0.0, invd = 1.0;
+            float w = 0.f, dlt = 0.f;
             int nj = 1, jlo = 0, jcnt = 0, ls = 0, n1 = 0, items_all = 0;
             if (v1) {
                 const RingRec rr = P.ring[rb + ir];
-                C0 = (float)fma(rr.rc, e3[0], uq[0]);
-                C1 = (float)fma(rr.rc, e3[1], uq[1]);
-                C2 = (float)fma(rr.rc, e3[2], uq[2]);
-                r = rr.rs;
+                rcd = rr.rc;
+                rsd = rr.rs;
+                invd = rr.inv_nj;
                 nj = rr.nj;
                 w = rr.w;
                 dlt = rr.delta;
-                invn = rr.inv_nj;
-                const float C[3] = {C0, C1, C2};
-                ring_arc(U, C, r, (float)rr.rc, nj, jlo, jcnt);
+                if (TAB) {
+                    const unsigned e = P.tab_arc[ebase + run_ex + (ir - run_i0)];
+                    jlo = (int)(e & 0xffffu);
+                    jcnt = (int)(e >> 16);
+                } else {
+                    const float C[3] = {(float)fma(rr.rc, e3[0], uq[0]),
+                                        (float)fma(rr.rc, e3[1], uq[1]),
+                                        (float)fma(rr.rc, e3[2], uq[2])};
+                    ring_arc(U, C, rr.rsf, (float)rr.rc, nj, jlo, jcnt);
+                }
                 ls = rr.lshift;
                 if (jcnt > 0) {
                     int jend = jlo + jcnt;
@@ -259,7 +324,12 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                     }
                 }
             }
-            if (ADJ && v1 && items_all > 0) w = w * (gp[(size_t)q * P.nt + kr] * gscale);
+            if (ADJ && v1 && items_all > 0) w = w * gp[(size_t)q * P.nt + kr];
+            if (MODE != WALK_POINTS) {
+                B->rmin[lane] = 0x7fffffff;
+                B->rmax[lane] = -1;
+                wave_sync();
+            }
             for (int pass2 = 0; __ballot(items_all - pass2 * CAP2 > 0) != 0ull; ++pass2) {
             const int nitems = min(max(items_all - pass2 * CAP2, 0), CAP2);
             level_begin<5>(L2, nitems);
@@ -267,9 +337,8 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 int s2, m;
                 bool v2 = level_item(L2, F2, s2, m);
                 m += pass2 * CAP2;
-                const float c0 = bperm_f(s2, C0), c1 = bperm_f(s2, C1), c2 = bperm_f(s2, C2);
-                const float rr2 = bperm_f(s2, r), w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
-                const float in2 = bperm_f(s2, invn);
+                const double rc2 = bperm_d(s2, rcd), rs2 = bperm_d(s2, rsd), in2 = bperm_d(s2, invd);
+                const float w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
                 const int nj2 = bperm_i(s2, nj), jlo2 = bperm_i(s2, jlo), jc2 = bperm_i(s2, jcnt);
                 const int ls2 = bperm_i(s2, ls), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
                 // Segment of this item and its index range.
@@ -279,42 +348,99 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
                 const int jb = wrap ? sb : max(sb, jlo2);
                 const int je = min(se, wrap ? jlo2 + jc2 - nj2 : jlo2 + jc2);
                 const int jref = sb + ((se - sb - 1) >> 1);
-                float cr, sr;
-                sincos_turns((float)jref * in2, cr, sr);
-                const float a0 = rr2 * e1[0], a1 = rr2 * e1[1], a2 = rr2 * e1[2];
-                const float b0 = rr2 * e2[0], b1 = rr2 * e2[1], b2 = rr2 * e2[2];
-                const float A0 = fmaf(a0, cr, b0 * sr), A1 = fmaf(a1, cr, b1 * sr), A2 = fmaf(a2, cr, b2 * sr);
-                const float B0 = fmaf(b0, cr, -(a0 * sr)), B1 = fmaf(b1, cr, -(a1 * sr)),
-                            B2 = fmaf(b2, cr, -(a2 * sr));
-                const float P0 = c0 + A0, P1 = c1 + A1, P2 = c2 + A2;
+                const int ub = wrap ? jb + nj2 - jlo2 : jb - jlo2;   // offset of jb in the arc
+                // Reference point of the segment in FP64, split into an
+                // integer cell (relative to the box) and an FP32 fraction, and
+                // the radial (X) and tangential (Y) vectors there: point j is
+                // ref + X (cos d - 1) + Y sin d, d = (j - jref) 2 pi / nj.
+                double cr, sr;
+                sincos_turns_d((double)jref * in2, cr, sr);
+                float Pl[3], X[3], Y[3];
+                int Db[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double ra = rs2 * fma(cr, e1d[a], sr * e2d[a]);
+                    const double ta = rs2 * fma(cr, e2d[a], -(sr * e1d[a]));
+                    const double pa = fma(rc2, e3[a], uq[a]) + ra;
+                    const double ph = floor(pa);
+                    Pl[a] = (float)(pa - ph);
+                    Db[a] = (int)ph - lo[a];
+                    X[a] = (float)ra;
+                    Y[a] = (float)ta;
+                }
                 const int dj0 = jb - jref;
                 const int npts = v2 ? max(je - jb, 0) : 0;
                 level_begin<6>(L3, npts);
                 for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
                     int s3, loc3;
                     bool v3 = level_item(L3, F3, s3, loc3);
-                    const float p0 = bperm_f(s3, P0), p1 = bperm_f(s3, P1), p2 = bperm_f(s3, P2);
-                    const float x0 = bperm_f(s3, A0), x1 = bperm_f(s3, A1), x2 = bperm_f(s3, A2);
-                    const float y0 = bperm_f(s3, B0), y1 = bperm_f(s3, B1), y2 = bperm_f(s3, B2);
-                    const float dd = bperm_f(s3, dl2), wv = bperm_f(s3, w2);
+                    const float p0 = bperm_f(s3, Pl[0]), p1 = bperm_f(s3, Pl[1]), p2 = bperm_f(s3, Pl[2]);
+                    const int d0 = bperm_i(s3, Db[0]), d1 = bperm_i(s3, Db[1]), d2 = bperm_i(s3, Db[2]);
+                    const float x0 = bperm_f(s3, X[0]), x1 = bperm_f(s3, X[1]), x2 = bperm_f(s3, X[2]);
+                    const float y0 = bperm_f(s3, Y[0]), y1 = bperm_f(s3, Y[1]), y2 = bperm_f(s3, Y[2]);
+                    const float dd = bperm_f(s3, dl2);
                     const int dj = bperm_i(s3, dj0) + loc3;
-                    const int kk = bperm_i(s3, k2);
                     float cm1, sn;
                     small_rot((float)dj * dd, cm1, sn);
+                    // Fractional coordinates about the reference cell: the same
+                    // FP32 operations in every brick, so ownership is exact.
                     const float ux = fmaf(y0, sn, fmaf(x0, cm1, p0));
                     const float uy = fmaf(y1, sn, fmaf(x1, cm1, p1));
                     const float uz = fmaf(y2, sn, fmaf(x2, cm1, p2));
                     const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-                    const int cx = (int)fx0 - lo[0], cy = (int)fy0 - lo[1], cz = (int)fz0 - lo[2];
+                    const int cx = (int)fx0 + d0, cy = (int)fy0 + d1, cz = (int)fz0 + d2;
                     const bool own = v3 && (unsigned)cx < (unsigned)(hi[0] - lo[0]) &&
                                      (unsigned)cy < (unsigned)(hi[1] - lo[1]) &&
                                      (unsigned)cz < (unsigned)(hi[2] - lo[2]);
-                    fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
+                    if (MODE == WALK_POINTS) {
+                        const float wv = bperm_f(s3, w2);
+                        const int kk = bperm_i(s3, k2);
+                        fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
+                    } else {
+                        const int rl = bperm_i(s3, s2);
+                        const int uu = bperm_i(s3, ub) + loc3;
+                        if (own) {
+                            atomicMin(&B->rmin[rl], uu);
+                            atomicMax(&B->rmax[rl], uu);
+                        }
+                    }
                 }
             }
             }  // pass2
+            if (MODE != WALK_POINTS) {
+                wave_sync();
+                const int umin = B->rmin[lane], umax = B->rmax[lane];
+                const bool has = v1 && umax >= 0;
+                if (MODE == WALK_COUNT) {
+                    if (has) {
+                        atomicMin(&B->smin[s1], ir);
+                        atomicMax(&B->smax[s1], ir);
+                    }
+                } else if (v1 && ir >= run_i0 && ir < run_i0 + run_n) {
+                    int jl = jlo + umin;
+                    if (jl >= nj) jl -= nj;
+                    P.tab_arc[ebase + run_ex + (ir - run_i0)] =
+                        has ? ((unsigned)jl | ((unsigned)(umax - umin + 1) << 16)) : 0u;
+                }
+                wave_sync();
+            }
         }
         }  // pass1
+        if (MODE == WALK_COUNT) {
+            wave_sync();
+            if (k <= khi) {
+                const int imin = B->smin[lane], imax = B->smax[lane];
+                const bool any = imax >= 0;
+                P.tab_run[unit * P.window + (k - klo)] =
+                    any ? ((unsigned)imin | ((unsigned)(imax - imin + 1) << 16)) : 0u;
+                ucount += any ? imax - imin + 1 : 0;
+            }
+            wave_sync();
+        }
+    }
+    if (MODE == WALK_COUNT) {
+        const float tot = wave_sum_dpp((float)ucount);
+        if (lane == 0) P.tab_cnt[unit] = (int)tot;
     }
 }
 
@@ -323,17 +449,17 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, const int lo[
 // ---------------------------------------------------------------------------
 // G: partial sums per (brick, transducer) window.
 // ---------------------------------------------------------------------------
-template <int IMG_DT>
+template <int IMG_DT, bool TAB>
 __global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
-               int *__restrict__ klo_out, int qsplit)
+               int *__restrict__ klo_out)
 {
     __shared__ float box[BOX_WORDS];
     __shared__ WaveLds wl[WAVES];
     __shared__ double gwin[WAVES][WMAX];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
-    brick_box(P, b, false, lo, hi, n0, n1);
+    brick_box(P, b, lo, hi, n0, n1);
 
     // Stage nodes lo .. lo+BOX-1 (zero outside the grid).
     for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
@@ -355,9 +481,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     const int lane = lane_id();
     WaveLds &W = wl[wave];
     double *gw = gwin[wave];
-    const int qper = (P.nq + qsplit - 1) / qsplit;
-    const int qb = blockIdx.y * qper, qe = min(P.nq, qb + qper);
-    for (int q = qb + wave; q < qe; q += WAVES) {
+    for (int q = wave; q < P.nq; q += WAVES) {
         for (int j = lane; j < P.window; j += WAVE) gw[j] = 0.0;
         wave_sync();
         int klo = 0;
@@ -386,7 +510,8 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                 racc += val;
             }
         };
-        walk_unit<false>(P, q, lo, hi, W, nullptr, 1.f, klo, gather);
+        walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
+                                           klo, gather);
         if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
@@ -397,22 +522,25 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 }
 
 // ---------------------------------------------------------------------------
-// G^T: each brick accumulates its nodes in an FP64 LDS box with the native
-// FP64 LDS atomic add (ds_add_f64; the FP32 one is microcoded on this part
-// and ~20x slower), so no partial flushes are needed; the owned nodes are
-// rounded once to the output type at the end.  16 waves share the box.
+// G^T: each brick takes the same cells (hence the same points) as in G and
+// accumulates their trilinear weights in an FP64 LDS box with the native FP64
+// LDS atomic add (ds_add_f64; the FP32 one is microcoded on this part and
+// ~20x slower), so no partial flushes are needed.  16 waves share the box.
+// The box (its owned nodes and the one-node layer below them, which belongs
+// to the neighbouring bricks) is written to HBM in FP32 and adj_gather_kernel
+// adds the overlapping layers.
 // ---------------------------------------------------------------------------
 constexpr int ADJ_WAVES = 16;
 
-template <int OUT_DT>
+template <bool TAB>
 __global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
-srt_adj_kernel(Problem P, const float *__restrict__ gp, void *__restrict__ img)
+srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf)
 {
     __shared__ double box[BOX_WORDS];
     __shared__ WaveLds wl[ADJ_WAVES];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
-    brick_box(P, b, true, lo, hi, n0, n1);
+    brick_box(P, b, lo, hi, n0, n1);
     for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0.0;
     __syncthreads();
 
@@ -438,46 +566,80 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, void *__restrict__ img)
                 atomicAdd(pb + BOX_SZ + BOX_SY + 1, (double)(fx * w11));
             }
         };
-        walk_unit<true>(P, q, lo, hi, W, gp, 1.f, klo, scatter);
+        walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp, klo,
+                                          scatter);
     }
     __syncthreads();
-    const int ox = n1[0] - n0[0], oy = n1[1] - n0[1], oz = n1[2] - n0[2];
-    const int nown = ox * oy * oz;
-    for (int t = threadIdx.x; t < nown; t += blockDim.x) {
-        int x = t % ox, y = (t / ox) % oy, z = t / (ox * oy);
-        size_t n = ((size_t)(n0[2] + z) * P.ny + (n0[1] + y)) * P.nx + (n0[0] + x);
-        float v = (float)box[(z + 1) * BOX_SZ + (y + 1) * BOX_SY + (x + 1)];
-        if (OUT_DT == 0) {
-            ((float *)img)[n] = v;
-        } else {
-            unsigned u = __float_as_uint(v);
-            u += 0x7fffu + ((u >> 16) & 1u);
-            ((unsigned short *)img)[n] = (unsigned short)(u >> 16);
-        }
+    float *dst = bbuf + (size_t)b * BOX3;
+    for (int t = threadIdx.x; t < BOX3; t += blockDim.x) {
+        int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
+        dst[t] = (float)box[z * BOX_SZ + y * BOX_SY + x];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Arc table, built once per plan in two passes over the same enumeration as
+// G: WALK_COUNT records, per (brick, transducer, shell), the run of rings
+// that hold owned points and the unit's entry count; after the host has
+// turned the counts into offsets, WALK_FILL writes each ring's tight arc.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
+arc_build_kernel(Problem P)
+{
+    __shared__ WaveLds wl[WAVES];
+    __shared__ BuildLds bl[WAVES];
+    const int b = blockIdx.x;
+    int lo[3], hi[3], n0[3], n1[3];
+    brick_box(P, b, lo, hi, n0, n1);
+    const int wave = threadIdx.x / WAVE;
+    auto none = [](bool, int, int, int, float, float, float, float, int, int) {};
+    for (int q = wave; q < P.nq; q += WAVES) {
+        int klo = 0;
+        walk_unit<false, false, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
+                                      nullptr, klo, none);
     }
 }
 
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
-                          int qsplit, hipStream_t s)
+                          hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz, qsplit), block(WAVES * WAVE);
-    if (img_dtype == 0)
-        hipLaunchKernelGGL(srt_fwd_kernel<0>, grid, block, 0, s, P, img, part, klo, qsplit);
-    else
-        hipLaunchKernelGGL(srt_fwd_kernel<1>, grid, block, 0, s, P, img, part, klo, qsplit);
+    dim3 grid(P.nbx * P.nby * P.nbz), block(WAVES * WAVE);
+    const bool tab = P.tab_arc != nullptr;
+    if (img_dtype == 0) {
+        if (tab)
+            hipLaunchKernelGGL((srt_fwd_kernel<0, true>), grid, block, 0, s, P, img, part, klo);
+        else
+            hipLaunchKernelGGL((srt_fwd_kernel<0, false>), grid, block, 0, s, P, img, part, klo);
+    } else {
+        if (tab)
+            hipLaunchKernelGGL((srt_fwd_kernel<1, true>), grid, block, 0, s, P, img, part, klo);
+        else
+            hipLaunchKernelGGL((srt_fwd_kernel<1, false>), grid, block, 0, s, P, img, part, klo);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_srt_adj(const Problem &P, const float *gp, float *img_part, void *img,
-                          int img_dtype, int qsplit, hipStream_t s)
+hipError_t launch_srt_adj(const Problem &P, const float *gp, float *bbuf, void *img,
+                          int img_dtype, hipStream_t s)
 {
-    (void)img_part;
-    (void)qsplit;
     dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
-    if (img_dtype == 0)
-        hipLaunchKernelGGL(srt_adj_kernel<0>, grid, block, 0, s, P, gp, img);
+    if (P.tab_arc != nullptr)
+        hipLaunchKernelGGL(srt_adj_kernel<true>, grid, block, 0, s, P, gp, bbuf);
     else
-        hipLaunchKernelGGL(srt_adj_kernel<1>, grid, block, 0, s, P, gp, img);
+        hipLaunchKernelGGL(srt_adj_kernel<false>, grid, block, 0, s, P, gp, bbuf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_adj_gather(P, bbuf, img, img_dtype, s);
+}
+
+hipError_t launch_arc_build(const Problem &P, int fill, hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz), block(WAVES * WAVE);
+    if (fill)
+        hipLaunchKernelGGL(arc_build_kernel<WALK_FILL>, grid, block, 0, s, P);
+    else
+        hipLaunchKernelGGL(arc_build_kernel<WALK_COUNT>, grid, block, 0, s, P);
     return hipGetLastError();
 }
 

@@ -27,8 +27,8 @@ OAT_F32 = 0
 OAT_BF16 = 1
 OAT_FLAG_SRT_ONLY = 1
 
-EXPORTED = ("oat_plan_create", "oat_plan_destroy", "oat_project", "oat_backproject",
-            "oat_fbp", "oat_last_error", "oat_plan_stats")
+EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
+            "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats")
 
 
 class OatError(RuntimeError):
@@ -45,6 +45,10 @@ class _Geom(ctypes.Structure):
                 ("det_area", ctypes.POINTER(ctypes.c_double)),
                 ("n_t", ctypes.c_int32), ("dt", ctypes.c_double), ("t0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("arc_table_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -65,6 +69,9 @@ def lib():
         vp = ctypes.c_void_p
         L.oat_plan_create.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int, ctypes.POINTER(vp)]
         L.oat_plan_create.restype = ctypes.c_int
+        L.oat_plan_create_ex.argtypes = [ctypes.POINTER(_Geom), ctypes.c_int,
+                                         ctypes.POINTER(_Options), ctypes.POINTER(vp)]
+        L.oat_plan_create_ex.restype = ctypes.c_int
         L.oat_plan_destroy.argtypes = [vp]
         L.oat_plan_destroy.restype = None
         for name in ("oat_project", "oat_backproject", "oat_fbp"):
@@ -100,7 +107,9 @@ def _dtype_code(t) -> int:
 class Plan:
     """Tables and workspace for one geometry on one device (oat_plan)."""
 
-    def __init__(self, geom: Geometry, device: int = 0):
+    def __init__(self, geom: Geometry, device: int = 0, arc_table="auto"):
+        """arc_table: "auto" (build it if it fits in 40% of free device
+        memory), False / 0 (never), or a byte budget (oat_plan_options)."""
         self.geom = geom
         self.device = int(device)
         self._xyz = np.ascontiguousarray(geom.det_xyz, dtype=np.float64).reshape(-1, 3)
@@ -111,8 +120,16 @@ class Plan:
                         self._xyz.shape[0], self._xyz.ctypes.data_as(dp),
                         self._area.ctypes.data_as(dp) if self._area is not None else dp(),
                         geom.n_t, geom.dt, geom.t0, geom.c0, geom.gamma)
+        if arc_table == "auto" or arc_table is None:
+            budget = -1
+        elif arc_table is False:
+            budget = 0
+        else:
+            budget = int(arc_table)
+        self._opt = _Options(budget)
         h = ctypes.c_void_p()
-        _check(lib().oat_plan_create(ctypes.byref(self._g), self.device, ctypes.byref(h)))
+        _check(lib().oat_plan_create_ex(ctypes.byref(self._g), self.device,
+                                        ctypes.byref(self._opt), ctypes.byref(h)))
         self._h = h
 
     # -- plumbing ---------------------------------------------------------
@@ -128,9 +145,10 @@ class Plan:
             pass
 
     def stats(self) -> dict:
-        v = (ctypes.c_int64 * 6)()
-        _check(lib().oat_plan_stats(self._h, v, 6))
-        keys = ("rings", "bricks", "brick", "window", "workspace_bytes", "table_bytes")
+        v = (ctypes.c_int64 * 9)()
+        _check(lib().oat_plan_stats(self._h, v, 9))
+        keys = ("rings", "bricks", "brick", "window", "workspace_bytes", "table_bytes",
+                "arc_table_bytes", "arc_table_entries", "arc_table_build_us")
         return dict(zip(keys, [int(x) for x in v]))
 
     def _prep(self, t, shape):

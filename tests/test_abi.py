@@ -64,9 +64,23 @@ def test_invalid_geometry_is_rejected_before_launch(kw):
     assert oat.last_error() != ""
 
 
+def test_negative_table_budget_is_rejected():
+    g = _geom()
+    xyz = np.ascontiguousarray(g.det_xyz, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = oat._Geom(g.nx, g.ny, g.nz, g.dx, g.x0, g.y0, g.z0, xyz.shape[0], xyz.ctypes.data_as(dp),
+                  dp(), g.n_t, g.dt, g.t0, g.c0, g.gamma)
+    h = ctypes.c_void_p()
+    opt = oat._Options(-2)
+    assert oat.lib().oat_plan_create_ex(ctypes.byref(p), 0, ctypes.byref(opt),
+                                        ctypes.byref(h)) == oat.OAT_ERR_ARG
+    assert not h.value and "arc_table_bytes" in oat.last_error()
+
+
 def test_null_arguments():
     L = oat.lib()
     assert L.oat_plan_create(None, 0, None) == oat.OAT_ERR_ARG
+    assert L.oat_plan_create_ex(None, 0, None, None) == oat.OAT_ERR_ARG
     assert L.oat_project(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
     assert L.oat_backproject(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
     assert L.oat_fbp(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG

@@ -148,8 +148,9 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("table", [True, False])
 @pytest.mark.parametrize("case", range(len(RAGGED)))
-def test_ragged_grids(case, Plan):
+def test_ragged_grids(case, table, Plan):
     c = RAGGED[case]
     nx, ny, nz = c["n"]
     det = synth.fibonacci_sphere(c["Q"], c["Rs"])
@@ -157,12 +158,13 @@ def test_ragged_grids(case, Plan):
                           synth.centred_origin(ny, c["dx"]) + c["off"][1],
                           synth.centred_origin(nz, c["dx"]) + c["off"][2], det, c["K"], c["dt"],
                           c["t0"], 1.5, 1.3)
-    _say(f"[gpu] ragged case {case} {c}")
+    _say(f"[gpu] ragged case {case} arc table {table} {c}")
     gd = geom.as_dict()
     rng = np.random.default_rng(case)
     img = rng.uniform(0, 1, size=geom.shape)
     img = img.astype(np.float32).astype(np.float64)
-    plan = Plan(geom, 0)
+    plan = Plan(geom, 0, arc_table="auto" if table else False)
+    assert (plan.stats()["arc_table_bytes"] > 0) == table
     g = _np(plan.project(_t(img), srt_only=True))
     assert rel(g, ref.srt(gd, img)) < 1e-6
     p = _np(plan.project(_t(img)))
@@ -209,3 +211,30 @@ def test_repeat_runs(small):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert rel(_np(c), _np(d)) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_arc_table_and_arc_bounds_agree(seed, Plan):
+    """The plan's arc table (tight arcs of the owned points) and the kernels'
+    own arc bounds enumerate the same points: G and G^T agree to FP32
+    summation order, and both match the oracle."""
+    geom, _, img = synth.config_small(seed)
+    _say(f"[gpu] arc table vs arc bounds seed {seed}")
+    pt = Plan(geom, 0)
+    pn = Plan(geom, 0, arc_table=False)
+    st, sn = pt.stats(), pn.stats()
+    assert st["arc_table_bytes"] > 0 and st["arc_table_entries"] > 0
+    assert sn["arc_table_bytes"] == 0
+    assert Plan(geom, 0, arc_table=1).stats()["arc_table_bytes"] == 0   # budget too small
+    x = _t(img)
+    gt, gn = _np(pt.project(x, srt_only=True)), _np(pn.project(x, srt_only=True))
+    e = rel(gt, gn)
+    _say(f"  G table vs bounds rel {e:.3e}")
+    assert e < 1e-6
+    assert rel(gn, ref.srt(geom.as_dict(), img)) < 1e-6
+    rng = np.random.default_rng(400 + seed)
+    y = _t(rng.normal(size=(geom.n_det, geom.n_t)))
+    at, an = _np(pt.backproject(y, srt_only=True)), _np(pn.backproject(y, srt_only=True))
+    e = rel(at, an)
+    _say(f"  G^T table vs bounds rel {e:.3e}")
+    assert e < 1e-6
