@@ -350,58 +350,68 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 const int jref = sb + ((se - sb - 1) >> 1);
                 const int ub = wrap ? jb + nj2 - jlo2 : jb - jlo2;   // offset of jb in the arc
                 // Reference point of the segment in FP64, split into an
-                // integer cell (relative to the box) and an FP32 fraction, and
-                // the radial (X) and tangential (Y) vectors there: point j is
-                // ref + X (cos d - 1) + Y sin d, d = (j - jref) 2 pi / nj.
+                // integer cell (relative to the box, packed 10 bits per axis)
+                // and an FP32 fraction, and its in-plane coordinates
+                // (xa, xb) = rs (cos, sin) of the reference azimuth: point j
+                // is ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
+                // b = xb (cos d - 1) + xa sin d, d = (j - jref) 2 pi / nj.
                 double cr, sr;
                 sincos_turns_d((double)jref * in2, cr, sr);
-                float Pl[3], X[3], Y[3];
-                int Db[3];
+                float Pl[3];
+                int dpk = 0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const double ra = rs2 * fma(cr, e1d[a], sr * e2d[a]);
-                    const double ta = rs2 * fma(cr, e2d[a], -(sr * e1d[a]));
-                    const double pa = fma(rc2, e3[a], uq[a]) + ra;
+                    const double pa = fma(rc2, e3[a], uq[a]) + rs2 * fma(cr, e1d[a], sr * e2d[a]);
                     const double ph = floor(pa);
                     Pl[a] = (float)(pa - ph);
-                    Db[a] = (int)ph - lo[a];
-                    X[a] = (float)ra;
-                    Y[a] = (float)ta;
+                    // clamped offsets only occur for points far outside the box
+                    const int db = min(max((int)ph - lo[a], -512), 511) + 512;
+                    dpk |= db << (10 * a);
                 }
-                const int dj0 = jb - jref;
+                const float xa = (float)(rs2 * cr), xb = (float)(rs2 * sr);
                 const int npts = v2 ? max(je - jb, 0) : 0;
-                level_begin<6>(L3, npts);
+                // jb - jref in [-16, 16], npts <= 32, shell index < 4096
+                const int meta = (jb - jref + 64) | (npts << 7) | (k2 << 13);
+                // Level 3: each lane takes two consecutive points of a segment.
+                level_begin<5>(L3, (npts + 1) >> 1);
                 for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
-                    int s3, loc3;
-                    bool v3 = level_item(L3, F3, s3, loc3);
+                    int s3, pr;
+                    const bool v3 = level_item(L3, F3, s3, pr);
                     const float p0 = bperm_f(s3, Pl[0]), p1 = bperm_f(s3, Pl[1]), p2 = bperm_f(s3, Pl[2]);
-                    const int d0 = bperm_i(s3, Db[0]), d1 = bperm_i(s3, Db[1]), d2 = bperm_i(s3, Db[2]);
-                    const float x0 = bperm_f(s3, X[0]), x1 = bperm_f(s3, X[1]), x2 = bperm_f(s3, X[2]);
-                    const float y0 = bperm_f(s3, Y[0]), y1 = bperm_f(s3, Y[1]), y2 = bperm_f(s3, Y[2]);
+                    const int dp = bperm_i(s3, dpk);
+                    const float qa = bperm_f(s3, xa), qb = bperm_f(s3, xb);
                     const float dd = bperm_f(s3, dl2);
-                    const int dj = bperm_i(s3, dj0) + loc3;
-                    float cm1, sn;
-                    small_rot((float)dj * dd, cm1, sn);
-                    // Fractional coordinates about the reference cell: the same
-                    // FP32 operations in every brick, so ownership is exact.
-                    const float ux = fmaf(y0, sn, fmaf(x0, cm1, p0));
-                    const float uy = fmaf(y1, sn, fmaf(x1, cm1, p1));
-                    const float uz = fmaf(y2, sn, fmaf(x2, cm1, p2));
-                    const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-                    const int cx = (int)fx0 + d0, cy = (int)fy0 + d1, cz = (int)fz0 + d2;
-                    const bool own = v3 && (unsigned)cx < (unsigned)(hi[0] - lo[0]) &&
-                                     (unsigned)cy < (unsigned)(hi[1] - lo[1]) &&
-                                     (unsigned)cz < (unsigned)(hi[2] - lo[2]);
-                    if (MODE == WALK_POINTS) {
-                        const float wv = bperm_f(s3, w2);
-                        const int kk = bperm_i(s3, k2);
-                        fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
-                    } else {
-                        const int rl = bperm_i(s3, s2);
-                        const int uu = bperm_i(s3, ub) + loc3;
-                        if (own) {
-                            atomicMin(&B->rmin[rl], uu);
-                            atomicMax(&B->rmax[rl], uu);
+                    const int mt = bperm_i(s3, meta);
+                    const float wv = MODE == WALK_POINTS ? bperm_f(s3, w2) : 0.f;
+                    const int rl = MODE == WALK_POINTS ? 0 : bperm_i(s3, s2);
+                    const int ur = MODE == WALK_POINTS ? 0 : bperm_i(s3, ub) + 2 * pr;
+                    const int d0 = (dp & 1023) - 512, d1 = ((dp >> 10) & 1023) - 512,
+                              d2 = ((dp >> 20) & 1023) - 512;
+                    const int np = (mt >> 7) & 63, kk = mt >> 13;
+                    const int djA = (mt & 127) - 64 + 2 * pr;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        float cm1, sn;
+                        small_rot((float)(djA + h) * dd, cm1, sn);
+                        const float al = fmaf(qa, cm1, -(qb * sn));
+                        const float be = fmaf(qb, cm1, qa * sn);
+                        // Fractional coordinates about the reference cell: the
+                        // same FP32 operations in every brick, so ownership is
+                        // exact.
+                        const float ux = fmaf(be, e2[0], fmaf(al, e1[0], p0));
+                        const float uy = fmaf(be, e2[1], fmaf(al, e1[1], p1));
+                        const float uz = fmaf(be, e2[2], fmaf(al, e1[2], p2));
+                        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+                        const int cx = (int)fx0 + d0, cy = (int)fy0 + d1, cz = (int)fz0 + d2;
+                        const bool own = v3 && 2 * pr + h < np &&
+                                         (unsigned)cx < (unsigned)(hi[0] - lo[0]) &&
+                                         (unsigned)cy < (unsigned)(hi[1] - lo[1]) &&
+                                         (unsigned)cz < (unsigned)(hi[2] - lo[2]);
+                        if (MODE == WALK_POINTS) {
+                            fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
+                        } else if (own) {
+                            atomicMin(&B->rmin[rl], ur + h);
+                            atomicMax(&B->rmax[rl], ur + h);
                         }
                     }
                 }
