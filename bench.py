@@ -35,6 +35,45 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube.txt")
+
+
+def kernel_sources_sha256():
+    """Hash of the HIP/C++ sources the kernels are built from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1304_2017_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a device copy of known size),
+    or None when the summary is missing or the kernel sources have changed
+    since the counters were taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    fields = {}
+    for ln in lines:
+        t = ln.split()
+        if len(t) >= 2 and not ln.startswith("#"):
+            fields.setdefault(t[0], []).append(t[1:])
+    if fields.get("sources", [[None]])[0][0] != kernel_sources_sha256():
+        return None
+    for t in fields.get("kernel", []):
+        if t[0] == kernel:
+            kv = dict(zip(t[1::2], t[2::2]))
+            return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def quad_points(geom):
     """Quadrature points that one G or G^T pass evaluates: every cell of the
     footprint [-1, n-1]^3 is crossed by dx/(c0 dt) points per transducer
@@ -94,7 +133,11 @@ def main():
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")
     geom, ells, img = synth.config_large(0, dtype=np.float32)
+    t_plan = time.perf_counter()
     plan = Plan(geom, 0)
+    plan_s = time.perf_counter() - t_plan
+    st = plan.stats()
+    log(f"[bench] plan {plan_s:.2f} s, arc table {st['arc_table_bytes'] / 1e9:.2f} GB")
     x = torch.from_numpy(img).to(dev)
     p = torch.empty(plan.data_shape, device=dev)
     a = torch.empty(plan.image_shape, device=dev)
@@ -147,7 +190,8 @@ def main():
     dom_name, dom_ms = ("srt_adj_kernel", t_ht) if t_ht >= t_h else ("srt_fwd_kernel", t_h)
     achieved = OPS_PER_POINT * pts / (dom_ms * 1e-3)
     roof = dict(bound="alu", kernel=dom_name, achieved=achieved, peak=VALU_PEAK,
-                unit="VALU lane-op/s", frac=achieved / VALU_PEAK, traffic=None,
+                unit="VALU lane-op/s", frac=achieved / VALU_PEAK,
+                traffic=measured_traffic(dom_name),
                 ops_per_point=OPS_PER_POINT, points_per_launch=pts)
     out = dict(metric="H/H^T voxel-view updates/s", value=value, unit="voxel-view updates/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
@@ -155,7 +199,9 @@ def main():
                data="synthetic",
                config=dict(workload="256^3 image (0.1 mm), 2048 transducers on a 40 mm "
                                     "hemisphere, 1024 samples at 20 MHz; step = H + H^T + FBP",
-                           nx=256, n_det=Q, n_t=geom.n_t, storage="f32"),
+                           nx=256, n_det=Q, n_t=geom.n_t, storage="f32",
+                           arc_table_bytes=st["arc_table_bytes"],
+                           plan_build_s=plan_s),
                ops=dict(H_ms=t_h, HT_ms=t_ht, FBP_ms=t_f,
                         H_updates_per_s=N * Q / (t_h * 1e-3),
                         HT_updates_per_s=N * Q / (t_ht * 1e-3),
