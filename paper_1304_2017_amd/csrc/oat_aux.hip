@@ -89,11 +89,17 @@ srt_reduce_kernel(Problem P, const float *__restrict__ part, const int *__restri
 }
 
 // g'[q,k] = coef (y_{k-1} - y_{k+1}) / t_k  (0 where t_k <= 0; y_{-1} = y_K = 0),
-// or a plain FP32 copy of y when apply_dt == 0.
-__global__ void diff_adj_kernel(Problem P, const void *__restrict__ y, int y_dt,
-                                float *__restrict__ gp, int apply_dt)
+// or a plain FP32 copy of y when apply_dt == 0.  Each workgroup also writes
+// to P.gp_max[blockIdx.x] the largest |g'| among its samples whose shell can
+// reach the image support (G^T sets its fixed-point scale from these; the
+// other samples meet no quadrature point).
+__global__ void __launch_bounds__(256) diff_adj_kernel(Problem P, const void *__restrict__ y,
+                                                       int y_dt, float *__restrict__ gp,
+                                                       int apply_dt)
 {
+    __shared__ float wmax[4];
     const size_t total = (size_t)P.nq * P.nt;
+    float m = 0.f;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
         const int k = (int)(i % P.nt);
@@ -107,7 +113,15 @@ __global__ void diff_adj_kernel(Problem P, const void *__restrict__ y, int y_dt,
             v = load_val(y, i, y_dt);
         }
         gp[i] = v;
+        const float rho = fmaf((float)k, P.rho_step, P.rho0);
+        const float dq = P.det[i / P.nt].dist;
+        if (fabsf(rho - dq) <= P.r_sup + 2.f) m = fmaxf(m, fabsf(v));
     }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        P.gp_max[blockIdx.x] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
 }
 
 // G^T output.  A brick's box holds the nodes of its cells, one node below
@@ -244,10 +258,9 @@ hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo
 hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp, int apply_dt,
                            hipStream_t s)
 {
-    size_t total = (size_t)P.nq * P.nt;
-    int blocks = (int)((total + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(diff_adj_kernel, dim3(blocks), dim3(256), 0, s, P, y, y_dtype, gp, apply_dt);
+    // Always DIFF_BLOCKS workgroups: G^T reads that many maxima.
+    hipLaunchKernelGGL(diff_adj_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, P, y, y_dtype, gp,
+                       apply_dt);
     return hipGetLastError();
 }
 

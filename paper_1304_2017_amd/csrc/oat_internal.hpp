@@ -19,6 +19,7 @@ constexpr int BOX3 = BOX * BOX * BOX;          // dense box in HBM (G^T brick ou
 constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
 constexpr int WAVE = 64;
 constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
+constexpr int DIFF_BLOCKS = 1024;            // workgroups of the D^T kernel (one max each)
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).
 struct alignas(16) DetRec {
@@ -72,6 +73,9 @@ struct Problem {
     // FP64 problem statement for FBP's floor decisions (same formula as the
     // problem statement: kt = (|r_n - r_q| / c0 - t0) / dt, r_n = r_0 + dx * n)
     double x0, y0, z0, dxd, c0d, t0d, dtd;
+    float w_max;           // largest ring weight
+    float r_sup;           // radius of the image support sphere / dx
+    float *gp_max;         // [DIFF_BLOCKS] per-block max |g'| written by the D^T kernel
     const DetRec *det;
     const ShellRec *shell;
     const RingRec *ring;

@@ -65,11 +65,13 @@ struct oat_plan {
     int *d_klo = nullptr;        // [bricks][Q]
     float *d_gp = nullptr;       // D^T y  [Q][K]
     float *d_bbuf = nullptr;     // G^T brick boxes [bricks][BOX^3]
+    float *d_gpmax = nullptr;    // [DIFF_BLOCKS] per-block max |D^T y|
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
     int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0;
     int max_nj = 0, max_rings = 0;
+    float w_max = 0.f;
     int64_t n_rings = 0;
     int64_t ws_bytes = 0, table_bytes = 0;
 };
@@ -179,7 +181,7 @@ void oat_plan_destroy(oat_plan *plan)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(plan->device);
     void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
-                    plan->d_klo, plan->d_gp, plan->d_bbuf, plan->d_tab_off,
+                    plan->d_klo, plan->d_gp, plan->d_bbuf, plan->d_gpmax, plan->d_tab_off,
                     plan->d_tab_run, plan->d_tab_arc};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -276,6 +278,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     std::vector<ShellRec> shell(K);
     std::vector<RingRec> ring;
     int max_nj = 0, max_rings = 0;
+    float w_max = 0.f;
     for (int k = 0; k < K; ++k) {
         double rho = g->c0 * (g->t0 + k * g->dt);
         ShellRec &S = shell[k];
@@ -309,6 +312,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
             rr.lshift = seg_shift((int)nj);
             rr.pad = 0;
             if (nj > max_nj) max_nj = (int)nj;
+            if (rr.w > w_max) w_max = rr.w;
             ring.push_back(rr);
         }
     }
@@ -348,6 +352,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         }
         P.window = w;
     }
+    P.w_max = w_max;
+    P.r_sup = (float)(R / dx);
     P.t0 = (float)g->t0;
     P.dt = (float)g->dt;
     P.d_coef = (float)(g->gamma / (4.0 * M_PI * g->c0 * g->c0) / (2.0 * g->dt));
@@ -388,7 +394,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = alloc((void **)&plan->d_part, part_b, "partials")) != hipSuccess ||
         (e = alloc((void **)&plan->d_klo, klo_b, "klo")) != hipSuccess ||
         (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_bbuf, bbuf_b, "brick boxes")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_bbuf, bbuf_b, "brick boxes")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_gpmax, sizeof(float) * DIFF_BLOCKS, "gp max")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -405,6 +412,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.det = plan->d_det;
     P.shell = plan->d_shell;
     P.ring = plan->d_ring;
+    P.gp_max = plan->d_gpmax;
     P.tab_off = nullptr;
     P.tab_run = nullptr;
     P.tab_arc = nullptr;

@@ -5,8 +5,8 @@
 // G^T (adjoint, Sec. II.C): alpha'_n = sum_{q,k,i,j} w_{k,i} g'[q,k] psi_n(x_{q,k,i,j})
 //
 // The image is cut into bricks of BRICK^3 cells.  A workgroup owns one brick
-// and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, an FP64
-// accumulator for G^T.  Each wave takes one transducer at a time and
+// and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, a 64-bit
+// fixed-point accumulator for G^T.  Each wave takes one transducer at a time and
 // enumerates exactly the quadrature points whose trilinear cell lies in the
 // brick, in three wave-wide expansions:
 //   shells k -> candidate rings (k, i) -> ring segments -> points.
@@ -188,7 +188,7 @@ struct BuildLds {
 template <bool ADJ, bool TAB, int MODE, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
                                           const int hi[3], WaveLds &W, BuildLds *B,
-                                          const float *gp, int &klo_out, Fn &&fn)
+                                          const float *gp, float gscale, int &klo_out, Fn &&fn)
 {
     constexpr bool READ_RUNS = TAB || MODE == WALK_FILL;
     const DetRec &d = P.det[q];
@@ -324,7 +324,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                     }
                 }
             }
-            if (ADJ && v1 && items_all > 0) w = w * gp[(size_t)q * P.nt + kr];
+            if (ADJ && v1 && items_all > 0) w = w * (gp[(size_t)q * P.nt + kr] * gscale);
             if (MODE != WALK_POINTS) {
                 B->rmin[lane] = 0x7fffffff;
                 B->rmax[lane] = -1;
@@ -521,7 +521,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
             }
         };
         walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
-                                           klo, gather);
+                                           1.f, klo, gather);
         if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
@@ -533,9 +533,14 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 
 // ---------------------------------------------------------------------------
 // G^T: each brick takes the same cells (hence the same points) as in G and
-// accumulates their trilinear weights in an FP64 LDS box with the native FP64
-// LDS atomic add (ds_add_f64; the FP32 one is microcoded on this part and
-// ~20x slower), so no partial flushes are needed.  16 waves share the box.
+// accumulates their trilinear weights in an LDS box of 64-bit integers.
+// Every weight w g' psi is scaled by 2^s, rounded to an integer and added
+// with the native 64-bit integer LDS atomic (ds_add_u64; about half the cost
+// of ds_add_f64 on this part, and the FP32 one is microcoded).  s is the
+// largest power of two that keeps every weight below 2^30 (from the largest
+// |g'| of the call and the largest ring weight), so each rounding error is at
+// most 2^-31 of the largest weight, the sums are exact and independent of
+// the order of the atomics: G^T is deterministic.  16 waves share the box.
 // The box (its owned nodes and the one-node layer below them, which belongs
 // to the neighbouring bricks) is written to HBM in FP32 and adj_gather_kernel
 // adds the overlapping layers.
@@ -546,13 +551,27 @@ template <bool TAB>
 __global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf)
 {
-    __shared__ double box[BOX_WORDS];
+    __shared__ unsigned long long box[BOX_WORDS];
     __shared__ WaveLds wl[ADJ_WAVES];
+    __shared__ float wmax[ADJ_WAVES];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
-    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0.0;
+    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
+    // Largest |g'| of the call (one value per D^T workgroup).
+    float m = 0.f;
+    for (int t = threadIdx.x; t < DIFF_BLOCKS; t += blockDim.x) m = fmaxf(m, P.gp_max[t]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane_id() == 0) wmax[threadIdx.x / WAVE] = m;
     __syncthreads();
+    m = 0.f;
+    for (int w = 0; w < ADJ_WAVES; ++w) m = fmaxf(m, wmax[w]);
+    const float bound = m * P.w_max;
+    int e = 0;
+    (void)frexpf(bound, &e);                  // bound < 2^e
+    const int sh = bound > 0.f ? min(max(30 - e, -100), 100) : 0;
+    const float gscale = ldexpf(1.f, sh);
+    const double unscale = ldexp(1.0, -sh);
 
     const int wave = threadIdx.x / WAVE;
     WaveLds &W = wl[wave];
@@ -563,27 +582,32 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf
             (void)kk;
             (void)kbase;
             if (own) {
-                double *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
-                float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
-                float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv, w11 = fy * fz * wv;
-                atomicAdd(pb, (double)(gx * w00));
-                atomicAdd(pb + 1, (double)(fx * w00));
-                atomicAdd(pb + BOX_SY, (double)(gx * w01));
-                atomicAdd(pb + BOX_SY + 1, (double)(fx * w01));
-                atomicAdd(pb + BOX_SZ, (double)(gx * w10));
-                atomicAdd(pb + BOX_SZ + 1, (double)(fx * w10));
-                atomicAdd(pb + BOX_SZ + BOX_SY, (double)(gx * w11));
-                atomicAdd(pb + BOX_SZ + BOX_SY + 1, (double)(fx * w11));
+                unsigned long long *pb =
+                    box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
+                const float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
+                const float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv,
+                            w11 = fy * fz * wv;
+                auto add = [](unsigned long long *p, float v) {
+                    atomicAdd(p, (unsigned long long)(long long)__float2int_rn(v));
+                };
+                add(pb, gx * w00);
+                add(pb + 1, fx * w00);
+                add(pb + BOX_SY, gx * w01);
+                add(pb + BOX_SY + 1, fx * w01);
+                add(pb + BOX_SZ, gx * w10);
+                add(pb + BOX_SZ + 1, fx * w10);
+                add(pb + BOX_SZ + BOX_SY, gx * w11);
+                add(pb + BOX_SZ + BOX_SY + 1, fx * w11);
             }
         };
-        walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp, klo,
-                                          scatter);
+        walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp,
+                                          gscale, klo, scatter);
     }
     __syncthreads();
     float *dst = bbuf + (size_t)b * BOX3;
     for (int t = threadIdx.x; t < BOX3; t += blockDim.x) {
         int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
-        dst[t] = (float)box[z * BOX_SZ + y * BOX_SY + x];
+        dst[t] = (float)((double)(long long)box[z * BOX_SZ + y * BOX_SY + x] * unscale);
     }
 }
 
@@ -607,7 +631,7 @@ arc_build_kernel(Problem P)
     for (int q = wave; q < P.nq; q += WAVES) {
         int klo = 0;
         walk_unit<false, false, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
-                                      nullptr, klo, none);
+                                      nullptr, 1.f, klo, none);
     }
 }
 
