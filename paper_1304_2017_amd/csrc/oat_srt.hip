@@ -87,6 +87,22 @@ __device__ __forceinline__ float wave_sum_dpp(float v)
 
 __device__ __forceinline__ uint64_t mask_below() { return (1ull << lane_id()) - 1ull; }
 
+// floor(x) as an integer in one instruction (the compiler emits floor + convert).
+__device__ __forceinline__ int cvt_floor(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// One quadrature point as handed to the gather/scatter: owned by the brick,
+// cell relative to the box, fractional position in the cell.
+struct Pt {
+    bool own;
+    int cx, cy, cz;
+    float fx, fy, fz;
+};
+
 // One level of wave-wide expansion: producer lanes hold counts, consumers
 // walk the concatenation 64 items at a time.  Head bits mark where each
 // producer's run starts; a ballot plus popcount turns them into a rank, and a
@@ -183,8 +199,9 @@ struct BuildLds {
 // Ring arcs come from the ball/slab bounds (TAB = false) or from the plan's
 // arc table (TAB = true, tight arcs of exactly the rings that hold owned
 // points); both give the same owned points.  In WALK_POINTS mode fn is called
-// per window of 64 points with (valid&owned, cell index relative to the box,
-// fractions, item value, shell index, first shell of the unit).
+// per window of 64 lanes with the lane's two consecutive points of one
+// segment (Pt each), their weight, their shell index and the unit's first
+// shell.
 template <bool ADJ, bool TAB, int MODE, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
                                           const int hi[3], WaveLds &W, BuildLds *B,
@@ -389,6 +406,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                               d2 = ((dp >> 20) & 1023) - 512;
                     const int np = (mt >> 7) & 63, kk = mt >> 13;
                     const int djA = (mt & 127) - 64 + 2 * pr;
+                    Pt pt[2];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         float cm1, sn;
@@ -401,18 +419,26 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                         const float ux = fmaf(be, e2[0], fmaf(al, e1[0], p0));
                         const float uy = fmaf(be, e2[1], fmaf(al, e1[1], p1));
                         const float uz = fmaf(be, e2[2], fmaf(al, e1[2], p2));
-                        const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-                        const int cx = (int)fx0 + d0, cy = (int)fy0 + d1, cz = (int)fz0 + d2;
-                        const bool own = v3 && 2 * pr + h < np &&
-                                         (unsigned)cx < (unsigned)(hi[0] - lo[0]) &&
-                                         (unsigned)cy < (unsigned)(hi[1] - lo[1]) &&
-                                         (unsigned)cz < (unsigned)(hi[2] - lo[2]);
-                        if (MODE == WALK_POINTS) {
-                            fn(own, cx, cy, cz, ux - fx0, uy - fy0, uz - fz0, wv, kk, klo);
-                        } else if (own) {
-                            atomicMin(&B->rmin[rl], ur + h);
-                            atomicMax(&B->rmax[rl], ur + h);
-                        }
+                        Pt &t = pt[h];
+                        t.cx = cvt_floor(ux) + d0;
+                        t.cy = cvt_floor(uy) + d1;
+                        t.cz = cvt_floor(uz) + d2;
+                        t.fx = __builtin_amdgcn_fractf(ux);
+                        t.fy = __builtin_amdgcn_fractf(uy);
+                        t.fz = __builtin_amdgcn_fractf(uz);
+                        t.own = v3 && 2 * pr + h < np && (unsigned)t.cx < (unsigned)(hi[0] - lo[0]) &&
+                                (unsigned)t.cy < (unsigned)(hi[1] - lo[1]) &&
+                                (unsigned)t.cz < (unsigned)(hi[2] - lo[2]);
+                    }
+                    if (MODE == WALK_POINTS) {
+                        fn(pt[0], pt[1], wv, kk, klo);
+                    } else {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            if (pt[h].own) {
+                                atomicMin(&B->rmin[rl], ur + h);
+                                atomicMax(&B->rmax[rl], ur + h);
+                            }
                     }
                 }
             }
@@ -500,24 +526,28 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
         // window with the native LDS FP64 atomic when the shell changes.
         float racc = 0.f;
         int rk = -1, rbase = 0;
-        auto gather = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz, float wv,
-                          int kk, int kbase) {
-            if (own) {
-                const float *pb = box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
-                float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
-                float v100 = pb[BOX_SZ], v101 = pb[BOX_SZ + 1], v110 = pb[BOX_SZ + BOX_SY],
-                      v111 = pb[BOX_SZ + BOX_SY + 1];
-                float c00 = fmaf(fx, v001 - v000, v000), c01 = fmaf(fx, v011 - v010, v010);
-                float c10 = fmaf(fx, v101 - v100, v100), c11 = fmaf(fx, v111 - v110, v110);
-                float c0 = fmaf(fy, c01 - c00, c00), c1 = fmaf(fy, c11 - c10, c10);
-                float val = fmaf(fz, c1 - c0, c0) * wv;
+        auto interp = [&](const Pt &t) {
+            const float *pb = box + __umul24((unsigned)t.cz, BOX_SZ) + __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+            const float *pz = pb + BOX_SZ;
+            const float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
+            const float v100 = pz[0], v101 = pz[1], v110 = pz[BOX_SY], v111 = pz[BOX_SY + 1];
+            const float c00 = fmaf(t.fx, v001 - v000, v000), c01 = fmaf(t.fx, v011 - v010, v010);
+            const float c10 = fmaf(t.fx, v101 - v100, v100), c11 = fmaf(t.fx, v111 - v110, v110);
+            const float c0 = fmaf(t.fy, c01 - c00, c00), c1 = fmaf(t.fy, c11 - c10, c10);
+            return fmaf(t.fz, c1 - c0, c0);
+        };
+        auto gather = [&](const Pt &a, const Pt &c, float wv, int kk, int kbase) {
+            float sum = 0.f;
+            if (a.own) sum = interp(a);
+            if (c.own) sum += interp(c);
+            if (a.own || c.own) {
                 if (kk != rk) {
                     if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
                     rk = kk;
                     rbase = kbase;
                     racc = 0.f;
                 }
-                racc += val;
+                racc = fmaf(sum, wv, racc);
             }
         };
         walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
@@ -534,13 +564,13 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // ---------------------------------------------------------------------------
 // G^T: each brick takes the same cells (hence the same points) as in G and
 // accumulates their trilinear weights in an LDS box of 64-bit integers.
-// Every weight w g' psi is scaled by 2^s, rounded to an integer and added
+// Every weight w g' psi is scaled by 2^s, truncated to an integer and added
 // with the native 64-bit integer LDS atomic (ds_add_u64; about half the cost
 // of ds_add_f64 on this part, and the FP32 one is microcoded).  s is the
 // largest power of two that keeps every weight below 2^30 (from the largest
-// |g'| of the call and the largest ring weight), so each rounding error is at
-// most 2^-31 of the largest weight, the sums are exact and independent of
-// the order of the atomics: G^T is deterministic.  16 waves share the box.
+// reachable |g'| of the call and the largest ring weight), so each
+// conversion error is below 2^-30 of the largest weight, and the sums are
+// exact and independent of the order of the atomics: G^T is deterministic.  16 waves share the box.
 // The box (its owned nodes and the one-node layer below them, which belongs
 // to the neighbouring bricks) is written to HBM in FP32 and adj_gather_kernel
 // adds the overlapping layers.
@@ -577,28 +607,32 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf
     WaveLds &W = wl[wave];
     for (int q = wave; q < P.nq; q += ADJ_WAVES) {
         int klo = 0;
-        auto scatter = [&](bool own, int cx, int cy, int cz, float fx, float fy, float fz,
-                           float wv, int kk, int kbase) {
+        // Weights are below 2^30 in magnitude; conversion truncates toward
+        // zero (an error below one unit, 2^-30 of the largest weight).
+        auto scatter1 = [&](const Pt &t, float wv) {
+            unsigned long long *pb =
+                box + __umul24((unsigned)t.cz, BOX_SZ) + __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+            unsigned long long *pz = pb + BOX_SZ;
+            const float gx = 1.f - t.fx, gy = 1.f - t.fy, gz = 1.f - t.fz;
+            const float w00 = gy * gz * wv, w01 = t.fy * gz * wv, w10 = gy * t.fz * wv,
+                        w11 = t.fy * t.fz * wv;
+            auto add = [](unsigned long long *p, float v) {
+                atomicAdd(p, (unsigned long long)(long long)(int)v);
+            };
+            add(pb, gx * w00);
+            add(pb + 1, t.fx * w00);
+            add(pb + BOX_SY, gx * w01);
+            add(pb + BOX_SY + 1, t.fx * w01);
+            add(pz, gx * w10);
+            add(pz + 1, t.fx * w10);
+            add(pz + BOX_SY, gx * w11);
+            add(pz + BOX_SY + 1, t.fx * w11);
+        };
+        auto scatter = [&](const Pt &a, const Pt &c, float wv, int kk, int kbase) {
             (void)kk;
             (void)kbase;
-            if (own) {
-                unsigned long long *pb =
-                    box + __umul24((unsigned)cz, BOX_SZ) + __umul24((unsigned)cy, BOX_SY) + cx;
-                const float gx = 1.f - fx, gy = 1.f - fy, gz = 1.f - fz;
-                const float w00 = gy * gz * wv, w01 = fy * gz * wv, w10 = gy * fz * wv,
-                            w11 = fy * fz * wv;
-                auto add = [](unsigned long long *p, float v) {
-                    atomicAdd(p, (unsigned long long)(long long)__float2int_rn(v));
-                };
-                add(pb, gx * w00);
-                add(pb + 1, fx * w00);
-                add(pb + BOX_SY, gx * w01);
-                add(pb + BOX_SY + 1, fx * w01);
-                add(pb + BOX_SZ, gx * w10);
-                add(pb + BOX_SZ + 1, fx * w10);
-                add(pb + BOX_SZ + BOX_SY, gx * w11);
-                add(pb + BOX_SZ + BOX_SY + 1, fx * w11);
-            }
+            if (a.own) scatter1(a, wv);
+            if (c.own) scatter1(c, wv);
         };
         walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp,
                                           gscale, klo, scatter);
@@ -627,7 +661,7 @@ arc_build_kernel(Problem P)
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
     const int wave = threadIdx.x / WAVE;
-    auto none = [](bool, int, int, int, float, float, float, float, int, int) {};
+    auto none = [](const Pt &, const Pt &, float, int, int) {};
     for (int q = wave; q < P.nq; q += WAVES) {
         int klo = 0;
         walk_unit<false, false, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
