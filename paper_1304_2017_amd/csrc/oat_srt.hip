@@ -154,6 +154,7 @@ constexpr int CAP2 = 16;   // segments per ring per pass (64 * 16 bits)
 
 // Per-wave LDS scratch.
 struct WaveLds {
+    float4 stage[64][3];   // per-segment data handed from level 2 to level 3
     unsigned bits1[128];
     unsigned bits2[32];
     unsigned bits3[64];
@@ -389,19 +390,33 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 const int npts = v2 ? max(je - jb, 0) : 0;
                 // jb - jref in [-16, 16], npts <= 32, shell index < 4096
                 const int meta = (jb - jref + 64) | (npts << 7) | (k2 << 13);
-                // Level 3: each lane takes two consecutive points of a segment.
+                // The segment's data goes to the wave's LDS stage, where the
+                // lanes of its points read it (a broadcast read; cheaper than
+                // one bpermute per value on this part).
+                wave_sync();
+                W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(dpk));
+                W.stage[lane][1] = make_float4(xa, xb, dl2, __int_as_float(meta));
+                W.stage[lane][2] = make_float4(w2, __int_as_float(s2), __int_as_float(ub), 0.f);
+                // Level 3: each lane takes two consecutive points of a segment
+                // (level_begin orders the stage writes before the reads).
                 level_begin<5>(L3, (npts + 1) >> 1);
                 for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
                     int s3, pr;
                     const bool v3 = level_item(L3, F3, s3, pr);
-                    const float p0 = bperm_f(s3, Pl[0]), p1 = bperm_f(s3, Pl[1]), p2 = bperm_f(s3, Pl[2]);
-                    const int dp = bperm_i(s3, dpk);
-                    const float qa = bperm_f(s3, xa), qb = bperm_f(s3, xb);
-                    const float dd = bperm_f(s3, dl2);
-                    const int mt = bperm_i(s3, meta);
-                    const float wv = MODE == WALK_POINTS ? bperm_f(s3, w2) : 0.f;
-                    const int rl = MODE == WALK_POINTS ? 0 : bperm_i(s3, s2);
-                    const int ur = MODE == WALK_POINTS ? 0 : bperm_i(s3, ub) + 2 * pr;
+                    const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1];
+                    const float p0 = r0.x, p1 = r0.y, p2 = r0.z;
+                    const int dp = __float_as_int(r0.w);
+                    const float qa = r1.x, qb = r1.y, dd = r1.z;
+                    const int mt = __float_as_int(r1.w);
+                    float wv = 0.f;
+                    int rl = 0, ur = 0;
+                    if (MODE == WALK_POINTS) {
+                        wv = W.stage[s3][2].x;
+                    } else {
+                        const float4 r2 = W.stage[s3][2];
+                        rl = __float_as_int(r2.y);
+                        ur = __float_as_int(r2.z) + 2 * pr;
+                    }
                     const int d0 = (dp & 1023) - 512, d1 = ((dp >> 10) & 1023) - 512,
                               d2 = ((dp >> 20) & 1023) - 512;
                     const int np = (mt >> 7) & 63, kk = mt >> 13;
@@ -485,14 +500,16 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
 // ---------------------------------------------------------------------------
 // G: partial sums per (brick, transducer) window.
 // ---------------------------------------------------------------------------
+constexpr int FWD_WAVES = 16;
+
 template <int IMG_DT, bool TAB>
-__global__ void __launch_bounds__(WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(FWD_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
                int *__restrict__ klo_out)
 {
     __shared__ float box[BOX_WORDS];
-    __shared__ WaveLds wl[WAVES];
-    __shared__ double gwin[WAVES][WMAX];
+    __shared__ WaveLds wl[FWD_WAVES];
+    __shared__ double gwin[FWD_WAVES][WMAX];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
@@ -517,7 +534,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     const int lane = lane_id();
     WaveLds &W = wl[wave];
     double *gw = gwin[wave];
-    for (int q = wave; q < P.nq; q += WAVES) {
+    for (int q = wave; q < P.nq; q += FWD_WAVES) {
         for (int j = lane; j < P.window; j += WAVE) gw[j] = 0.0;
         wave_sync();
         int klo = 0;
@@ -570,15 +587,15 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // largest power of two that keeps every weight below 2^30 (from the largest
 // reachable |g'| of the call and the largest ring weight), so each
 // conversion error is below 2^-30 of the largest weight, and the sums are
-// exact and independent of the order of the atomics: G^T is deterministic.  16 waves share the box.
+// exact and independent of the order of the atomics: G^T is deterministic.  12 waves share the box.
 // The box (its owned nodes and the one-node layer below them, which belongs
 // to the neighbouring bricks) is written to HBM in FP32 and adj_gather_kernel
 // adds the overlapping layers.
 // ---------------------------------------------------------------------------
-constexpr int ADJ_WAVES = 16;
+constexpr int ADJ_WAVES = 12;
 
 template <bool TAB>
-__global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(3, 3)))
 srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf)
 {
     __shared__ unsigned long long box[BOX_WORDS];
@@ -672,7 +689,7 @@ arc_build_kernel(Problem P)
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
                           hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(WAVES * WAVE);
+    dim3 grid(P.nbx * P.nby * P.nbz), block(FWD_WAVES * WAVE);
     const bool tab = P.tab_arc != nullptr;
     if (img_dtype == 0) {
         if (tab)
