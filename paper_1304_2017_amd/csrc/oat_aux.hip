@@ -34,6 +34,14 @@ __device__ __forceinline__ void store_val(void *p, size_t i, int dt, float v)
 
 constexpr int RED_WAVES = 4;
 
+// floor(x) as an integer in one instruction.
+__device__ __forceinline__ int cvt_floor(float x)
+{
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 }  // namespace
 
 // One workgroup per transducer: sum the (brick, transducer) windows of G in
@@ -213,27 +221,32 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
             const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
             const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
             const float ri = rsqrtf(r2);
-            const float dist = r2 * ri;
-            const float kt = fmaf(dist, P.sigma, -P.tau);
-            float kf = floorf(kt);
-            const float fr = kt - kf;
-            const float tol = 4e-6f * fabsf(kt) + 1e-5f;
+            const float kt = fmaf(r2 * ri, P.sigma, -P.tau);
+            float fr = __builtin_amdgcn_fractf(kt);
+            int ki = cvt_floor(kt);
+            // |FP32 kt - kt| <= 5e-7 (kt + tau) + 1e-6 (transducer position
+            // rounded to FP32, the difference, the squared norm, rsqrt to
+            // 1 ulp, the product): within twice that of an integer, decide
+            // floor(kt) in FP64 from the problem statement in physical units
+            // (no contraction in this file).
+            const float tol = fmaf(1e-6f, kt + P.tau, 1e-5f);
             if (fr < tol || fr > 1.f - tol) {
-                // Near an integer: decide floor(kt) in FP64 from the problem
-                // statement in physical units (no contraction in this file).
                 const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
                 const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
                 const double dd = sqrt(wx * wx + wy * wy + wz * wz);
                 const double kt64 = (dd / P.c0d - P.t0d) / P.dtd;
-                kf = (float)floor(kt64);
+                ki = (int)floor(kt64);
+                fr = kt - (float)ki;
             }
-            const float inv = ri / P.sigma;   // 1 / (kt + tau)
-            const float clo = fmaf(kf + 1.f + P.tau, inv, -1.5f);
-            const float chi = fmaf(-(kf + P.tau), inv, 1.5f);
-            int li = (int)kf - sklo[j];
+            // With fr = kt - k and inv = 1/(kt + tau) the two coefficients of
+            // Eq. (disfbp) are (1 - fr) inv - 1/2 and fr inv + 1/2, so the term
+            // is inv (p_k + fr (p_{k+1} - p_k)) + (p_{k+1} - p_k) / 2.
+            const float inv = ri * P.inv_sigma;
+            int li = ki - sklo[j];
             li = min(max(li, 0), win - 2);
             const float *pr = sp + j * win + li;
-            acc = fmaf(d.fbp_w, fmaf(clo, pr[0], chi * pr[1]), acc);
+            const float p0 = pr[0], dp = pr[1] - p0;
+            acc = fmaf(d.fbp_w, fmaf(inv, fmaf(fr, dp, p0), 0.5f * dp), acc);
         }
     }
     if (in) {

@@ -69,6 +69,7 @@ struct Problem {
     float d_coef;          // Gamma / (4 pi c0^2) / (2 dt)
     float fbp_scale;       // -1 / (pi Gamma c0 dt)
     float sigma;           // dx / (c0 dt)
+    float inv_sigma;       // c0 dt / dx
     float tau;             // t0 / dt
     // FP64 problem statement for FBP's floor decisions (same formula as the
     // problem statement: kt = (|r_n - r_q| / c0 - t0) / dt, r_n = r_0 + dx * n)

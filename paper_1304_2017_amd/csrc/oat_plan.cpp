@@ -359,6 +359,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.d_coef = (float)(g->gamma / (4.0 * M_PI * g->c0 * g->c0) / (2.0 * g->dt));
     P.fbp_scale = (float)(-1.0 / (M_PI * g->gamma * g->c0 * g->dt));
     P.sigma = (float)(dx / (g->c0 * g->dt));
+    P.inv_sigma = (float)(g->c0 * g->dt / dx);
     P.tau = (float)(g->t0 / g->dt);
     P.x0 = g->x0;
     P.y0 = g->y0;
