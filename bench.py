@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = non-packed FP32 VALU lane-ops/s.
 VALU_PEAK = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12   # bytes/s
 # Algorithmic FP32 VALU operations of one quadrature point of G or G^T
 # (position 6 FMA, cos/sin of the azimuth 2 transcendental = 8 issue slots,
 # floor 3, fraction 3, cell address 3, trilinear 7 lerps = 14, weighted add 2).
@@ -103,13 +104,89 @@ def cpu_baseline(geom, img, p_np, budget_s=20.0):
     ref.fbp(gd, p_np, voxels=vox)
     t_f = (time.perf_counter() - t) * N / vox.size
     total = t_h + t_ht + t_f
+    cores = ref.max_threads()
+    # The same on one thread, on a smaller sample (the paper's CPU code was sequential).
+    ref.set_threads(1)
+    try:
+        r1 = rows[:1]
+        t = time.perf_counter()
+        ref.project(gd, img, rows=r1)
+        t1_h = (time.perf_counter() - t) * Q
+        t = time.perf_counter()
+        ref.backproject(gd, p_np[r1], rows=r1)
+        t1_ht = (time.perf_counter() - t) * Q
+        v1 = vox[:2000]
+        t = time.perf_counter()
+        ref.fbp(gd, p_np, voxels=v1)
+        t1_f = (time.perf_counter() - t) * N / v1.size
+    finally:
+        ref.set_threads(cores)
     res = dict(value=3.0 * N * Q / total, unit="voxel-view updates/s",
-               cores=ref.max_threads(), kind="oracle",
+               cores=cores, kind="oracle",
                sample=(f"H on {rows.size} of {Q} transducers, H^T on {rows_t.size}, "
                        f"FBP on {vox.size} of {N} voxels; times scaled linearly to the "
                        f"full operators (extrapolated s: H {t_h:.0f}, H^T {t_ht:.0f}, "
-                       f"FBP {t_f:.0f})"))
+                       f"FBP {t_f:.0f}); one thread: H and H^T on 1 transducer, FBP on "
+                       f"2000 voxels (extrapolated s: H {t1_h:.0f}, H^T {t1_ht:.0f}, "
+                       f"FBP {t1_f:.0f})"),
+               value_1thread=3.0 * N * Q / (t1_h + t1_ht + t1_f))
     return res
+
+
+def time_op(fn, reps, warm=1):
+    """Median wall time (s) of fn over reps runs after warm runs, each
+    bracketed by HIP events on the current stream."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    return float(np.median(ts))
+
+
+def matrix(reps):
+    """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
+    transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
+    storage.  Prints a markdown table."""
+    import torch
+    from paper_1304_2017_amd import synth
+    from paper_1304_2017_amd.oat import Plan
+    cfgs = [("B: 256^3, 2048 hemisphere, K 1024", lambda: synth.config_large(0)),
+            ("E: 256^3, 8192 sphere, K 1024", lambda: synth.config_e(0)),
+            ("P: 210x210x440 at 0.14 mm, 64x90 rings, K 1022", lambda: synth.config_p(0))]
+    print("| workload | storage | H ms | H^T ms | FBP ms | H upd/s | H^T upd/s | FBP upd/s | "
+          "nominal HBM % (H) | plan s | arc table GB |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for name, make in cfgs:
+        geom, _, img = make()
+        t0 = time.perf_counter()
+        plan = Plan(geom, 0)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        st = plan.stats()
+        NQ = float(geom.n_vox) * geom.n_det
+        for dt, nbytes in ((torch.float32, 8), (torch.bfloat16, 4)):
+            x = torch.from_numpy(np.asarray(img, dtype=np.float32)).cuda().to(dt)
+            p = torch.empty(plan.data_shape, device="cuda", dtype=dt)
+            a = torch.empty(plan.image_shape, device="cuda", dtype=dt)
+            th = time_op(lambda: plan.project(x, out=p), reps)
+            tt = time_op(lambda: plan.backproject(p, out=a), reps)
+            tf = time_op(lambda: plan.fbp(p, out=a), reps)
+            print(f"| {name} | {'f32' if dt == torch.float32 else 'bf16'} | {th * 1e3:.1f} | "
+                  f"{tt * 1e3:.1f} | {tf * 1e3:.1f} | {NQ / th:.3e} | {NQ / tt:.3e} | {NQ / tf:.3e} | "
+                  f"{100 * NQ / th * nbytes / HBM_PEAK:.1f} | {plan_s:.2f} | "
+                  f"{st['arc_table_bytes'] / 1e9:.1f} |", flush=True)
+            del x, p, a
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
 
 
 def main():
@@ -120,6 +197,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--matrix", action="store_true",
+                    help="time H, H^T, FBP at three workloads, FP32 and BF16 (markdown table)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -130,6 +209,9 @@ def main():
     from paper_1304_2017_amd import synth
     from paper_1304_2017_amd.oat import Plan
 
+    if args.matrix:
+        matrix(max(args.steps, 3))
+        return
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")
     geom, ells, img = synth.config_large(0, dtype=np.float32)
@@ -189,10 +271,14 @@ def main():
     # one small data-side kernel, under 1% of its time).
     dom_name, dom_ms = ("srt_adj_kernel", t_ht) if t_ht >= t_h else ("srt_fwd_kernel", t_h)
     achieved = OPS_PER_POINT * pts / (dom_ms * 1e-3)
+    traffic = measured_traffic(dom_name)
     roof = dict(bound="alu", kernel=dom_name, achieved=achieved, peak=VALU_PEAK,
-                unit="VALU lane-op/s", frac=achieved / VALU_PEAK,
-                traffic=measured_traffic(dom_name),
+                unit="VALU lane-op/s", frac=achieved / VALU_PEAK, traffic=traffic,
                 ops_per_point=OPS_PER_POINT, points_per_launch=pts)
+    # HBM, two readings: what an untiled kernel would stream per update (8 bytes
+    # in FP32) at this rate, and the measured bytes of the dominant kernel.
+    hbm = dict(nominal_frac=value * 8.0 / HBM_PEAK,
+               measured_frac=(traffic / (dom_ms * 1e-3) / HBM_PEAK) if traffic else None)
     out = dict(metric="H/H^T voxel-view updates/s", value=value, unit="voxel-view updates/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -207,7 +293,7 @@ def main():
                         HT_updates_per_s=N * Q / (t_ht * 1e-3),
                         FBP_updates_per_s=N * Q / (t_f * 1e-3),
                         FBP_valu_frac=OPS_PER_FBP_UPDATE * N * Q / (t_f * 1e-3) / VALU_PEAK),
-               roofline=roof)
+               roofline=roof, hbm=hbm)
     if not args.no_cpu:
         log("[bench] oracle CPU baseline (bounded sample)")
         p_np = p.double().cpu().numpy()

@@ -393,6 +393,16 @@ long ref_count_points(const ref_geom *G, const int *qsel, int nsel)
     return total;
 }
 
+/* Thread count of the following calls (timing only; results do not depend on it). */
+void ref_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int ref_max_threads(void)
 {
 #ifdef _OPENMP

@@ -51,6 +51,8 @@ def lib():
         L.ref_count_points.argtypes = [G, _c_ip, ctypes.c_int]
         L.ref_count_points.restype = ctypes.c_long
         L.ref_max_threads.restype = ctypes.c_int
+        L.ref_set_threads.argtypes = [ctypes.c_int]
+        L.ref_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -173,3 +175,8 @@ def count_points(geom, rows=None):
 
 def max_threads():
     return int(lib().ref_max_threads())
+
+
+def set_threads(n: int):
+    """OpenMP threads of later calls (timing only)."""
+    lib().ref_set_threads(int(n))

@@ -274,3 +274,80 @@ def config_large(seed: int = 0, dtype=np.float32):
     rng = np.random.default_rng(seed)
     ells = random_ellipsoids(rng, 40, geom, 0.3, 3.0, 0.0, 1.0)
     return geom, ells, voxelise_ellipsoids(geom, ells, dtype=dtype)
+
+
+def blurred_ball(geom: Geometry, ball: Ball, sigma: float) -> np.ndarray:
+    """A uniform ball convolved with an isotropic Gaussian of standard
+    deviation sigma, sampled at the nodes: with r the distance to the centre,
+    A { [erf((a-r)/(s sqrt2)) + erf((a+r)/(s sqrt2))]/2
+        + s/(r sqrt(2 pi)) [exp(-(a+r)^2/(2 s^2)) - exp(-(a-r)^2/(2 s^2))] }."""
+    from scipy.special import erf
+    X, Y, Z = geom.node_coords()
+    r = np.sqrt((X - ball.centre[0]) ** 2 + (Y - ball.centre[1]) ** 2 + (Z - ball.centre[2]) ** 2)
+    a, s = ball.radius, sigma
+    rs = np.maximum(r, 1e-9)
+    v = 0.5 * (erf((a - r) / (s * math.sqrt(2.0))) + erf((a + r) / (s * math.sqrt(2.0))))
+    v += s / (rs * math.sqrt(2.0 * math.pi)) * (np.exp(-(a + r) ** 2 / (2 * s * s)) -
+                                                  np.exp(-(a - r) ** 2 / (2 * s * s)))
+    return ball.amplitude * v
+
+
+def config_c_geometry():
+    """192^3 nodes at 0.1 mm; 4096 transducers on a full Fibonacci sphere of
+    radius 40 mm; 1024 samples at 20 MHz (the PLS workload)."""
+    n, dx = 192, 0.1
+    o = centred_origin(n, dx)
+    return Geometry(n, n, n, dx, o, o, o, fibonacci_sphere(4096, 40.0), 1024, 0.05, 0.0, 1.5, 1.0,
+                    name="192^3 / 4096 transducers / 1024 samples")
+
+
+def config_c(seed: int = 0):
+    """config_c_geometry with data = analytic N-wave of 9 seeded uniform balls
+    (radii 0.5-2 mm in the central 8 mm) plus white noise of 2% of max|u|."""
+    geom = config_c_geometry()
+    rng = np.random.default_rng(seed)
+    balls = random_balls(rng, 9, 0.5, 2.0, 8.0)
+    u = gaussian_noise(rng, nwave_balls(geom, balls), 0.02)
+    return geom, balls, u
+
+
+def config_e_geometry():
+    """256^3 nodes at 0.1 mm; 8192 transducers on a full Fibonacci sphere of
+    radius 45 mm; 1024 samples at 20 MHz."""
+    n, dx = 256, 0.1
+    o = centred_origin(n, dx)
+    return Geometry(n, n, n, dx, o, o, o, fibonacci_sphere(8192, 45.0), 1024, 0.05, 0.0, 1.5, 1.0,
+                    name="256^3 / 8192 transducers / 1024 samples")
+
+
+def config_e(seed: int = 0, dtype=np.float32):
+    """config_e_geometry with 60 seeded ellipsoids as in config_large."""
+    geom = config_e_geometry()
+    rng = np.random.default_rng(seed)
+    ells = random_ellipsoids(rng, 60, geom, 0.3, 3.0, 0.0, 1.0)
+    return geom, ells, voxelise_ellipsoids(geom, ells, dtype=dtype)
+
+
+def config_p_geometry():
+    """The paper's simulation shape: 210 x 210 x 440 nodes at 0.14 mm; 64 rings
+    x 90 views on a sphere of radius 65 mm at theta_n = (n + 1/2) pi/64, patch
+    areas Rs^2 (pi/64)(2 pi/90) sin(theta); 1022 samples at 20 MHz from
+    t0 = 17.5 us; c0 = 1.54 mm/us."""
+    nx, ny, nz, dx = 210, 210, 440, 0.14
+    xyz, area = ring_layout(64, 90, 65.0, math.pi / 128.0, math.pi / 64.0)
+    return Geometry(nx, ny, nz, dx, centred_origin(nx, dx), centred_origin(ny, dx),
+                    centred_origin(nz, dx), xyz, 1022, 0.05, 17.5, 1.54, 1.0, area,
+                    name="210x210x440 / 64x90 ring views / 1022 samples")
+
+
+def config_p(seed: int = 0, dtype=np.float32):
+    """config_p_geometry with 9 seeded uniform balls (radii 1-4 mm, inside the
+    central 12 mm) blurred by a Gaussian of FWHM 0.77 mm."""
+    geom = config_p_geometry()
+    rng = np.random.default_rng(seed)
+    balls = random_balls(rng, 9, 1.0, 4.0, 12.0)
+    sigma = 0.77 / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    img = np.zeros(geom.shape)
+    for b in balls:
+        img += blurred_ball(geom, b, sigma)
+    return geom, balls, img.astype(dtype)
