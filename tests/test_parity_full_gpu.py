@@ -102,3 +102,56 @@ def test_full_size_fbp_sampled_voxels(large):
     e = rel(f[vox], want)
     _say(f"  rel {e:.3e}")
     assert e < 1e-5
+
+
+def test_sphere_8192_shapes_on_64_transducers():
+    """256^3 at 0.1 mm with every 128th of 8192 sphere transducers (45 mm):
+    the whole H, H^T and FBP outputs against the oracle."""
+    from paper_1304_2017_amd.oat import Plan
+    geom_full, _, img = synth.config_e(0)
+    geom = geom_full.with_detectors(np.arange(0, 8192, 128))
+    _say(f"[gpu-full] 256^3 / 64 of 8192 sphere transducers")
+    plan = Plan(geom, 0)
+    gd = geom.as_dict()
+    img64 = img.astype(np.float64)
+    p = plan.project(torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    p = p.double().cpu().numpy()
+    eh = rel(p, ref.project(gd, img64))
+    rng = np.random.default_rng(21)
+    y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32)
+    a = plan.backproject(torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    eht = rel(a.double().cpu().numpy(), ref.backproject(gd, y.astype(np.float64)))
+    pf = p.astype(np.float32)
+    f = plan.fbp(torch.from_numpy(pf).cuda())
+    torch.cuda.synchronize()
+    ef = rel(f.double().cpu().numpy(), ref.fbp(gd, pf.astype(np.float64)))
+    _say(f"  H rel {eh:.3e}  H^T rel {eht:.3e}  FBP rel {ef:.3e}")
+    assert eh < 1e-5 and eht < 1e-5 and ef < 1e-5
+
+
+def test_paper_shape_rows_and_voxels():
+    """210 x 210 x 440 at 0.14 mm, 64 x 90 ring views at 65 mm, t0 = 17.5 us:
+    G and H rows and sampled FBP voxels against the oracle."""
+    from paper_1304_2017_amd.oat import Plan
+    geom, _, img = synth.config_p(0)
+    _say("[gpu-full] paper shape 210x210x440 / 5760 ring views")
+    plan = Plan(geom, 0)
+    gd = geom.as_dict()
+    img64 = img.astype(np.float64)
+    rows = np.array([0, 1234, 2900, 5759], dtype=np.int32)
+    x = torch.from_numpy(img).cuda()
+    p = plan.project(x)
+    g = plan.project(x, srt_only=True)
+    torch.cuda.synchronize()
+    eg = rel(g.double().cpu().numpy()[rows], ref.srt(gd, img64, rows=rows))
+    ep = rel(p.double().cpu().numpy()[rows], ref.project(gd, img64, rows=rows))
+    pn = p.float()
+    f = plan.fbp(pn)
+    torch.cuda.synchronize()
+    vox = np.random.default_rng(22).choice(geom.n_vox, 2000, replace=False)
+    ef = rel(f.double().cpu().numpy().ravel()[vox],
+             ref.fbp(gd, pn.double().cpu().numpy(), voxels=vox))
+    _say(f"  G rel {eg:.3e}  H rel {ep:.3e}  FBP rel {ef:.3e}")
+    assert eg < 1e-6 and ep < 1e-5 and ef < 1e-5
