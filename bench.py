@@ -151,6 +151,44 @@ def time_op(fn, reps, warm=1):
     return float(np.median(ts))
 
 
+def pls_run(cfg, iters):
+    """PLS-TV (smoothed isotropic TV, nonlinear CG) from a = 0 on the 192^3 /
+    4096-transducer N-wave data (cfg "c") or on H a_true + 1% noise at the
+    256^3 / 8192-transducer workload (cfg "e"), with FP32 and BF16 operator
+    storage.  Prints one JSON line per storage type."""
+    import torch
+    from paper_1304_2017_amd import recon, synth
+    from paper_1304_2017_amd.oat import Plan
+    if cfg == "c":
+        geom, _, u_np = synth.config_c(0)
+        plan = Plan(geom, 0)
+        u = torch.from_numpy(u_np.astype(np.float32)).cuda()
+    else:
+        geom, _, img = synth.config_e(0)
+        plan = Plan(geom, 0)
+        clean = plan.project(torch.from_numpy(img).cuda())
+        torch.cuda.synchronize()
+        gen = torch.Generator(device="cuda").manual_seed(0)
+        u = clean + 0.01 * float(clean.abs().max()) * torch.randn(clean.shape, device="cuda",
+                                                                   generator=gen)
+    # eps: 1e-3 of the largest image value one expects (amplitudes <= 1);
+    # mu: the penalty of the zero image is 0.1% of ||u||^2.
+    eps = 1e-3
+    mu = 1e-3 * float(u.double().pow(2).sum()) / (geom.n_vox * eps)
+    for dt in (torch.float32, torch.bfloat16):
+        recon.pls_tv(plan, u, mu=mu, eps=eps, iters=1, storage=dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters, storage=dt, track=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps(dict(workload=geom.name, storage=str(dt).split(".")[-1], iters=iters,
+                              mu=mu, eps=eps, seconds=el, s_per_iter=el / iters,
+                              residuals=[round(v, 6) for v in res.residuals],
+                              objective=[float("%.8g" % v) for v in res.objective])), flush=True)
+    plan.close()
+
+
 def matrix(reps):
     """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
     transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
@@ -199,6 +237,9 @@ def main():
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
     ap.add_argument("--matrix", action="store_true",
                     help="time H, H^T, FBP at three workloads, FP32 and BF16 (markdown table)")
+    ap.add_argument("--pls", choices=["c", "e"], default=None,
+                    help="run PLS-TV at the 192^3/4096 (c) or 256^3/8192 (e) workload")
+    ap.add_argument("--iters", type=int, default=30, help="PLS-TV iterations (--pls)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -211,6 +252,9 @@ def main():
 
     if args.matrix:
         matrix(max(args.steps, 3))
+        return
+    if args.pls:
+        pls_run(args.pls, args.iters)
         return
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")

@@ -121,3 +121,150 @@ def test_pls_cg_matches_oracle_recursion(mu):
     obj = res.objective
     assert all(obj[i + 1] <= obj[i] * (1 + 1e-6) for i in range(len(obj) - 1))
     assert res.residuals[-1] < res.residuals[0]
+
+
+# ---------------------------------------------------------------------------
+# PLS with the smoothed total-variation penalty
+# ---------------------------------------------------------------------------
+def test_forward_diff_values_and_adjoint():
+    g = torch.Generator().manual_seed(3)
+    a = torch.randn((4, 5, 6), generator=g, dtype=torch.float64)
+    gx, gy, gz = recon.forward_diff(a)
+    # brute-force definition at a few nodes
+    assert float(gx[1, 2, 3]) == float(a[1, 2, 4] - a[1, 2, 3])
+    assert float(gy[3, 1, 0]) == float(a[3, 2, 0] - a[3, 1, 0])
+    assert float(gz[2, 4, 5]) == float(a[3, 4, 5] - a[2, 4, 5])
+    assert float(gx[0, 0, 5]) == 0.0 and float(gy[0, 4, 0]) == 0.0 and float(gz[3, 0, 0]) == 0.0
+    # <D a, (p, q, r)> = <a, D^T (p, q, r)>
+    p, q, r = (torch.randn((4, 5, 6), generator=g, dtype=torch.float64) for _ in range(3))
+    lhs = float((gx * p).sum() + (gy * q).sum() + (gz * r).sum())
+    rhs = float((a * recon.forward_diff_adj(p, q, r)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_tv_closed_forms_and_gradient():
+    eps = 0.05
+    c = torch.full((3, 4, 5), 2.0, dtype=torch.float64)
+    tv, grad, _ = recon.tv_eps(c, eps)
+    assert abs(tv - 60 * eps) < 1e-12 and float(grad.abs().max()) == 0.0
+    # ramp along x with slope s: |grad| = s except in the last x slice
+    s = 0.3
+    ramp = s * torch.arange(5, dtype=torch.float64)[None, None, :].expand(3, 4, 5).contiguous()
+    tv, _, _ = recon.tv_eps(ramp, eps)
+    want = 3 * 4 * (4 * np.sqrt(s * s + eps * eps) + eps)
+    assert abs(tv - want) < 1e-12 * want
+    # gradient against central differences
+    g = torch.Generator().manual_seed(4)
+    a = torch.randn((4, 4, 4), generator=g, dtype=torch.float64)
+    v = torch.randn((4, 4, 4), generator=g, dtype=torch.float64)
+    _, grad, _ = recon.tv_eps(a, eps)
+    h = 1e-6
+    fd = (recon.tv_eps(a + h * v, eps)[0] - recon.tv_eps(a - h * v, eps)[0]) / (2 * h)
+    an = float((grad * v).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+class _DensePlan:
+    """A dense random H on the CPU with the Plan interface (solver tests)."""
+
+    def __init__(self, shape, m, seed):
+        g = torch.Generator().manual_seed(seed)
+        self.image_shape = shape
+        self.data_shape = (m, 1)
+        self.A = torch.randn((m, int(np.prod(shape))), generator=g, dtype=torch.float64) / m ** 0.5
+
+    def project(self, x, out_dtype=None):
+        return (self.A @ x.double().reshape(-1)).reshape(self.data_shape).to(x.dtype)
+
+    def backproject(self, y, out_dtype=None):
+        return (self.A.T @ y.double().reshape(-1)).reshape(self.image_shape).to(y.dtype)
+
+
+def test_pls_tv_descends_to_the_minimiser():
+    from scipy.optimize import minimize
+    shape, mu, eps = (4, 5, 6), 0.05, 0.1
+    plan = _DensePlan(shape, 150, 5)
+    g = torch.Generator().manual_seed(6)
+    truth = torch.zeros(shape, dtype=torch.float64)
+    truth[1:3, 1:4, 2:5] = 1.0
+    u = (plan.A @ truth.reshape(-1) + 0.01 * torch.randn(150, generator=g, dtype=torch.float64))
+    u = u.reshape(150, 1)
+
+    def F(x):
+        t = torch.from_numpy(x).reshape(shape)
+        r = u.reshape(-1) - plan.A @ t.reshape(-1)
+        tv, grad, _ = recon.tv_eps(t, eps)
+        return float(r @ r) + mu * tv, (-2 * plan.A.T @ r + mu * grad.reshape(-1)).numpy()
+
+    opt = minimize(F, np.zeros(np.prod(shape)), jac=True, method="L-BFGS-B",
+                   options=dict(maxiter=5000, gtol=1e-12, ftol=1e-15))
+    res = recon.pls_tv(plan, u.float(), mu=mu, eps=eps, iters=300)
+    obj = res.objective
+    assert all(obj[i + 1] <= obj[i] * (1 + 1e-5) for i in range(len(obj) - 1))
+    got, _ = F(res.image.double().numpy().ravel())
+    assert got - opt.fun <= 1e-4 * opt.fun
+
+
+def _np_tv(a, eps):
+    """Independent numpy form of TV_eps and its gradient (forward differences
+    with zero across the far faces)."""
+    d = [np.zeros_like(a) for _ in range(3)]
+    d[0][:, :, :-1] = a[:, :, 1:] - a[:, :, :-1]
+    d[1][:, :-1, :] = a[:, 1:, :] - a[:, :-1, :]
+    d[2][:-1, :, :] = a[1:, :, :] - a[:-1, :, :]
+    s = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + eps * eps)
+    q = [di / s for di in d]
+    grad = np.zeros_like(a)
+    grad[:, :, 1:] += q[0][:, :, :-1]
+    grad[:, :, :-1] -= q[0][:, :, :-1]
+    grad[:, 1:, :] += q[1][:, :-1, :]
+    grad[:, :-1, :] -= q[1][:, :-1, :]
+    grad[1:, :, :] += q[2][:-1, :, :]
+    grad[:-1, :, :] -= q[2][:-1, :, :]
+    return s.sum(), grad, 1.0 / s
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_pls_tv_matches_oracle_recursion(storage):
+    from oracle import ref
+    from paper_1304_2017_amd.oat import Plan
+    _say(f"[gpu] PLS-TV {storage}")
+    geom, balls, _ = synth.config_small(1)
+    geom = geom.with_detectors(np.arange(0, 64, 2))
+    plan = Plan(geom, 0)
+    u = synth.nwave_balls(geom, balls).astype(np.float32).astype(np.float64)
+    mu, eps, iters = 2e-3, 1e-2, 5
+    dt = torch.float32 if storage == "f32" else torch.bfloat16
+    res = recon.pls_tv(plan, torch.from_numpy(u).float().cuda(), mu=mu, eps=eps, iters=iters,
+                       storage=dt)
+    gd = geom.as_dict()
+    H = lambda x: ref.project(gd, x)
+    HT = lambda y: ref.backproject(gd, y)
+    a = np.zeros(geom.shape)
+    r = u.copy()
+    tv, tg, w = _np_tv(a, eps)
+    g = -2 * HT(r) + mu * tg
+    d = -g
+    for _ in range(iters):
+        Hd = H(d)
+        dd = [np.zeros_like(d) for _ in range(3)]
+        dd[0][:, :, :-1] = np.diff(d, axis=2)
+        dd[1][:, :-1, :] = np.diff(d, axis=1)
+        dd[2][:-1, :, :] = np.diff(d, axis=0)
+        t = -np.vdot(g, d) / (2 * np.vdot(Hd, Hd) + mu * np.sum(w * (dd[0] ** 2 + dd[1] ** 2 + dd[2] ** 2)))
+        a = a + t * d
+        r = r - t * Hd
+        tv, tg, w = _np_tv(a, eps)
+        gn = -2 * HT(r) + mu * tg
+        beta = max(0.0, np.vdot(gn, gn - g) / np.vdot(g, g))
+        d = -gn + beta * d
+        if np.vdot(gn, d) >= 0:
+            d = -gn
+        g = gn
+    got = res.image.double().cpu().numpy()
+    e = float(np.linalg.norm(got - a) / np.linalg.norm(a))
+    _say(f"  iterate rel {e:.3e}; residuals {['%.4f' % v for v in res.residuals]}")
+    assert e < (1e-3 if storage == "f32" else 3e-2)
+    obj = res.objective
+    assert all(obj[i + 1] <= obj[i] * (1 + 1e-4) for i in range(len(obj) - 1))
