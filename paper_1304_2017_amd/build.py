@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liboat.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-DEVICE_SOURCES = ["oat_srt.hip", "oat_aux.hip"]
+DEVICE_SOURCES = ["oat_srt.hip", "oat_aux.hip", "oat_cnn.hip"]
 HOST_SOURCES = ["oat_plan.cpp"]
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -24,7 +24,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 def sources():
     return ([os.path.join(CSRC, f) for f in DEVICE_SOURCES + HOST_SOURCES]
             + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-            + [os.path.join(INCLUDE, "oat.h")])
+            + [os.path.join(INCLUDE, f) for f in ("oat.h", "oat_cnn.h")])
 
 
 def build(verbose: bool = False) -> str:

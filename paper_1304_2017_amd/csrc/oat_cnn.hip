@@ -1,0 +1,314 @@
+// Small 3-D convolution network on gfx950: "same" 3x3x3 convolutions with
+// 1 or 16 channels, their weight gradient, Adam and a mean-squared-error
+// loss, behind the C ABI of include/oat_cnn.h.  Used as a learned
+// preconditioner of the PLS reconstruction; activations stored in FP32 or
+// BF16, all sums in FP32 (weights) or FP64 (loss).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "oat.h"
+#include "oat_cnn.h"
+#include "oat_internal.hpp"
+
+namespace {
+
+constexpr int TT = 8;               // output tile edge
+constexpr int TI = TT + 2;          // input tile edge (one-voxel halo)
+constexpr int TI3 = TI * TI * TI;   // 1000
+constexpr int TT3 = TT * TT * TT;   // 512
+constexpr int NT = 512;             // threads per workgroup
+
+__device__ __forceinline__ float ldv(const void *p, size_t i, int dt)
+{
+    if (dt == 0) return ((const float *)p)[i];
+    return __uint_as_float(((unsigned)((const unsigned short *)p)[i]) << 16);
+}
+
+__device__ __forceinline__ void stv(void *p, size_t i, int dt, float v)
+{
+    if (dt == 0) {
+        ((float *)p)[i] = v;
+    } else {
+        unsigned u = __float_as_uint(v);
+        u += 0x7fffu + ((u >> 16) & 1u);     // round to nearest even
+        ((unsigned short *)p)[i] = (unsigned short)(u >> 16);
+    }
+}
+
+// Input tile of CI channels with a one-voxel halo (zero outside the volume).
+template <int CI>
+__device__ __forceinline__ void load_tile(float (*xs)[TI3], const void *x, int xdt, int D, int H,
+                                          int W, int x0, int y0, int z0)
+{
+    const size_t plane = (size_t)H * W, vol = plane * D;
+    for (int i = threadIdx.x; i < CI * TI3; i += NT) {
+        const int ci = i / TI3, r = i - ci * TI3;
+        const int zz = r / (TI * TI), yy = (r / TI) % TI, xx = r % TI;
+        const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+        float v = 0.f;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = ldv(x, ci * vol + gz * plane + (size_t)gy * W + gx, xdt);
+        xs[ci][r] = v;
+    }
+}
+
+// One output voxel per thread, all CO channels; 8^3 voxels per workgroup.
+template <int CI, int CO>
+__global__ void __launch_bounds__(NT) conv_fwd_kernel(const void *__restrict__ x, int xdt, int D,
+                                                      int H, int W, const float *__restrict__ wt,
+                                                      const float *__restrict__ bias,
+                                                      void *__restrict__ y, int ydt, int relu,
+                                                      const void *__restrict__ mask)
+{
+    __shared__ float xs[CI][TI3];
+    __shared__ float ws[CI * 27][CO];       // [ci][tap][co]: a broadcast read per (ci, tap)
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
+    for (int i = threadIdx.x; i < CI * 27 * CO; i += NT) {
+        const int co = i % CO, r = i / CO, ci = r / 27, t = r % 27;
+        ws[r][co] = wt[(co * CI + ci) * 27 + t];
+    }
+    load_tile<CI>(xs, x, xdt, D, H, W, x0, y0, z0);
+    __syncthreads();
+    const int lx = threadIdx.x % TT, ly = (threadIdx.x / TT) % TT, lz = threadIdx.x / (TT * TT);
+    float acc[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) acc[co] = bias ? bias[co] : 0.f;
+    for (int ci = 0; ci < CI; ++ci) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const float v = xs[ci][((lz + dz) * TI + ly + dy) * TI + lx + dx];
+            const float *wr = ws[ci * 27 + t];
+#pragma unroll
+            for (int co = 0; co < CO; ++co) acc[co] = fmaf(wr[co], v, acc[co]);
+        }
+    }
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= W || gy >= H || gz >= D) return;
+    const size_t plane = (size_t)H * W, vol = plane * D, off = gz * plane + (size_t)gy * W + gx;
+#pragma unroll
+    for (int co = 0; co < CO; ++co) {
+        float r = acc[co];
+        if (relu) r = fmaxf(r, 0.f);
+        if (mask && !(ldv(mask, co * vol + off, ydt) > 0.f)) r = 0.f;
+        stv(y, co * vol + off, ydt, r);
+    }
+}
+
+// Per-tile partial weight and bias gradients: part[tile][j], j = (co, ci, tap)
+// for j < CO*CI*27 and co for the CO entries after them.
+template <int CI, int CO>
+__global__ void __launch_bounds__(NT) conv_bwd_w_kernel(const void *__restrict__ x, int xdt,
+                                                        const void *__restrict__ dy, int dydt,
+                                                        int D, int H, int W, float *__restrict__ part)
+{
+    __shared__ float xs[CI][TI3];
+    __shared__ float gs[CO][TT3];
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
+    load_tile<CI>(xs, x, xdt, D, H, W, x0, y0, z0);
+    const size_t plane = (size_t)H * W, vol = plane * D;
+    for (int i = threadIdx.x; i < CO * TT3; i += NT) {
+        const int co = i / TT3, v = i - co * TT3;
+        const int gz = z0 + v / (TT * TT), gy = y0 + (v / TT) % TT, gx = x0 + v % TT;
+        float g = 0.f;
+        if (gz < D && gy < H && gx < W) g = ldv(dy, co * vol + gz * plane + (size_t)gy * W + gx, dydt);
+        gs[co][v] = g;
+    }
+    __syncthreads();
+    constexpr int NW = CO * CI * 27, NJ = NW + CO;
+    const size_t tile = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float *dst = part + tile * NJ;
+    for (int j = threadIdx.x; j < NJ; j += NT) {
+        float s = 0.f;
+        if (j < NW) {
+            const int co = j / (CI * 27), r = j % (CI * 27), ci = r / 27, t = r % 27;
+            const int dz = t / 9, dyy = (t / 3) % 3, dx = t % 3;
+            for (int v = 0; v < TT3; ++v) {
+                const int lz = v / (TT * TT), ly = (v / TT) % TT, lx = v % TT;
+                s = fmaf(gs[co][v], xs[ci][((lz + dz) * TI + ly + dyy) * TI + lx + dx], s);
+            }
+        } else {
+            const int co = j - NW;
+            for (int v = 0; v < TT3; ++v) s += gs[co][v];
+        }
+        dst[j] = s;
+    }
+}
+
+// Sum the per-tile partials in tile order (deterministic).
+__global__ void sum_tiles_kernel(const float *__restrict__ part, int ntiles, int nj, int nw,
+                                 float *__restrict__ dw, float *__restrict__ db)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nj) return;
+    float s = 0.f;
+    for (int t = 0; t < ntiles; ++t) s += part[(size_t)t * nj + j];
+    if (j < nw)
+        dw[j] = s;
+    else if (db)
+        db[j - nw] = s;
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+constexpr int MSE_BLOCKS = 1024;
+
+__global__ void mse_kernel(const void *__restrict__ y, int ydt, const void *__restrict__ t, int tdt,
+                           int64_t n, void *__restrict__ dy, double *__restrict__ part)
+{
+    __shared__ double ws[4];
+    double s = 0.0;
+    const float k = 2.f / (float)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = ldv(y, i, ydt) - ldv(t, i, tdt);
+        s += (double)d * (double)d;
+        stv(dy, i, ydt, k * d);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ void mse_sum_kernel(const double *__restrict__ part, int64_t n, float *__restrict__ loss)
+{
+    __shared__ double ws[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < MSE_BLOCKS; i += blockDim.x) s += part[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[0] = (float)(((ws[0] + ws[1]) + (ws[2] + ws[3])) / (double)n);
+}
+
+int cnn_fail(int code, const char *msg)
+{
+    oat::set_last_error(msg);
+    return code;
+}
+
+int launched(const char *who)
+{
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return OAT_OK;
+    oat::set_last_error((std::string(who) + ": " + hipGetErrorName(e)).c_str());
+    return OAT_ERR_DEVICE;
+}
+
+bool ch_ok(int c) { return c == 1 || c == 16; }
+bool dt_ok(int d) { return d == OAT_F32 || d == OAT_BF16; }
+
+dim3 tiles(int d, int h, int w) { return dim3((w + TT - 1) / TT, (h + TT - 1) / TT, (d + TT - 1) / TT); }
+
+}  // namespace
+
+extern "C" {
+
+int oat_conv3d_forward(const void *x, oat_dtype xdt, int c_in, int d, int h, int w,
+                       const float *weight, const float *bias, int c_out, void *y, oat_dtype ydt,
+                       int relu, const void *mask, void *stream)
+{
+    if (!x || !weight || !y) return cnn_fail(OAT_ERR_ARG, "oat_conv3d_forward: null pointer");
+    if (!ch_ok(c_in) || !ch_ok(c_out)) return cnn_fail(OAT_ERR_ARG, "channels must be 1 or 16");
+    if (d < 1 || h < 1 || w < 1) return cnn_fail(OAT_ERR_ARG, "volume sizes must be >= 1");
+    if (!dt_ok(xdt) || !dt_ok(ydt)) return cnn_fail(OAT_ERR_DTYPE, "unknown dtype");
+    if (x == y) return cnn_fail(OAT_ERR_ARG, "input and output alias");
+    hipStream_t s = (hipStream_t)stream;
+    dim3 g = tiles(d, h, w), b(NT);
+#define FWD(CI, CO)                                                                                 \
+    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), g, b, 0, s, x, (int)xdt, d, h, w, weight, bias, y, \
+                       (int)ydt, relu, mask)
+    if (c_in == 1 && c_out == 16) FWD(1, 16);
+    else if (c_in == 16 && c_out == 16) FWD(16, 16);
+    else if (c_in == 16 && c_out == 1) FWD(16, 1);
+    else FWD(1, 1);
+#undef FWD
+    return launched("oat_conv3d_forward");
+}
+
+size_t oat_conv3d_backward_weight_workspace(int c_in, int c_out, int d, int h, int w)
+{
+    if (!ch_ok(c_in) || !ch_ok(c_out) || d < 1 || h < 1 || w < 1) return 0;
+    dim3 g = tiles(d, h, w);
+    return sizeof(float) * (size_t)g.x * g.y * g.z * (size_t)(c_out * c_in * 27 + c_out);
+}
+
+int oat_conv3d_backward_weight(const void *x, oat_dtype xdt, const void *dy, oat_dtype dydt,
+                               int c_in, int c_out, int d, int h, int w, float *dweight,
+                               float *dbias, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!x || !dy || !dweight || !workspace)
+        return cnn_fail(OAT_ERR_ARG, "oat_conv3d_backward_weight: null pointer");
+    if (!ch_ok(c_in) || !ch_ok(c_out)) return cnn_fail(OAT_ERR_ARG, "channels must be 1 or 16");
+    if (d < 1 || h < 1 || w < 1) return cnn_fail(OAT_ERR_ARG, "volume sizes must be >= 1");
+    if (!dt_ok(xdt) || !dt_ok(dydt)) return cnn_fail(OAT_ERR_DTYPE, "unknown dtype");
+    if (workspace_bytes < oat_conv3d_backward_weight_workspace(c_in, c_out, d, h, w))
+        return cnn_fail(OAT_ERR_ARG, "oat_conv3d_backward_weight: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    dim3 g = tiles(d, h, w), b(NT);
+    float *part = (float *)workspace;
+#define BWD(CI, CO)                                                                                \
+    hipLaunchKernelGGL((conv_bwd_w_kernel<CI, CO>), g, b, 0, s, x, (int)xdt, dy, (int)dydt, d, h, w, \
+                       part)
+    if (c_in == 1 && c_out == 16) BWD(1, 16);
+    else if (c_in == 16 && c_out == 16) BWD(16, 16);
+    else if (c_in == 16 && c_out == 1) BWD(16, 1);
+    else BWD(1, 1);
+#undef BWD
+    int rc = launched("oat_conv3d_backward_weight");
+    if (rc) return rc;
+    const int nw = c_out * c_in * 27, nj = nw + c_out, ntiles = (int)(g.x * g.y * g.z);
+    hipLaunchKernelGGL(sum_tiles_kernel, dim3((nj + 255) / 256), dim3(256), 0, s, part, ntiles, nj,
+                       nw, dweight, dbias);
+    return launched("oat_conv3d_backward_weight");
+}
+
+int oat_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
+                  float beta1, float beta2, float eps, int step, void *stream)
+{
+    if (!param || !grad || !m || !v || n < 0 || step < 1)
+        return cnn_fail(OAT_ERR_ARG, "oat_adam_step: bad argument");
+    if (n == 0) return OAT_OK;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, param, grad, m,
+                       v, n, lr, beta1, beta2, eps, c1, c2);
+    return launched("oat_adam_step");
+}
+
+size_t oat_mse_workspace(void) { return sizeof(double) * MSE_BLOCKS; }
+
+int oat_mse(const void *y, oat_dtype ydt, const void *target, oat_dtype tdt, int64_t n, float *loss,
+            void *dy, void *workspace, void *stream)
+{
+    if (!y || !target || !loss || !dy || !workspace || n < 1)
+        return cnn_fail(OAT_ERR_ARG, "oat_mse: bad argument");
+    if (!dt_ok(ydt) || !dt_ok(tdt)) return cnn_fail(OAT_ERR_DTYPE, "unknown dtype");
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(mse_kernel, dim3(MSE_BLOCKS), dim3(256), 0, s, y, (int)ydt, target, (int)tdt, n,
+                       dy, (double *)workspace);
+    int rc = launched("oat_mse");
+    if (rc) return rc;
+    hipLaunchKernelGGL(mse_sum_kernel, dim3(1), dim3(256), 0, s, (const double *)workspace, n, loss);
+    return launched("oat_mse");
+}
+
+}  // extern "C"

@@ -92,6 +92,10 @@ struct Problem {
     int *tab_cnt;
 };
 
+// Sets the thread-local text returned by oat_last_error (defined with the
+// plan's entry points).
+void set_last_error(const char *msg);
+
 // Launchers (defined in the .hip files); dtype: 0 = f32, 1 = bf16.
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part,
                           int *klo, hipStream_t s);

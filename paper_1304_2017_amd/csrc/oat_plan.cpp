@@ -170,6 +170,8 @@ int build_arc_table(oat_plan *plan, int64_t budget)
 
 }  // namespace
 
+void oat::set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
+
 extern "C" {
 
 const char *oat_last_error(void) { return g_last_error.c_str(); }

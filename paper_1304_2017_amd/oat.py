@@ -28,7 +28,10 @@ OAT_BF16 = 1
 OAT_FLAG_SRT_ONLY = 1
 
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
-            "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats")
+            "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",
+            # include/oat_cnn.h
+            "oat_conv3d_forward", "oat_conv3d_backward_weight_workspace",
+            "oat_conv3d_backward_weight", "oat_adam_step", "oat_mse_workspace", "oat_mse")
 
 
 class OatError(RuntimeError):
@@ -82,6 +85,20 @@ def lib():
         L.oat_last_error.restype = ctypes.c_char_p
         L.oat_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
         L.oat_plan_stats.restype = ctypes.c_int
+        ci, sz, i64, f = ctypes.c_int, ctypes.c_size_t, ctypes.c_int64, ctypes.c_float
+        L.oat_conv3d_forward.argtypes = [vp, ci, ci, ci, ci, ci, vp, vp, ci, vp, ci, ci, vp, vp]
+        L.oat_conv3d_forward.restype = ci
+        L.oat_conv3d_backward_weight_workspace.argtypes = [ci, ci, ci, ci, ci]
+        L.oat_conv3d_backward_weight_workspace.restype = sz
+        L.oat_conv3d_backward_weight.argtypes = [vp, ci, vp, ci, ci, ci, ci, ci, ci, vp, vp, vp, sz,
+                                                 vp]
+        L.oat_conv3d_backward_weight.restype = ci
+        L.oat_adam_step.argtypes = [vp, vp, vp, vp, i64, f, f, f, f, ci, vp]
+        L.oat_adam_step.restype = ci
+        L.oat_mse_workspace.argtypes = []
+        L.oat_mse_workspace.restype = sz
+        L.oat_mse.argtypes = [vp, ci, vp, ci, i64, vp, vp, vp, vp]
+        L.oat_mse.restype = ci
         _lib = L
     return _lib
 

@@ -172,14 +172,9 @@ def tv_eps(a: torch.Tensor, eps: float):
     return float(s.double().sum()), grad, w
 
 
-def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
-           storage=torch.float32, track: bool = True) -> PLSResult:
-    """Nonlinear CG for min ||u - H a||^2 + mu TV_eps(a) from a = 0.
-    `storage` is the dtype of the operator inputs and outputs (FP32 or BF16);
-    iterates and residuals are kept in FP32 and every inner product in FP64."""
-    u = u.float().contiguous()
-    unorm = max(_dot(u, u) ** 0.5, 1e-300)
-
+def _pls_tv_steps(plan, u: torch.Tensor, mu: float, eps: float, iters: int, storage):
+    """The PLS-TV recursion; yields (a, g, ||u - H a||^2, TV_eps(a)) for the
+    start a = 0 and after every iteration."""
     def H(x):
         return plan.project(x.to(storage).contiguous(), out_dtype=storage).float()
 
@@ -191,10 +186,7 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
     tv, tg, w = tv_eps(a, eps)
     g = -2.0 * HT(r) + mu * tg
     d = -g
-    res = PLSResult(a)
-    if track:
-        res.residuals.append(1.0)
-        res.objective.append(unorm ** 2 + mu * tv)
+    yield a, g, _dot(r, r), tv
     gg = _dot(g, g)
     for _ in range(iters):
         Hd = H(d)
@@ -203,7 +195,7 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
         den = 2.0 * _dot(Hd, Hd) + mu * curv
         slope = _dot(g, d)
         if den <= 0.0 or slope >= 0.0:
-            break
+            return
         t = -slope / den
         a = a + t * d
         r = r - t * Hd
@@ -215,9 +207,29 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
         if _dot(g_new, d) >= 0.0:
             d = -g_new
         g, gg = g_new, gg_new
+        yield a, g, _dot(r, r), tv
+
+
+def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
+           storage=torch.float32, track: bool = True) -> PLSResult:
+    """Nonlinear CG for min ||u - H a||^2 + mu TV_eps(a) from a = 0.
+    `storage` is the dtype of the operator inputs and outputs (FP32 or BF16);
+    iterates and residuals are kept in FP32 and every inner product in FP64."""
+    u = u.float().contiguous()
+    unorm = max(_dot(u, u) ** 0.5, 1e-300)
+    res = PLSResult(None)
+    for a, _, rn, tv in _pls_tv_steps(plan, u, mu, eps, iters, storage):
+        res.image = a
         if track:
-            rn = _dot(r, r)
             res.residuals.append(rn ** 0.5 / unorm)
             res.objective.append(rn + mu * tv)
-    res.image = a
     return res
+
+
+def pls_tv_iterates(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 10,
+                    storage=torch.float32):
+    """(a_k, g_k) for k = 0 .. iters-1 of `pls_tv` (iterate and objective
+    gradient before step k)."""
+    u = u.float().contiguous()
+    for k, (a, g, _, _) in enumerate(_pls_tv_steps(plan, u, mu, eps, iters - 1, storage)):
+        yield a, g
