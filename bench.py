@@ -189,6 +189,72 @@ def pls_run(cfg, iters):
     plan.close()
 
 
+def learned_run(n_phantoms, epochs, iters):
+    """Time-to-residual of PLS-TV, plain vs learned preconditioner, at the
+    256^3 / 8192-sphere workload (data H a_true + 1% noise).  The network is
+    trained first (time reported separately) on (gradient, error) pairs from
+    10 plain iterations per seeded 128^3 / 1024-transducer phantom.  r* is the
+    plain residual after `iters` iterations; the learned run stops at r*.
+    Prints one JSON line."""
+    import torch
+    from paper_1304_2017_amd import precond, recon, synth
+    from paper_1304_2017_amd.oat import Plan
+    t0 = time.perf_counter()
+    gd, phantoms = synth.config_d_phantoms(n_phantoms, seed=1)
+    t_phantoms = time.perf_counter() - t0
+    log(f"[learned] {len(phantoms)} phantoms in {t_phantoms:.1f} s")
+    plan_d = Plan(gd, 0)
+    t0 = time.perf_counter()
+    pairs = precond.training_pairs(plan_d, [torch.from_numpy(p) for p in phantoms], iters=10)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    plan_d.close()
+    del phantoms
+    log(f"[learned] {len(pairs)} pairs in {t_pairs:.1f} s")
+    model = precond.Preconditioner(seed=0)
+    t0 = time.perf_counter()
+    tl = precond.train(model, pairs, epochs=epochs, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n = len(pairs)
+    loss_first, loss_last = float(np.mean(tl.loss[:n])), float(np.mean(tl.loss[-n:]))
+    log(f"[learned] trained {epochs} epochs in {t_train:.1f} s; loss {loss_first:.4f} -> {loss_last:.4f}")
+    del pairs
+    torch.cuda.empty_cache()
+
+    geom, _, img = synth.config_e(0)
+    plan = Plan(geom, 0)
+    clean = plan.project(torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    u = clean + 0.01 * float(clean.abs().max()) * torch.randn(clean.shape, device="cuda", generator=gen)
+    eps = 1e-3
+    mu = 1e-3 * float(u.double().pow(2).sum()) / (geom.n_vox * eps)
+    recon.pls_tv(plan, u, mu=mu, eps=eps, iters=1)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    r_star = plain.residuals[-1]
+    log(f"[learned] plain {iters} iterations {t_plain:.1f} s, r* = {r_star:.5f}")
+    t0 = time.perf_counter()
+    learned = precond.pls_tv_learned(plan, u, model, mu=mu, eps=eps, iters=iters, target=r_star)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    k_plain = next(i for i, r in enumerate(plain.residuals) if r <= r_star)
+    k_learned = next((i for i, r in enumerate(learned.residuals) if r <= r_star), None)
+    print(json.dumps(dict(
+        workload=geom.name, data="H a_true + 1% noise, 60 seeded ellipsoids", mu=mu, eps=eps,
+        r_star=r_star, plain=dict(iterations=k_plain, seconds=t_plain,
+                                  residuals=[round(v, 6) for v in plain.residuals]),
+        learned=dict(iterations=k_learned, seconds=t_learned, reached=k_learned is not None,
+                     residuals=[round(v, 6) for v in learned.residuals]),
+        training=dict(workload=gd.name, phantoms=n_phantoms, pairs=n, epochs=epochs,
+                      phantom_s=t_phantoms, pairs_s=t_pairs, train_s=t_train,
+                      loss_first_epoch=loss_first, loss_last_epoch=loss_last))), flush=True)
+
+
 def matrix(reps):
     """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
     transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
@@ -239,7 +305,11 @@ def main():
                     help="time H, H^T, FBP at three workloads, FP32 and BF16 (markdown table)")
     ap.add_argument("--pls", choices=["c", "e"], default=None,
                     help="run PLS-TV at the 192^3/4096 (c) or 256^3/8192 (e) workload")
-    ap.add_argument("--iters", type=int, default=30, help="PLS-TV iterations (--pls)")
+    ap.add_argument("--iters", type=int, default=30, help="PLS-TV iterations (--pls, --learned)")
+    ap.add_argument("--learned", action="store_true",
+                    help="train the learned preconditioner and time PLS-TV plain vs learned")
+    ap.add_argument("--phantoms", type=int, default=64, help="training phantoms (--learned)")
+    ap.add_argument("--epochs", type=int, default=5, help="training epochs (--learned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -255,6 +325,9 @@ def main():
         return
     if args.pls:
         pls_run(args.pls, args.iters)
+        return
+    if args.learned:
+        learned_run(args.phantoms, args.epochs, args.iters)
         return
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")

@@ -351,3 +351,24 @@ def config_p(seed: int = 0, dtype=np.float32):
     for b in balls:
         img += blurred_ball(geom, b, sigma)
     return geom, balls, img.astype(dtype)
+
+
+def config_d_geometry():
+    """128^3 nodes at 0.1 mm; 1024 transducers on a full Fibonacci sphere of
+    radius 25 mm; 512 samples at 20 MHz (the training workload)."""
+    n, dx = 128, 0.1
+    o = centred_origin(n, dx)
+    return Geometry(n, n, n, dx, o, o, o, fibonacci_sphere(1024, 25.0), 512, 0.05, 0.0, 1.5, 1.0,
+                    name="128^3 / 1024 transducers / 512 samples")
+
+
+def config_d_phantoms(count: int = 64, seed: int = 0, dtype=np.float32):
+    """`count` seeded phantoms on config_d_geometry, each 15-60 ellipsoids as
+    in config_large."""
+    geom = config_d_geometry()
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        ells = random_ellipsoids(rng, int(rng.integers(15, 61)), geom, 0.3, 3.0, 0.0, 1.0)
+        out.append(voxelise_ellipsoids(geom, ells, dtype=dtype))
+    return geom, out
