@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(FBP_TX *FBP_TY)
 fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int win, int chunk)
 {
     __shared__ float sp[FBP_LDS];
-    __shared__ int sklo[FBP_LDS / 8];
+    __shared__ int2 sklo[FBP_LDS / 8];    // first staged sample, FP64-decision tolerance
     const int tx = threadIdx.x % FBP_TX, ty = threadIdx.x / FBP_TX;
     const int ix = blockIdx.x * FBP_TX + tx, iy = blockIdx.y * FBP_TY + ty, iz = blockIdx.z;
     const bool in = ix < P.nx && iy < P.ny;
@@ -201,12 +201,17 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
             const DetRec &d = P.det[q0 + j];
             const float vx = cx - d.uqf[0], vy = cy - d.uqf[1], vz = fz - d.uqf[2];
             const float dc = sqrtf(vx * vx + vy * vy + vz * vz);
-            sklo[j] = (int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2;
+            // |FP32 kt - kt| <= 5e-7 (kt + tau) + 1e-6 (transducer position
+            // rounded to FP32, the difference, the squared norm, rsqrt to
+            // 1 ulp, the product); the tolerance is twice that at the tile's
+            // largest kt.
+            const float tol = fmaf(1e-6f, (dc + hd + 1.f) * P.sigma, 1e-5f);
+            sklo[j] = make_int2((int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2, __float_as_int(tol));
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nq * win; t += blockDim.x) {
             const int j = t / win, i = t % win;
-            const int k = sklo[j] + i;
+            const int k = sklo[j].x + i;
             float v = 0.f;
             if (k >= 0 && k < K) {
                 const size_t idx = (size_t)(q0 + j) * K + k;
@@ -220,16 +225,16 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
             const DetRec &d = P.det[q0 + j];
             const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
             const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
-            const float ri = rsqrtf(r2);
+            // r2 is hundreds of cells squared: the hardware rsqrt (1 ulp) needs
+            // no denormal scaling.
+            const float ri = __builtin_amdgcn_rsqf(r2);
             const float kt = fmaf(r2 * ri, P.sigma, -P.tau);
             float fr = __builtin_amdgcn_fractf(kt);
             int ki = cvt_floor(kt);
-            // |FP32 kt - kt| <= 5e-7 (kt + tau) + 1e-6 (transducer position
-            // rounded to FP32, the difference, the squared norm, rsqrt to
-            // 1 ulp, the product): within twice that of an integer, decide
-            // floor(kt) in FP64 from the problem statement in physical units
-            // (no contraction in this file).
-            const float tol = fmaf(1e-6f, kt + P.tau, 1e-5f);
+            // Within the tolerance of an integer, decide floor(kt) in FP64 from
+            // the problem statement in physical units (no contraction here).
+            const int2 sk = sklo[j];
+            const float tol = __int_as_float(sk.y);
             if (fr < tol || fr > 1.f - tol) {
                 const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
                 const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
@@ -242,7 +247,7 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
             // Eq. (disfbp) are (1 - fr) inv - 1/2 and fr inv + 1/2, so the term
             // is inv (p_k + fr (p_{k+1} - p_k)) + (p_{k+1} - p_k) / 2.
             const float inv = ri * P.inv_sigma;
-            int li = ki - sklo[j];
+            int li = ki - sk.x;
             li = min(max(li, 0), win - 2);
             const float *pr = sp + j * win + li;
             const float p0 = pr[0], dp = pr[1] - p0;
