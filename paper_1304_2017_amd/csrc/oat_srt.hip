@@ -206,7 +206,8 @@ struct BuildLds {
 template <bool ADJ, bool TAB, int MODE, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
                                           const int hi[3], WaveLds &W, BuildLds *B,
-                                          const float *gp, float gscale, int &klo_out, Fn &&fn)
+                                          const float *gp, float gscale, float gscale2,
+                                          int &klo_out, Fn &&fn)
 {
     constexpr bool READ_RUNS = TAB || MODE == WALK_FILL;
     const DetRec &d = P.det[q];
@@ -342,7 +343,8 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                     }
                 }
             }
-            if (ADJ && v1 && items_all > 0) w = w * (gp[(size_t)q * P.nt + kr] * gscale);
+            if (ADJ && v1 && items_all > 0)
+                w = w * ((gp[(size_t)q * P.nt + kr] * gscale) * gscale2);
             if (MODE != WALK_POINTS) {
                 B->rmin[lane] = 0x7fffffff;
                 B->rmax[lane] = -1;
@@ -568,7 +570,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
             }
         };
         walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
-                                           1.f, klo, gather);
+                                           1.f, 1.f, klo, gather);
         if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
@@ -613,11 +615,14 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf
     __syncthreads();
     m = 0.f;
     for (int w = 0; w < ADJ_WAVES; ++w) m = fmaxf(m, wmax[w]);
-    const float bound = m * P.w_max;
+    // 2^s = 2^(s/2) 2^(s - s/2): two normal FP32 factors (|s| <= 252) cover
+    // every finite FP32 |g'|, denormals included, for ring weights between
+    // 2^-70 and 2^90.
+    const double bound = (double)m * (double)P.w_max;
     int e = 0;
-    (void)frexpf(bound, &e);                  // bound < 2^e
-    const int sh = bound > 0.f ? min(max(30 - e, -100), 100) : 0;
-    const float gscale = ldexpf(1.f, sh);
+    (void)frexp(bound, &e);                   // bound < 2^e
+    const int sh = (bound > 0.0 && bound <= 1e300) ? min(max(30 - e, -252), 252) : 0;
+    const float gscale = ldexpf(1.f, sh / 2), gscale2 = ldexpf(1.f, sh - sh / 2);
     const double unscale = ldexp(1.0, -sh);
 
     const int wave = threadIdx.x / WAVE;
@@ -652,7 +657,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf
             if (c.own) scatter1(c, wv);
         };
         walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp,
-                                          gscale, klo, scatter);
+                                          gscale, gscale2, klo, scatter);
     }
     __syncthreads();
     float *dst = bbuf + (size_t)b * BOX3;
@@ -682,7 +687,7 @@ arc_build_kernel(Problem P)
     for (int q = wave; q < P.nq; q += WAVES) {
         int klo = 0;
         walk_unit<false, false, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
-                                      nullptr, 1.f, klo, none);
+                                      nullptr, 1.f, 1.f, klo, none);
     }
 }
 

@@ -290,3 +290,24 @@ def test_row_selection_matches_full():
     rows = np.array([5, 40, 63])
     full = ref.project(gd, img)
     np.testing.assert_array_equal(ref.project(gd, img, rows=rows), full[rows])
+
+
+@pytest.mark.parametrize("make", ["config_small", "config_large_geometry", "config_c_geometry",
+                                  "config_d_geometry", "config_e_geometry", "config_p_geometry"])
+def test_workloads_satisfy_the_geometry_assumptions(make):
+    """Every synthetic workload keeps its transducers outside the sphere that
+    holds the image support; the paper-sized ones record every shell that can
+    reach the support."""
+    g = getattr(synth, make)()
+    geom = g[0] if isinstance(g, tuple) else g
+    R = ref.support_radius(geom.as_dict())
+    d = np.linalg.norm(geom.det_xyz, axis=1)
+    assert d.min() > R
+    t_last = geom.t0 + (geom.n_t - 1) * geom.dt
+    assert geom.c0 * geom.t0 <= max(d.min() - R, 0.0) + 1e-9
+    if make == "config_small":
+        # the small case ends its record before the far side of the support,
+        # so the parity tests also cover shells clipped by the time window
+        assert d.min() + R > geom.c0 * t_last > d.max()
+    else:
+        assert geom.c0 * t_last >= d.max() + R

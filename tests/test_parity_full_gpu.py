@@ -155,3 +155,29 @@ def test_paper_shape_rows_and_voxels():
              ref.fbp(gd, pn.double().cpu().numpy(), voxels=vox))
     _say(f"  G rel {eg:.3e}  H rel {ep:.3e}  FBP rel {ef:.3e}")
     assert eg < 1e-6 and ep < 1e-5 and ef < 1e-5
+
+
+def test_full_size_bf16_backproject_and_fbp(large):
+    """BF16 storage for H^T and FBP at full size (oracle fed the same
+    BF16-rounded inputs); H^T repeats bit for bit."""
+    geom, img, plan = large
+    rows = np.array([17, 1024], dtype=np.int32)
+    rng = np.random.default_rng(13)
+    y = np.zeros((geom.n_det, geom.n_t), dtype=np.float32)
+    y[rows] = rng.normal(size=(rows.size, geom.n_t)).astype(np.float32)
+    yb = torch.from_numpy(y).to(torch.bfloat16).cuda()
+    a = plan.backproject(yb, out_dtype=torch.bfloat16)
+    a2 = plan.backproject(yb, out_dtype=torch.bfloat16)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a2)
+    y_b = yb.double().cpu().numpy()
+    e = rel(a.double().cpu().numpy(), ref.backproject(geom.as_dict(), y_b[rows], rows=rows))
+    p = torch.from_numpy(rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32))
+    pb = p.to(torch.bfloat16).cuda()
+    f = plan.fbp(pb, out_dtype=torch.bfloat16)
+    torch.cuda.synchronize()
+    vox = rng.choice(geom.n_vox, 2000, replace=False)
+    ef = rel(f.double().cpu().numpy().ravel()[vox],
+             ref.fbp(geom.as_dict(), pb.double().cpu().numpy(), voxels=vox))
+    _say(f"[gpu-full] BF16 H^T rel {e:.3e}  FBP rel {ef:.3e}")
+    assert e < 2e-3 and ef < 2e-3

@@ -52,10 +52,20 @@ def Plan():
     return P
 
 
+def _small_case(seed, Plan):
+    geom, balls, img = synth.config_small(seed)
+    return geom, balls, img, Plan(geom, 0), seed
+
+
 @pytest.fixture(scope="module", params=[0, 1, 2, 3, 4])
 def small(request, Plan):
-    geom, balls, img = synth.config_small(request.param)
-    return geom, balls, img, Plan(geom, 0), request.param
+    return _small_case(request.param, Plan)
+
+
+@pytest.fixture(scope="module", params=[0, 1])
+def small_bf16(request, Plan):
+    """Two seeds suffice for the BF16 storage checks."""
+    return _small_case(request.param, Plan)
 
 
 def test_srt_only_matches_oracle(small):
@@ -117,10 +127,8 @@ def test_adjoint_identity_on_gpu(small):
     assert abs(lhs - rhs) <= 1e-5 * scale
 
 
-def test_bf16_storage(small):
-    geom, balls, img, plan, seed = small
-    if seed > 1:
-        pytest.skip("two seeds suffice for BF16")
+def test_bf16_storage(small_bf16):
+    geom, balls, img, plan, seed = small_bf16
     _say(f"[gpu] BF16 32^3 seed {seed}")
     gd = geom.as_dict()
     img_b = _bf16_round(img)
@@ -194,12 +202,10 @@ def test_zero_inputs_and_overwrite(Plan):
     assert float(out_i.abs().max()) == 0.0
 
 
-def test_repeat_runs(small):
+def test_repeat_runs(Plan):
     """H sums its brick partials in a fixed order and H^T accumulates exact
     fixed-point integers (order-independent), so both are bit-stable."""
-    geom, _, img, plan, seed = small
-    if seed:
-        pytest.skip("one seed suffices")
+    geom, _, img, plan, seed = _small_case(0, Plan)
     _say("[gpu] repeat runs")
     x = _t(img)
     a = plan.project(x).clone()
@@ -237,3 +243,21 @@ def test_arc_table_and_arc_bounds_agree(seed, Plan):
     e = rel(at, an)
     _say(f"  G^T table vs bounds rel {e:.3e}")
     assert e < 1e-6
+
+
+def test_backproject_with_wide_dynamic_range(Plan):
+    """The fixed-point scale of G^T follows the largest |D^T y|: one
+    transducer 1e4 times louder than the others, and data of magnitude 1e-30,
+    still match the oracle."""
+    geom = synth.config_small(0)[0]
+    plan = Plan(geom, 0)
+    gd = geom.as_dict()
+    rng = np.random.default_rng(31)
+    y = rng.normal(size=(geom.n_det, geom.n_t))
+    y[5] *= 1e4
+    y = y.astype(np.float32).astype(np.float64)
+    e = rel(_np(plan.backproject(_t(y))), ref.backproject(gd, y))
+    tiny = (rng.normal(size=(geom.n_det, geom.n_t)) * 1e-30).astype(np.float32).astype(np.float64)
+    e2 = rel(_np(plan.backproject(_t(tiny))), ref.backproject(gd, tiny))
+    _say(f"[gpu] H^T loud transducer rel {e:.3e}; 1e-30 data rel {e2:.3e}")
+    assert e < 1e-5 and e2 < 1e-5
