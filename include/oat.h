@@ -167,8 +167,10 @@ const char *oat_last_error(void);
  * stats[3] = shell window per (brick, transducer),
  * stats[4] = bytes of device workspace, stats[5] = bytes of device tables,
  * stats[6] = bytes of the arc table (0: none), stats[7] = its ring entries,
- * stats[8] = its build time in microseconds.
- * n = capacity of stats (at most 9 are written); returns OAT_OK. */
+ * stats[8] = its build time in microseconds,
+ * stats[9] = time of the G^T calibration pass in microseconds (the plan runs
+ * G^T's walk once with unit data to bound its fixed-point sums).
+ * n = capacity of stats (at most 10 are written); returns OAT_OK. */
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n);
 
 #ifdef __cplusplus

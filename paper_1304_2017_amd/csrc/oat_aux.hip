@@ -97,20 +97,21 @@ srt_reduce_kernel(Problem P, const float *__restrict__ part, const int *__restri
 }
 
 // g'[q,k] = coef (y_{k-1} - y_{k+1}) / t_k  (0 where t_k <= 0; y_{-1} = y_K = 0),
-// or a plain FP32 copy of y when apply_dt == 0.  Each workgroup also writes
-// to P.gp_max[blockIdx.x] the largest |g'| among its samples whose shell can
-// reach the image support (G^T sets its fixed-point scale from these; the
-// other samples meet no quadrature point).
+// or a plain FP32 copy of y when apply_dt == 0.  One workgroup per transducer
+// q, which also writes P.gp_rowmax[q], the largest |g'| among its samples
+// whose shell can reach the image support (G^T sets its fixed-point scales
+// from these; the other samples meet no quadrature point).
 __global__ void __launch_bounds__(256) diff_adj_kernel(Problem P, const void *__restrict__ y,
                                                        int y_dt, float *__restrict__ gp,
                                                        int apply_dt)
 {
     __shared__ float wmax[4];
-    const size_t total = (size_t)P.nq * P.nt;
+    const int q = blockIdx.x;
+    const size_t row = (size_t)q * P.nt;
+    const float dq = P.det[q].dist;
     float m = 0.f;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(i % P.nt);
+    for (int k = threadIdx.x; k < P.nt; k += blockDim.x) {
+        const size_t i = row + k;
         float v;
         if (apply_dt) {
             float t = fmaf((float)k, P.dt, P.t0);
@@ -122,14 +123,13 @@ __global__ void __launch_bounds__(256) diff_adj_kernel(Problem P, const void *__
         }
         gp[i] = v;
         const float rho = fmaf((float)k, P.rho_step, P.rho0);
-        const float dq = P.det[i / P.nt].dist;
         if (fabsf(rho - dq) <= P.r_sup + 2.f) m = fmaxf(m, fabsf(v));
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0)
-        P.gp_max[blockIdx.x] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        P.gp_rowmax[q] = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
 }
 
 // G^T output.  A brick's box holds the nodes of its cells, one node below
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) diff_adj_kernel(Problem P, const void *__
 // deterministic.
 template <int IMG_DT>
 __global__ void __launch_bounds__(256)
-adj_gather_kernel(Problem P, const float *__restrict__ bbuf, void *__restrict__ img)
+adj_gather_kernel(Problem P, const double *__restrict__ acc, void *__restrict__ img)
 {
     const int x = blockIdx.x * 64 + threadIdx.x % 64;
     const int y = blockIdx.y * 4 + threadIdx.x / 64;
@@ -158,14 +158,14 @@ adj_gather_kernel(Problem P, const float *__restrict__ bbuf, void *__restrict__ 
         off[a][1] = 0;
         cnt[a] = (r == BRICK - 1 && b0 + 1 < nb[a]) ? 2 : 1;
     }
-    double acc = 0.0;
+    double sum = 0.0;
     for (int iz = 0; iz < cnt[2]; ++iz)
         for (int iy = 0; iy < cnt[1]; ++iy)
             for (int ix = 0; ix < cnt[0]; ++ix) {
                 const size_t b = ((size_t)bi[2][iz] * P.nby + bi[1][iy]) * P.nbx + bi[0][ix];
-                acc += (double)bbuf[b * BOX3 + (off[2][iz] * BOX + off[1][iy]) * BOX + off[0][ix]];
+                sum += acc[b * BOX3 + (off[2][iz] * BOX + off[1][iy]) * BOX + off[0][ix]];
             }
-    store_val(img, ((size_t)z * P.ny + y) * P.nx + x, IMG_DT, (float)acc);
+    store_val(img, ((size_t)z * P.ny + y) * P.nx + x, IMG_DT, (float)sum);
 }
 
 // FBP, Eq. (disfbp): one thread per voxel of a 16 x 16 x 1 tile, loop over
@@ -276,20 +276,18 @@ hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo
 hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp, int apply_dt,
                            hipStream_t s)
 {
-    // Always DIFF_BLOCKS workgroups: G^T reads that many maxima.
-    hipLaunchKernelGGL(diff_adj_kernel, dim3(DIFF_BLOCKS), dim3(256), 0, s, P, y, y_dtype, gp,
-                       apply_dt);
+    hipLaunchKernelGGL(diff_adj_kernel, dim3(P.nq), dim3(256), 0, s, P, y, y_dtype, gp, apply_dt);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_gather(const Problem &P, const float *bbuf, void *img, int img_dtype,
+hipError_t launch_adj_gather(const Problem &P, const double *acc, void *img, int img_dtype,
                              hipStream_t s)
 {
     dim3 grid((P.nx + 63) / 64, (P.ny + 3) / 4, P.nz), block(256);
     if (img_dtype == 0)
-        hipLaunchKernelGGL(adj_gather_kernel<0>, grid, block, 0, s, P, bbuf, img);
+        hipLaunchKernelGGL(adj_gather_kernel<0>, grid, block, 0, s, P, acc, img);
     else
-        hipLaunchKernelGGL(adj_gather_kernel<1>, grid, block, 0, s, P, bbuf, img);
+        hipLaunchKernelGGL(adj_gather_kernel<1>, grid, block, 0, s, P, acc, img);
     return hipGetLastError();
 }
 

@@ -19,7 +19,16 @@ constexpr int BOX3 = BOX * BOX * BOX;          // dense box in HBM (G^T brick ou
 constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
 constexpr int WAVE = 64;
 constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
-constexpr int DIFF_BLOCKS = 1024;            // workgroups of the D^T kernel (one max each)
+// G^T: ADJ_WAVES waves per brick workgroup; transducers in windows of
+// ADJ_WINDOW = ADJ_ROUNDS transducers per wave, one fixed-point scale and one
+// flush of the LDS box per window.
+constexpr int ADJ_WAVES = 12;
+#ifndef OAT_ADJ_ROUNDS
+#define OAT_ADJ_ROUNDS 4
+#endif
+constexpr int ADJ_ROUNDS = OAT_ADJ_ROUNDS;
+constexpr int ADJ_WINDOW = ADJ_WAVES * ADJ_ROUNDS;
+__host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).
 struct alignas(16) DetRec {
@@ -76,7 +85,8 @@ struct Problem {
     double x0, y0, z0, dxd, c0d, t0d, dtd;
     float w_max;           // largest ring weight
     float r_sup;           // radius of the image support sphere / dx
-    float *gp_max;         // [DIFF_BLOCKS] per-block max |g'| written by the D^T kernel
+    float *gp_rowmax;      // [nq] max |g'| per transducer over reachable samples (D^T kernel)
+    const float *adj_r;    // [bricks][adj_windows(nq)] G^T calibration: max node sum of psi w
     const DetRec *det;
     const ShellRec *shell;
     const RingRec *ring;
@@ -106,9 +116,11 @@ hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo
                              void *out, int out_dtype, int apply_d, hipStream_t s);
 hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp,
                            int apply_dt, hipStream_t s);
-hipError_t launch_srt_adj(const Problem &P, const float *gp, float *bbuf, void *img,
+hipError_t launch_srt_adj(const Problem &P, const float *gp, double *acc, void *img,
                           int img_dtype, hipStream_t s);
-hipError_t launch_adj_gather(const Problem &P, const float *bbuf, void *img, int img_dtype,
+// Writes P.adj_r's values to r (the plan calls it once, with P.adj_r unset).
+hipError_t launch_adj_calibrate(const Problem &P, float *r, hipStream_t s);
+hipError_t launch_adj_gather(const Problem &P, const double *acc, void *img, int img_dtype,
                              hipStream_t s);
 hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img,
                       int img_dtype, hipStream_t s);

@@ -64,12 +64,13 @@ struct oat_plan {
     float *d_part = nullptr;     // G windows [bricks][Q][window]
     int *d_klo = nullptr;        // [bricks][Q]
     float *d_gp = nullptr;       // D^T y  [Q][K]
-    float *d_bbuf = nullptr;     // G^T brick boxes [bricks][BOX^3]
-    float *d_gpmax = nullptr;    // [DIFF_BLOCKS] per-block max |D^T y|
+    double *d_acc = nullptr;     // G^T brick node sums [bricks][BOX^3]
+    float *d_rowmax = nullptr;   // [Q] max reachable |D^T y| per transducer
+    float *d_adjr = nullptr;     // [bricks][windows] G^T calibration
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
-    int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0;
+    int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0, calib_us = 0;
     int max_nj = 0, max_rings = 0;
     float w_max = 0.f;
     int64_t n_rings = 0;
@@ -183,8 +184,8 @@ void oat_plan_destroy(oat_plan *plan)
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(plan->device);
     void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
-                    plan->d_klo, plan->d_gp, plan->d_bbuf, plan->d_gpmax, plan->d_tab_off,
-                    plan->d_tab_run, plan->d_tab_arc};
+                    plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
+                    plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -390,15 +391,18 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     size_t part_b = sizeof(float) * (size_t)nbricks * Q * P.window;
     size_t klo_b = sizeof(int) * (size_t)nbricks * Q;
     size_t gp_b = sizeof(float) * (size_t)Q * K;
-    size_t bbuf_b = sizeof(float) * (size_t)nbricks * BOX3;        // G^T brick boxes
+    size_t acc_b = sizeof(double) * (size_t)nbricks * BOX3;        // G^T brick node sums
+    size_t rowmax_b = sizeof(float) * (size_t)Q;
+    size_t adjr_b = sizeof(float) * (size_t)nbricks * adj_windows(Q);
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
         (e = alloc((void **)&plan->d_part, part_b, "partials")) != hipSuccess ||
         (e = alloc((void **)&plan->d_klo, klo_b, "klo")) != hipSuccess ||
         (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_bbuf, bbuf_b, "brick boxes")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_gpmax, sizeof(float) * DIFF_BLOCKS, "gp max")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_acc, acc_b, "brick node sums")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_rowmax, rowmax_b, "gp row max")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_adjr, adjr_b, "G^T calibration")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -415,13 +419,14 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.det = plan->d_det;
     P.shell = plan->d_shell;
     P.ring = plan->d_ring;
-    P.gp_max = plan->d_gpmax;
+    P.gp_rowmax = plan->d_rowmax;
+    P.adj_r = nullptr;
     P.tab_off = nullptr;
     P.tab_run = nullptr;
     P.tab_arc = nullptr;
     P.tab_cnt = nullptr;
-    plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + bbuf_b);
-    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b);
+    plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + acc_b + rowmax_b);
+    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b);
     if (table_budget != 0) {
         int code = build_arc_table(plan, table_budget);
         if (code != OAT_OK) {
@@ -429,6 +434,22 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
             (void)hipSetDevice(prev);
             return code;
         }
+    }
+    {
+        // G^T calibration: per (brick, transducer window) the largest node
+        // sum of psi w, which bounds the fixed-point fields of every call.
+        const auto t0 = std::chrono::steady_clock::now();
+        e = launch_adj_calibrate(plan->P, plan->d_adjr, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            int code = fail_hip(e, "oat_plan_create: G^T calibration");
+            oat_plan_destroy(plan);
+            (void)hipSetDevice(prev);
+            return code;
+        }
+        plan->P.adj_r = plan->d_adjr;
+        plan->calib_us = (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(
+                             std::chrono::steady_clock::now() - t0).count();
     }
     (void)hipSetDevice(prev);
     *out = plan;
@@ -438,10 +459,10 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n)
 {
     if (!plan || !stats || n < 0) return fail(OAT_ERR_ARG, "oat_plan_stats: null argument");
-    int64_t v[9] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
-                    plan->P.window, plan->ws_bytes, plan->table_bytes, plan->tab_bytes,
-                    plan->tab_entries, plan->tab_build_us};
-    for (int i = 0; i < n && i < 9; ++i) stats[i] = v[i];
+    int64_t v[10] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
+                     plan->P.window, plan->ws_bytes, plan->table_bytes, plan->tab_bytes,
+                     plan->tab_entries, plan->tab_build_us, plan->calib_us};
+    for (int i = 0; i < n && i < 10; ++i) stats[i] = v[i];
     return OAT_OK;
 }
 
@@ -495,7 +516,7 @@ int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void
     hipError_t e = launch_diff_adj(plan->P, data, (int)data_dtype, plan->d_gp,
                                    (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
     if (e == hipSuccess)
-        e = launch_srt_adj(plan->P, plan->d_gp, plan->d_bbuf, img, (int)img_dtype, s);
+        e = launch_srt_adj(plan->P, plan->d_gp, plan->d_acc, img, (int)img_dtype, s);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_backproject: launch");
     return OAT_OK;

@@ -582,88 +582,203 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 
 // ---------------------------------------------------------------------------
 // G^T: each brick takes the same cells (hence the same points) as in G and
-// accumulates their trilinear weights in an LDS box of 64-bit integers.
-// Every weight w g' psi is scaled by 2^s, truncated to an integer and added
-// with the native 64-bit integer LDS atomic (ds_add_u64; about half the cost
-// of ds_add_f64 on this part, and the FP32 one is microcoded).  s is the
-// largest power of two that keeps every weight below 2^30 (from the largest
-// reachable |g'| of the call and the largest ring weight), so each
-// conversion error is below 2^-30 of the largest weight, and the sums are
-// exact and independent of the order of the atomics: G^T is deterministic.  12 waves share the box.
+// accumulates their trilinear weights w g' psi in an LDS box of fixed-point
+// integers, 12 waves sharing the box.
+//
+// One 64-bit word per cell column holds two 32-bit fields: node x in the low
+// half and node x + 1 in the high half, so a point adds its 8 corner weights
+// with 4 ds_add_u64 (the x pair of each (y, z) corner in one atomic; the
+// 64-bit integer add is the cheapest LDS atomic on this part, the FP32 one
+// is microcoded).  A field value v is added as the signed 64-bit integer
+// lo + hi 2^32; as long as the sums of both fields stay inside 32-bit signed
+// range the word decodes exactly: lo = low 32 bits (signed), hi = (word - lo)
+// >> 32 (arithmetic).
+//
+// The transducers are taken in windows of ADJ_WINDOW = ADJ_WAVES * ADJ_ROUNDS
+// (wave w takes transducers window * ADJ_WINDOW + w + ADJ_WAVES r).  A window's
+// weights are multiplied by S = 0.99 * 2^31 / (R G) and rounded to the nearest
+// integer (v_cvt_rpi_i32_f32), where
+//   R(brick, window) = max over box nodes of sum psi w over the window's
+//                      points (measured once per plan, calibration mode), and
+//   G(window)        = max |g'| of the window's transducers over the samples
+//                      whose shell can reach the image support,
+// so no field can leave 32-bit range.  After each window the fields are
+// decoded, multiplied by 1/S and added into the brick's FP64 node
+// accumulators in HBM (window order fixed: G^T is deterministic), and the box
+// is cleared.  Each rounding error is at most half a unit, 2^-32 of R G: the
+// precision of an FP32 sum of the window's terms, without its dependence on
+// the order of the atomics.
+//
+// Calibration mode (once per plan): the same walk with g' = 1 on the
+// per-node 64-bit box layout (8 atomics per point, each term below 2^30,
+// sums far below 2^63), writing R(brick, window) rounded up.
+//
 // The box (its owned nodes and the one-node layer below them, which belongs
-// to the neighbouring bricks) is written to HBM in FP32 and adj_gather_kernel
-// adds the overlapping layers.
+// to the neighbouring bricks) ends in HBM in FP64; adj_gather_kernel adds the
+// overlapping layers.
 // ---------------------------------------------------------------------------
-constexpr int ADJ_WAVES = 12;
+__device__ __forceinline__ int cvt_rne(float x)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));   // floor(x + 0.5)
+    return r;
+}
 
-template <bool TAB>
+// Exponent s with bound * 2^s < 2^target (bound > 0, finite), as two normal
+// FP32 factors 2^(s/2) 2^(s - s/2) (|s| <= 252) and the FP64 inverse.
+__device__ __forceinline__ void window_scale(double bound, int target, float &g1, float &g2,
+                                             double &unscale)
+{
+    int e = 0;
+    (void)frexp(bound, &e);                   // bound < 2^e
+    const int sh = (bound > 0.0 && bound <= 1e300) ? min(max(target - e, -252), 252) : 0;
+    g1 = ldexpf(1.f, sh / 2);
+    g2 = ldexpf(1.f, sh - sh / 2);
+    unscale = ldexp(1.0, -sh);
+}
+
+// Scale 0.99 * 2^31 / bound (bound > 0, finite) as two FP32 factors and the
+// FP64 inverse of their product: with it no sum of terms whose magnitudes
+// add up to at most bound leaves 32-bit signed range (the 1% margin covers
+// FP32 rounding of the terms and half a unit per rounded term).
+__device__ __forceinline__ void field_scale(double bound, float &g1, float &g2, double &unscale)
+{
+    if (!(bound > 0.0 && bound <= 1e300)) {
+        g1 = g2 = 1.f;
+        unscale = 1.0;
+        return;
+    }
+    int e = 0;
+    const double m = frexp(bound, &e);        // bound = m 2^e, m in [0.5, 1)
+    const int sh = min(max(31 - e, -250), 250);
+    g1 = ldexpf(1.f, sh / 2);
+    g2 = ldexpf((float)(0.99 / m), sh - sh / 2);
+    unscale = 1.0 / ((double)g1 * (double)g2);
+}
+
+template <bool TAB, bool CALIB>
 __global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(3, 3)))
-srt_adj_kernel(Problem P, const float *__restrict__ gp, float *__restrict__ bbuf)
+srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc,
+               float *__restrict__ rcal)
 {
     __shared__ unsigned long long box[BOX_WORDS];
     __shared__ WaveLds wl[ADJ_WAVES];
-    __shared__ float wmax[ADJ_WAVES];
+    __shared__ unsigned long long wred[ADJ_WAVES];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
     for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
-    // Largest |g'| of the call (one value per D^T workgroup).
-    float m = 0.f;
-    for (int t = threadIdx.x; t < DIFF_BLOCKS; t += blockDim.x) m = fmaxf(m, P.gp_max[t]);
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (lane_id() == 0) wmax[threadIdx.x / WAVE] = m;
     __syncthreads();
-    m = 0.f;
-    for (int w = 0; w < ADJ_WAVES; ++w) m = fmaxf(m, wmax[w]);
-    // 2^s = 2^(s/2) 2^(s - s/2): two normal FP32 factors (|s| <= 252) cover
-    // every finite FP32 |g'|, denormals included, for ring weights between
-    // 2^-70 and 2^90.
-    const double bound = (double)m * (double)P.w_max;
-    int e = 0;
-    (void)frexp(bound, &e);                   // bound < 2^e
-    const int sh = (bound > 0.0 && bound <= 1e300) ? min(max(30 - e, -252), 252) : 0;
-    const float gscale = ldexpf(1.f, sh / 2), gscale2 = ldexpf(1.f, sh - sh / 2);
-    const double unscale = ldexp(1.0, -sh);
-
-    const int wave = threadIdx.x / WAVE;
+    const int wave = threadIdx.x / WAVE, lane = lane_id();
     WaveLds &W = wl[wave];
-    for (int q = wave; q < P.nq; q += ADJ_WAVES) {
-        int klo = 0;
-        // Weights are below 2^30 in magnitude; conversion truncates toward
-        // zero (an error below one unit, 2^-30 of the largest weight).
-        auto scatter1 = [&](const Pt &t, float wv) {
-            unsigned long long *pb =
-                box + __umul24((unsigned)t.cz, BOX_SZ) + __umul24((unsigned)t.cy, BOX_SY) + t.cx;
-            unsigned long long *pz = pb + BOX_SZ;
-            const float gx = 1.f - t.fx, gy = 1.f - t.fy, gz = 1.f - t.fz;
-            const float w00 = gy * gz * wv, w01 = t.fy * gz * wv, w10 = gy * t.fz * wv,
-                        w11 = t.fy * t.fz * wv;
-            auto add = [](unsigned long long *p, float v) {
-                atomicAdd(p, (unsigned long long)(long long)(int)v);
-            };
-            add(pb, gx * w00);
-            add(pb + 1, t.fx * w00);
-            add(pb + BOX_SY, gx * w01);
-            add(pb + BOX_SY + 1, t.fx * w01);
-            add(pz, gx * w10);
-            add(pz + 1, t.fx * w10);
-            add(pz + BOX_SY, gx * w11);
-            add(pz + BOX_SY + 1, t.fx * w11);
-        };
-        auto scatter = [&](const Pt &a, const Pt &c, float wv, int kk, int kbase) {
-            (void)kk;
-            (void)kbase;
-            if (a.own) scatter1(a, wv);
-            if (c.own) scatter1(c, wv);
-        };
-        walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, gp,
-                                          gscale, gscale2, klo, scatter);
-    }
-    __syncthreads();
-    float *dst = bbuf + (size_t)b * BOX3;
-    for (int t = threadIdx.x; t < BOX3; t += blockDim.x) {
-        int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
-        dst[t] = (float)((double)(long long)box[z * BOX_SZ + y * BOX_SY + x] * unscale);
+    const int nwin = adj_windows(P.nq);
+    for (int win = 0; win < nwin; ++win) {
+        const int q0 = win * ADJ_WINDOW;
+        float g1, g2;
+        double unscale;
+        if (CALIB) {
+            window_scale((double)P.w_max, 30, g1, g2, unscale);
+        } else {
+            float m = 0.f;
+            for (int j = lane; j < ADJ_WINDOW && q0 + j < P.nq; j += WAVE)
+                m = fmaxf(m, P.gp_rowmax[q0 + j]);
+            for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+            field_scale((double)P.adj_r[(size_t)b * nwin + win] * (double)m, g1, g2, unscale);
+        }
+        for (int r = 0; r < ADJ_ROUNDS; ++r) {
+            const int q = q0 + r * ADJ_WAVES + wave;
+            if (q >= P.nq) break;
+            int klo = 0;
+            if (CALIB) {
+                auto scatter1 = [&](const Pt &t, float wv) {
+                    unsigned long long *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
+                                             __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+                    unsigned long long *pz = pb + BOX_SZ;
+                    const float gx = 1.f - t.fx, gy = 1.f - t.fy, gz = 1.f - t.fz;
+                    const float w00 = gy * gz * wv, w01 = t.fy * gz * wv, w10 = gy * t.fz * wv,
+                                w11 = t.fy * t.fz * wv;
+                    auto add = [](unsigned long long *p, float v) {
+                        atomicAdd(p, (unsigned long long)(long long)cvt_rne(v));
+                    };
+                    add(pb, gx * w00);
+                    add(pb + 1, t.fx * w00);
+                    add(pb + BOX_SY, gx * w01);
+                    add(pb + BOX_SY + 1, t.fx * w01);
+                    add(pz, gx * w10);
+                    add(pz + 1, t.fx * w10);
+                    add(pz + BOX_SY, gx * w11);
+                    add(pz + BOX_SY + 1, t.fx * w11);
+                };
+                auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
+                    if (a.own) scatter1(a, (wv * g1) * g2);
+                    if (c.own) scatter1(c, (wv * g1) * g2);
+                };
+                walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                                                   nullptr, nullptr, 1.f, 1.f, klo, scatter);
+            } else {
+                auto scatter1 = [&](const Pt &t, float wv) {
+                    unsigned long long *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
+                                             __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+                    unsigned long long *pz = pb + BOX_SZ;
+                    const float gx = 1.f - t.fx, gy = 1.f - t.fy, gz = 1.f - t.fz;
+                    const float w00 = gy * gz * wv, w01 = t.fy * gz * wv, w10 = gy * t.fz * wv,
+                                w11 = t.fy * t.fz * wv;
+                    // fields (node x, node x + 1) of one word
+                    auto add2 = [&](unsigned long long *p, float wyz) {
+                        const int l = cvt_rne(gx * wyz), h = cvt_rne(t.fx * wyz);
+                        atomicAdd(p, (unsigned long long)(long long)l +
+                                         ((unsigned long long)(unsigned)h << 32));
+                    };
+                    add2(pb, w00);
+                    add2(pb + BOX_SY, w01);
+                    add2(pz, w10);
+                    add2(pz + BOX_SY, w11);
+                };
+                auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
+                    if (a.own) scatter1(a, wv);
+                    if (c.own) scatter1(c, wv);
+                };
+                walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                                                  nullptr, gp, g1, g2, klo, scatter);
+            }
+        }
+        __syncthreads();
+        if (CALIB) {
+            unsigned long long m = 0ull;
+            for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) {
+                const long long v = (long long)box[t];
+                m = max(m, (unsigned long long)(v < 0 ? -v : v));
+            }
+            for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+            if (lane == 0) wred[wave] = m;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long mm = 0ull;
+                for (int w = 0; w < ADJ_WAVES; ++w) mm = max(mm, wred[w]);
+                // rounded up: (float) may round down, and each of the at most
+                // 2^20 terms of a node lost at most half a unit
+                const double r = ((double)mm + 1048576.0) * unscale;
+                rcal[(size_t)b * nwin + win] = (float)r * (1.f + 1.f / 1024.f);
+            }
+        } else {
+            double *dst = acc + (size_t)b * BOX3;
+            for (int t = threadIdx.x; t < BOX3; t += blockDim.x) {
+                const int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
+                const unsigned long long *row = box + z * BOX_SZ + y * BOX_SY;
+                long long v = 0;
+                if (x < BOX - 1) v += (long long)(int)(unsigned)row[x];
+                if (x > 0) {
+                    const long long wd = (long long)row[x - 1];
+                    const long long l = (long long)(int)(unsigned)wd;
+                    v += (wd - l) >> 32;
+                }
+                const double a = (double)v * unscale;
+                dst[t] = win == 0 ? a : dst[t] + a;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
+        __syncthreads();
     }
 }
 
@@ -710,17 +825,27 @@ hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, floa
     return hipGetLastError();
 }
 
-hipError_t launch_srt_adj(const Problem &P, const float *gp, float *bbuf, void *img,
+hipError_t launch_srt_adj(const Problem &P, const float *gp, double *acc, void *img,
                           int img_dtype, hipStream_t s)
 {
     dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
     if (P.tab_arc != nullptr)
-        hipLaunchKernelGGL(srt_adj_kernel<true>, grid, block, 0, s, P, gp, bbuf);
+        hipLaunchKernelGGL((srt_adj_kernel<true, false>), grid, block, 0, s, P, gp, acc, nullptr);
     else
-        hipLaunchKernelGGL(srt_adj_kernel<false>, grid, block, 0, s, P, gp, bbuf);
+        hipLaunchKernelGGL((srt_adj_kernel<false, false>), grid, block, 0, s, P, gp, acc, nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_adj_gather(P, bbuf, img, img_dtype, s);
+    return launch_adj_gather(P, acc, img, img_dtype, s);
+}
+
+hipError_t launch_adj_calibrate(const Problem &P, float *r, hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
+    if (P.tab_arc != nullptr)
+        hipLaunchKernelGGL((srt_adj_kernel<true, true>), grid, block, 0, s, P, nullptr, nullptr, r);
+    else
+        hipLaunchKernelGGL((srt_adj_kernel<false, true>), grid, block, 0, s, P, nullptr, nullptr, r);
+    return hipGetLastError();
 }
 
 hipError_t launch_arc_build(const Problem &P, int fill, hipStream_t s)

@@ -162,10 +162,10 @@ class Plan:
             pass
 
     def stats(self) -> dict:
-        v = (ctypes.c_int64 * 9)()
-        _check(lib().oat_plan_stats(self._h, v, 9))
+        v = (ctypes.c_int64 * 10)()
+        _check(lib().oat_plan_stats(self._h, v, 10))
         keys = ("rings", "bricks", "brick", "window", "workspace_bytes", "table_bytes",
-                "arc_table_bytes", "arc_table_entries", "arc_table_build_us")
+                "arc_table_bytes", "arc_table_entries", "arc_table_build_us", "adj_calibration_us")
         return dict(zip(keys, [int(x) for x in v]))
 
     def _prep(self, t, shape):

@@ -261,3 +261,24 @@ def test_backproject_with_wide_dynamic_range(Plan):
     e2 = rel(_np(plan.backproject(_t(tiny))), ref.backproject(gd, tiny))
     _say(f"[gpu] H^T loud transducer rel {e:.3e}; 1e-30 data rel {e2:.3e}")
     assert e < 1e-5 and e2 < 1e-5
+
+
+@pytest.fixture(scope="module")
+def small1_plan(Plan):
+    geom = synth.config_small(1)[0]
+    return geom, Plan(geom, 0)
+
+
+@pytest.mark.parametrize("q", [0, 11, 12, 47, 48, 63])
+def test_backproject_single_transducer(q, small1_plan):
+    """Data on one transducer only, at every position class of G^T's
+    transducer windows (first and last of a wave's rounds, last of a window,
+    first of the next): each scale must see that transducer's data."""
+    geom, plan = small1_plan
+    rng = np.random.default_rng(100 + q)
+    y = np.zeros((geom.n_det, geom.n_t))
+    y[q] = rng.normal(size=geom.n_t).astype(np.float32)
+    e = rel(_np(plan.backproject(_t(y))),
+            ref.backproject(geom.as_dict(), y[q:q + 1], rows=np.array([q], dtype=np.int32)))
+    _say(f"[gpu] H^T data on transducer {q}: rel {e:.3e}")
+    assert e < 1e-5
