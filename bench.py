@@ -266,8 +266,8 @@ def matrix(reps):
             ("E: 256^3, 8192 sphere, K 1024", lambda: synth.config_e(0)),
             ("P: 210x210x440 at 0.14 mm, 64x90 rings, K 1022", lambda: synth.config_p(0))]
     print("| workload | storage | H ms | H^T ms | FBP ms | H upd/s | H^T upd/s | FBP upd/s | "
-          "nominal HBM % (H) | plan s | arc table GB |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|")
+          "nominal HBM % (H) | plan s | arc table GB | segment table GB |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
     for name, make in cfgs:
         geom, _, img = make()
         t0 = time.perf_counter()
@@ -286,7 +286,8 @@ def matrix(reps):
             print(f"| {name} | {'f32' if dt == torch.float32 else 'bf16'} | {th * 1e3:.1f} | "
                   f"{tt * 1e3:.1f} | {tf * 1e3:.1f} | {NQ / th:.3e} | {NQ / tt:.3e} | {NQ / tf:.3e} | "
                   f"{100 * NQ / th * nbytes / HBM_PEAK:.1f} | {plan_s:.2f} | "
-                  f"{st['arc_table_bytes'] / 1e9:.1f} |", flush=True)
+                  f"{st['arc_table_bytes'] / 1e9:.1f} | {st['segment_table_bytes'] / 1e9:.1f} |",
+                  flush=True)
             del x, p, a
         plan.close()
         del plan
@@ -336,7 +337,8 @@ def main():
     plan = Plan(geom, 0)
     plan_s = time.perf_counter() - t_plan
     st = plan.stats()
-    log(f"[bench] plan {plan_s:.2f} s, arc table {st['arc_table_bytes'] / 1e9:.2f} GB")
+    log(f"[bench] plan {plan_s:.2f} s, arc table {st['arc_table_bytes'] / 1e9:.2f} GB, "
+        f"segment table {st['segment_table_bytes'] / 1e9:.2f} GB")
     x = torch.from_numpy(img).to(dev)
     p = torch.empty(plan.data_shape, device=dev)
     a = torch.empty(plan.image_shape, device=dev)
@@ -404,6 +406,7 @@ def main():
                                     "hemisphere, 1024 samples at 20 MHz; step = H + H^T + FBP",
                            nx=256, n_det=Q, n_t=geom.n_t, storage="f32",
                            arc_table_bytes=st["arc_table_bytes"],
+                           segment_table_bytes=st["segment_table_bytes"],
                            plan_build_s=plan_s),
                ops=dict(H_ms=t_h, HT_ms=t_ht, FBP_ms=t_f,
                         H_updates_per_s=N * Q / (t_h * 1e-3),

@@ -120,13 +120,26 @@ int oat_plan_create(const oat_geometry *geom, int device, oat_plan **out);
  *    0  never build it;
  *  > 0  build it if it fits in this many bytes.
  * Without a table, or when the geometry has rings of more than 65535 points
- * or shells of more than 65535 rings, the kernels bound the arcs themselves. */
+ * or shells of more than 65535 rings, the kernels bound the arcs themselves.
+ *
+ * segment_table_bytes: device memory the plan may spend on its segment
+ * table, built from the arc table (so only when that exists).  It lists, for
+ * every (image brick, transducer) pair, the ring segments (runs of at most 32
+ * consecutive points) that hold the brick's points, 8 bytes each: 40 GB for
+ * the 256^3 case above.  With it the kernels stream a pair's segments
+ * directly instead of expanding shells into rings and rings into segments
+ * (about a quarter less work per point).  Once it is built the plan frees
+ * the arc table.  Same values as arc_table_bytes; the automatic budget is 40%
+ * of the device memory free after the arc table is built, and must hold both
+ * tables while the segment table is filled.  Results are identical with or
+ * without it up to FP32 summation order (bit for bit in oat_backproject). */
 typedef struct {
     int64_t arc_table_bytes;
+    int64_t segment_table_bytes;
 } oat_plan_options;
 
-/* oat_plan_create with options (NULL = defaults).  OAT_ERR_ARG when
- * arc_table_bytes < -1. */
+/* oat_plan_create with options (NULL = defaults: -1 and -1).  OAT_ERR_ARG
+ * when arc_table_bytes or segment_table_bytes < -1. */
 int oat_plan_create_ex(const oat_geometry *geom, int device, const oat_plan_options *opt,
                        oat_plan **out);
 
@@ -166,11 +179,14 @@ const char *oat_last_error(void);
  * stats[1] = number of image bricks, stats[2] = brick edge (cells),
  * stats[3] = shell window per (brick, transducer),
  * stats[4] = bytes of device workspace, stats[5] = bytes of device tables,
- * stats[6] = bytes of the arc table (0: none), stats[7] = its ring entries,
+ * stats[6] = bytes of the arc table (0: none built; the plan frees it again
+ * when it builds the segment table), stats[7] = its ring entries,
  * stats[8] = its build time in microseconds,
  * stats[9] = time of the G^T calibration pass in microseconds (the plan runs
- * G^T's walk once with unit data to bound its fixed-point sums).
- * n = capacity of stats (at most 10 are written); returns OAT_OK. */
+ * G^T's walk once with unit data to bound its fixed-point sums),
+ * stats[10] = bytes of the segment table (0: none), stats[11] = its entries,
+ * stats[12] = its build time in microseconds.
+ * n = capacity of stats (at most 13 are written); returns OAT_OK. */
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n);
 
 #ifdef __cplusplus

@@ -100,6 +100,14 @@ struct Problem {
     unsigned *tab_run;
     unsigned *tab_arc;
     int *tab_cnt;
+    // Segment table (null when the plan has none): the segments of unit u
+    // are entries seg_off[u] .. seg_off[u+1]-1, two words each: the ring's
+    // global index, and jb | npts << 16 | (k - klo(u)) << 22 (first point
+    // index, points, shell offset), in the order of the arc-table walk.
+    // seg_cnt[u] = segments of unit u (written by the count pass).
+    const long long *seg_off;
+    unsigned *seg;
+    int *seg_cnt;
 };
 
 // Sets the thread-local text returned by oat_last_error (defined with the
@@ -109,9 +117,10 @@ void set_last_error(const char *msg);
 // Launchers (defined in the .hip files); dtype: 0 = f32, 1 = bf16.
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part,
                           int *klo, hipStream_t s);
-// Arc-table passes: fill = 0 writes tab_run and tab_cnt (tab_run zeroed
-// beforehand), fill = 1 writes tab_arc (tab_off set).
-hipError_t launch_arc_build(const Problem &P, int fill, hipStream_t s);
+// Table passes: mode 0 writes tab_run and tab_cnt (tab_run zeroed
+// beforehand), 1 writes tab_arc (tab_off set); with the arc table in place,
+// 2 writes seg_cnt and 3 writes seg (seg_off set).
+hipError_t launch_arc_build(const Problem &P, int mode, hipStream_t s);
 hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo,
                              void *out, int out_dtype, int apply_d, hipStream_t s);
 hipError_t launch_diff_adj(const Problem &P, const void *y, int y_dtype, float *gp,

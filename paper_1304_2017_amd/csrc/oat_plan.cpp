@@ -70,7 +70,10 @@ struct oat_plan {
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
+    long long *d_seg_off = nullptr;   // segment table (see Problem)
+    unsigned *d_seg = nullptr;
     int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0, calib_us = 0;
+    int64_t seg_bytes = 0, seg_entries = 0, seg_build_us = 0;
     int max_nj = 0, max_rings = 0;
     float w_max = 0.f;
     int64_t n_rings = 0;
@@ -169,6 +172,96 @@ int build_arc_table(oat_plan *plan, int64_t budget)
     return OAT_OK;
 }
 
+// Segment table from the arc table: a count pass (segments per unit), the
+// host prefix sum, a fill pass that writes each unit's segments in walk
+// order.  Skipped (OAT_OK, no table) when it does not fit the budget; on
+// success the arc table is freed.
+int build_seg_table(oat_plan *plan, int64_t budget)
+{
+    Problem &P = plan->P;
+    if (budget < 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return OAT_OK;
+        budget = (int64_t)(0.4 * (double)fr);
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t units = (int64_t)P.nbx * P.nby * P.nbz * P.nq;
+    const size_t cnt_b = sizeof(int) * (size_t)units;
+    const size_t off_b = sizeof(long long) * (size_t)(units + 1);
+    if ((int64_t)(cnt_b + off_b) > budget) return OAT_OK;
+    int *cnt = nullptr;
+    long long *off = nullptr;
+    unsigned *seg = nullptr;
+    auto release = [&]() {
+        if (cnt) (void)hipFree(cnt);
+        if (off) (void)hipFree(off);
+        if (seg) (void)hipFree(seg);
+        cnt = nullptr;
+        off = nullptr;
+        seg = nullptr;
+    };
+    if (hipMalloc((void **)&cnt, cnt_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return OAT_OK;
+    }
+    Problem Pc = P;
+    Pc.seg_cnt = cnt;
+    hipError_t e = launch_arc_build(Pc, 2, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    std::vector<int> hcnt(units);
+    if (e == hipSuccess) e = hipMemcpy(hcnt.data(), cnt, cnt_b, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        release();
+        return fail_hip(e, "oat_plan_create: segment table count pass");
+    }
+    std::vector<long long> hoff(units + 1);
+    long long total = 0;
+    for (int64_t u = 0; u < units; ++u) {
+        hoff[u] = total;
+        total += hcnt[u];
+    }
+    hoff[units] = total;
+    (void)hipFree(cnt);
+    cnt = nullptr;
+    const size_t seg_b = 2 * sizeof(unsigned) * (size_t)(total > 0 ? total : 1);
+    if ((int64_t)(seg_b + off_b) > budget || hipMalloc((void **)&off, off_b) != hipSuccess ||
+        hipMalloc((void **)&seg, seg_b) != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return OAT_OK;
+    }
+    e = hipMemcpy(off, hoff.data(), off_b, hipMemcpyHostToDevice);
+    Pc.seg_cnt = nullptr;
+    Pc.seg_off = off;
+    Pc.seg = seg;
+    if (e == hipSuccess) e = launch_arc_build(Pc, 3, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        release();
+        return fail_hip(e, "oat_plan_create: segment table fill pass");
+    }
+    // The kernels now read the segment table; the arc table is not needed.
+    (void)hipFree(plan->d_tab_run);
+    (void)hipFree(plan->d_tab_off);
+    (void)hipFree(plan->d_tab_arc);
+    plan->d_tab_run = nullptr;
+    plan->d_tab_off = nullptr;
+    plan->d_tab_arc = nullptr;
+    P.tab_run = nullptr;
+    P.tab_off = nullptr;
+    P.tab_arc = nullptr;
+    plan->d_seg_off = off;
+    plan->d_seg = seg;
+    P.seg_off = off;
+    P.seg = seg;
+    P.seg_cnt = nullptr;
+    plan->seg_bytes = (int64_t)(seg_b + off_b);
+    plan->seg_entries = total;
+    plan->seg_build_us = (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(
+                             std::chrono::steady_clock::now() - t0).count();
+    return OAT_OK;
+}
+
 }  // namespace
 
 void oat::set_last_error(const char *msg) { g_last_error = msg ? msg : ""; }
@@ -185,7 +278,8 @@ void oat_plan_destroy(oat_plan *plan)
     (void)hipSetDevice(plan->device);
     void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
                     plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
-                    plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc};
+                    plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
+                    plan->d_seg};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -204,6 +298,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     if (!g || !out) return fail(OAT_ERR_ARG, "oat_plan_create: null argument");
     const int64_t table_budget = opt ? opt->arc_table_bytes : -1;
     if (table_budget < -1) return fail(OAT_ERR_ARG, "arc_table_bytes must be >= -1");
+    const int64_t seg_budget = opt ? opt->segment_table_bytes : -1;
+    if (seg_budget < -1) return fail(OAT_ERR_ARG, "segment_table_bytes must be >= -1");
     *out = nullptr;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1)
         return fail(OAT_ERR_GEOMETRY, "grid sizes must be >= 1");
@@ -425,10 +521,15 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.tab_run = nullptr;
     P.tab_arc = nullptr;
     P.tab_cnt = nullptr;
+    P.seg_off = nullptr;
+    P.seg = nullptr;
+    P.seg_cnt = nullptr;
     plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + acc_b + rowmax_b);
     plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b);
     if (table_budget != 0) {
         int code = build_arc_table(plan, table_budget);
+        if (code == OAT_OK && seg_budget != 0 && plan->d_tab_arc)
+            code = build_seg_table(plan, seg_budget);
         if (code != OAT_OK) {
             oat_plan_destroy(plan);
             (void)hipSetDevice(prev);
@@ -459,10 +560,11 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
 int oat_plan_stats(const oat_plan *plan, int64_t *stats, int n)
 {
     if (!plan || !stats || n < 0) return fail(OAT_ERR_ARG, "oat_plan_stats: null argument");
-    int64_t v[10] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
+    int64_t v[13] = {plan->n_rings, (int64_t)plan->P.nbx * plan->P.nby * plan->P.nbz, BRICK,
                      plan->P.window, plan->ws_bytes, plan->table_bytes, plan->tab_bytes,
-                     plan->tab_entries, plan->tab_build_us, plan->calib_us};
-    for (int i = 0; i < n && i < 10; ++i) stats[i] = v[i];
+                     plan->tab_entries, plan->tab_build_us, plan->calib_us, plan->seg_bytes,
+                     plan->seg_entries, plan->seg_build_us};
+    for (int i = 0; i < n && i < 13; ++i) stats[i] = v[i];
     return OAT_OK;
 }
 

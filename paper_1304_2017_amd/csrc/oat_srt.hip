@@ -184,9 +184,18 @@ __device__ __forceinline__ void brick_box(const Problem &P, int b, int lo[3], in
 
 // What walk_unit does with the points it enumerates.
 enum WalkMode {
-    WALK_POINTS = 0,   // call fn on every window of points (G, G^T)
-    WALK_COUNT = 1,    // arc table, first pass: runs of rings with owned points
-    WALK_FILL = 2      // arc table, second pass: tight arc of every ring in a run
+    WALK_POINTS = 0,    // call fn on every window of points (G, G^T)
+    WALK_COUNT = 1,     // arc table, first pass: runs of rings with owned points
+    WALK_FILL = 2,      // arc table, second pass: tight arc of every ring in a run
+    WALK_SEGCOUNT = 3,  // segment table, first pass: segments per unit
+    WALK_SEGFILL = 4    // segment table, second pass: the unit's segment entries
+};
+
+// Where the rings and arcs of a unit come from.
+enum TableMode {
+    TM_BOUNDS = 0,  // ball/slab bounds of the brick, computed per unit
+    TM_ARC = 1,     // plan's arc table: tight arcs of the rings with owned points
+    TM_SEG = 2      // plan's segment table: the unit's segments, in walk order
 };
 
 // Per-wave LDS of the arc-table passes: owned-index span (in arc order) per
@@ -196,20 +205,132 @@ struct BuildLds {
     int smin[64], smax[64];
 };
 
+// One window of up to 64 segments, one per lane (v2 = the lane holds one):
+// ring (rc, rs, 1/nj, nj, delta, segment shift ls), shell k2, its weight w2
+// (w g' 2^s in G^T), points jb .. jb+npts-1 of segment jb >> ls.  Stages the
+// segments' data and walks their points two per lane (level 3).  ub and rl
+// are the arc-table passes' offset of jb in the ring's arc and the ring's
+// level-1 lane.
+template <int MODE, class Fn>
+__device__ __forceinline__ void segment_points(const Problem &P, WaveLds &W, BuildLds *B,
+                                               const int lo[3], const int hi[3],
+                                               const double uq[3], const double e3[3],
+                                               const double e1d[3], const double e2d[3],
+                                               const float e1[3], const float e2[3], bool v2,
+                                               double rc2, double rs2, double in2, float w2,
+                                               float dl2, int nj2, int ls2, int k2, int jb,
+                                               int npts, int ub, int rl, int klo, Fn &&fn)
+{
+    const int lane = lane_id();
+    Level L3{W.bits3, W.prod3, 0, 0};
+    const int sb = (jb >> ls2) << ls2, se = min(sb + (1 << ls2), nj2);
+    const int jref = sb + ((se - sb - 1) >> 1);
+    // Reference point of the segment in FP64, split into an integer cell
+    // (relative to the box, packed 10 bits per axis) and an FP32 fraction,
+    // and its in-plane coordinates (xa, xb) = rs (cos, sin) of the reference
+    // azimuth: point j is ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
+    // b = xb (cos d - 1) + xa sin d, d = (j - jref) 2 pi / nj.
+    double cr, sr;
+    sincos_turns_d((double)jref * in2, cr, sr);
+    float Pl[3];
+    int dpk = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double pa = fma(rc2, e3[a], uq[a]) + rs2 * fma(cr, e1d[a], sr * e2d[a]);
+        const double ph = floor(pa);
+        Pl[a] = (float)(pa - ph);
+        // clamped offsets only occur for points far outside the box
+        const int db = min(max((int)ph - lo[a], -512), 511) + 512;
+        dpk |= db << (10 * a);
+    }
+    const float xa = (float)(rs2 * cr), xb = (float)(rs2 * sr);
+    const int np = v2 ? npts : 0;
+    // jb - jref in [-16, 16], npts <= 32, shell index < 4096
+    const int meta = (jb - jref + 64) | (np << 7) | (k2 << 13);
+    // The segment's data goes to the wave's LDS stage, where the lanes of its
+    // points read it (a broadcast read; cheaper than one bpermute per value
+    // on this part).
+    wave_sync();
+    W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(dpk));
+    W.stage[lane][1] = make_float4(xa, xb, dl2, __int_as_float(meta));
+    W.stage[lane][2] = make_float4(w2, __int_as_float(rl), __int_as_float(ub), 0.f);
+    // Level 3: each lane takes two consecutive points of a segment
+    // (level_begin orders the stage writes before the reads).
+    level_begin<5>(L3, (np + 1) >> 1);
+    for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
+        int s3, pr;
+        const bool v3 = level_item(L3, F3, s3, pr);
+        const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1];
+        const float p0 = r0.x, p1 = r0.y, p2 = r0.z;
+        const int dp = __float_as_int(r0.w);
+        const float qa = r1.x, qb = r1.y, dd = r1.z;
+        const int mt = __float_as_int(r1.w);
+        float wv = 0.f;
+        int rlp = 0, ur = 0;
+        if (MODE == WALK_POINTS) {
+            wv = W.stage[s3][2].x;
+        } else {
+            const float4 r2 = W.stage[s3][2];
+            rlp = __float_as_int(r2.y);
+            ur = __float_as_int(r2.z) + 2 * pr;
+        }
+        const int d0 = (dp & 1023) - 512, d1 = ((dp >> 10) & 1023) - 512,
+                  d2 = ((dp >> 20) & 1023) - 512;
+        const int npp = (mt >> 7) & 63, kk = mt >> 13;
+        const int djA = (mt & 127) - 64 + 2 * pr;
+        Pt pt[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float cm1, sn;
+            small_rot((float)(djA + h) * dd, cm1, sn);
+            const float al = fmaf(qa, cm1, -(qb * sn));
+            const float be = fmaf(qb, cm1, qa * sn);
+            // Fractional coordinates about the reference cell: the same FP32
+            // operations in every brick, so ownership is exact.
+            const float ux = fmaf(be, e2[0], fmaf(al, e1[0], p0));
+            const float uy = fmaf(be, e2[1], fmaf(al, e1[1], p1));
+            const float uz = fmaf(be, e2[2], fmaf(al, e1[2], p2));
+            Pt &t = pt[h];
+            t.cx = cvt_floor(ux) + d0;
+            t.cy = cvt_floor(uy) + d1;
+            t.cz = cvt_floor(uz) + d2;
+            t.fx = __builtin_amdgcn_fractf(ux);
+            t.fy = __builtin_amdgcn_fractf(uy);
+            t.fz = __builtin_amdgcn_fractf(uz);
+            t.own = v3 && 2 * pr + h < npp && (unsigned)t.cx < (unsigned)(hi[0] - lo[0]) &&
+                    (unsigned)t.cy < (unsigned)(hi[1] - lo[1]) &&
+                    (unsigned)t.cz < (unsigned)(hi[2] - lo[2]);
+        }
+        if (MODE == WALK_POINTS) {
+            fn(pt[0], pt[1], wv, kk, klo);
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (pt[h].own) {
+                    atomicMin(&B->rmin[rlp], ur + h);
+                    atomicMax(&B->rmax[rlp], ur + h);
+                }
+        }
+    }
+}
+
 // Walk all points of transducer q owned by the brick (unit = brick * nq + q).
-// Ring arcs come from the ball/slab bounds (TAB = false) or from the plan's
-// arc table (TAB = true, tight arcs of exactly the rings that hold owned
-// points); both give the same owned points.  In WALK_POINTS mode fn is called
-// per window of 64 lanes with the lane's two consecutive points of one
-// segment (Pt each), their weight, their shell index and the unit's first
-// shell.
-template <bool ADJ, bool TAB, int MODE, class Fn>
+// The rings and arcs come from the ball/slab bounds (TM_BOUNDS), the plan's
+// arc table (TM_ARC: tight arcs of exactly the rings that hold owned points)
+// or its segment table (TM_SEG: those arcs' segments, listed per unit in the
+// order of the arc-table walk); all three give the same owned points.  In
+// WALK_POINTS mode fn is called per window of 64 lanes with the lane's two
+// consecutive points of one segment (Pt each), their weight, their shell
+// index and the unit's first shell.
+template <bool ADJ, int TM, int MODE, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
                                           const int hi[3], WaveLds &W, BuildLds *B,
                                           const float *gp, float gscale, float gscale2,
                                           int &klo_out, Fn &&fn)
 {
+    constexpr bool TAB = TM == TM_ARC;
     constexpr bool READ_RUNS = TAB || MODE == WALK_FILL;
+    constexpr bool SEGB = MODE == WALK_SEGCOUNT || MODE == WALK_SEGFILL;
     const DetRec &d = P.det[q];
     const double uq[3] = {d.uq[0], d.uq[1], d.uq[2]};
     const double e3[3] = {d.e3[0], d.e3[1], d.e3[2]};
@@ -217,8 +338,6 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
     const double e2d[3] = {d.e2d[0], d.e2d[1], d.e2d[2]};
     const float e1[3] = {d.e1[0], d.e1[1], d.e1[2]};
     const float e2[3] = {d.e2[0], d.e2[1], d.e2[2]};
-    ArcUnit U;
-    if (!TAB) arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
 
     // Shells that can reach the box.
     float dmin2 = 0.f, dmax2 = 0.f;
@@ -235,19 +354,41 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
     int khi = min(P.nt - 1, (int)floorf((dmax - P.rho0) / P.rho_step));
     khi = min(khi, klo + P.window - 1);
     klo_out = klo;
+    const int lane = lane_id();
 
+    if constexpr (TM == TM_SEG) {
+        // 64 segment entries per window: (ring, jb | npts << 16 | (k - klo) << 22).
+        const long long s0 = P.seg_off[unit], s1 = P.seg_off[unit + 1];
+        const uint2 *seg = reinterpret_cast<const uint2 *>(P.seg);
+        for (long long c = s0; c < s1; c += WAVE) {
+            const long long ei = c + lane;
+            const bool v2 = ei < s1;
+            const uint2 ent = v2 ? seg[ei] : make_uint2(0u, 0u);
+            const int jb = (int)(ent.y & 0xffffu), npts = (int)((ent.y >> 16) & 63u);
+            const int k2 = klo + (int)(ent.y >> 22);
+            const RingRec rr = P.ring[ent.x];
+            float w2 = rr.w;
+            if (ADJ && v2) w2 = w2 * ((gp[(size_t)q * P.nt + k2] * gscale) * gscale2);
+            segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rr.rc, rr.rs,
+                                 rr.inv_nj, w2, rr.delta, rr.nj, rr.lshift, k2, jb, npts, 0, 0,
+                                 klo, fn);
+        }
+        return;
+    }
+
+    ArcUnit U;
+    if (!TAB) arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
     const float D = TAB ? 0.f : sqrtf(U.rhov2 + U.V3 * U.V3);
     const float thb = TAB ? 0.f : acos_approx(U.V3 * rcp_approx(D));
     const float h2 = U.h2;
 
     Level L1{W.bits1, W.prod1, 0, 0};
     Level L2{W.bits2, W.prod2, 0, 0};
-    Level L3{W.bits3, W.prod3, 0, 0};
 
     const long long ebase = READ_RUNS ? P.tab_off[unit] : 0ll;
-    int run_base = 0;   // table entries of the earlier shell chunks
-    int ucount = 0;     // WALK_COUNT: table entries of the unit (per shell lane)
-    const int lane = lane_id();
+    int run_base = 0;     // table entries of the earlier shell chunks
+    int ucount = 0;       // WALK_COUNT: table entries of the unit (per shell lane)
+    long long scount = 0; // segment passes: segments of the unit so far
 
     for (int kc = klo; kc <= khi; kc += WAVE) {
         // Level 1 producers: one shell per lane -> candidate ring range.
@@ -345,11 +486,12 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
             }
             if (ADJ && v1 && items_all > 0)
                 w = w * ((gp[(size_t)q * P.nt + kr] * gscale) * gscale2);
-            if (MODE != WALK_POINTS) {
+            if (MODE == WALK_COUNT || MODE == WALK_FILL) {
                 B->rmin[lane] = 0x7fffffff;
                 B->rmax[lane] = -1;
                 wave_sync();
             }
+            const int rg = rb + ir;
             for (int pass2 = 0; __ballot(items_all - pass2 * CAP2 > 0) != 0ull; ++pass2) {
             const int nitems = min(max(items_all - pass2 * CAP2, 0), CAP2);
             level_begin<5>(L2, nitems);
@@ -357,8 +499,6 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 int s2, m;
                 bool v2 = level_item(L2, F2, s2, m);
                 m += pass2 * CAP2;
-                const double rc2 = bperm_d(s2, rcd), rs2 = bperm_d(s2, rsd), in2 = bperm_d(s2, invd);
-                const float w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
                 const int nj2 = bperm_i(s2, nj), jlo2 = bperm_i(s2, jlo), jc2 = bperm_i(s2, jcnt);
                 const int ls2 = bperm_i(s2, ls), n12 = bperm_i(s2, n1), k2 = bperm_i(s2, kr);
                 // Segment of this item and its index range.
@@ -367,100 +507,35 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 const int sb = s << ls2, se = min(sb + (1 << ls2), nj2);
                 const int jb = wrap ? sb : max(sb, jlo2);
                 const int je = min(se, wrap ? jlo2 + jc2 - nj2 : jlo2 + jc2);
-                const int jref = sb + ((se - sb - 1) >> 1);
-                const int ub = wrap ? jb + nj2 - jlo2 : jb - jlo2;   // offset of jb in the arc
-                // Reference point of the segment in FP64, split into an
-                // integer cell (relative to the box, packed 10 bits per axis)
-                // and an FP32 fraction, and its in-plane coordinates
-                // (xa, xb) = rs (cos, sin) of the reference azimuth: point j
-                // is ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
-                // b = xb (cos d - 1) + xa sin d, d = (j - jref) 2 pi / nj.
-                double cr, sr;
-                sincos_turns_d((double)jref * in2, cr, sr);
-                float Pl[3];
-                int dpk = 0;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const double pa = fma(rc2, e3[a], uq[a]) + rs2 * fma(cr, e1d[a], sr * e2d[a]);
-                    const double ph = floor(pa);
-                    Pl[a] = (float)(pa - ph);
-                    // clamped offsets only occur for points far outside the box
-                    const int db = min(max((int)ph - lo[a], -512), 511) + 512;
-                    dpk |= db << (10 * a);
-                }
-                const float xa = (float)(rs2 * cr), xb = (float)(rs2 * sr);
                 const int npts = v2 ? max(je - jb, 0) : 0;
-                // jb - jref in [-16, 16], npts <= 32, shell index < 4096
-                const int meta = (jb - jref + 64) | (npts << 7) | (k2 << 13);
-                // The segment's data goes to the wave's LDS stage, where the
-                // lanes of its points read it (a broadcast read; cheaper than
-                // one bpermute per value on this part).
-                wave_sync();
-                W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(dpk));
-                W.stage[lane][1] = make_float4(xa, xb, dl2, __int_as_float(meta));
-                W.stage[lane][2] = make_float4(w2, __int_as_float(s2), __int_as_float(ub), 0.f);
-                // Level 3: each lane takes two consecutive points of a segment
-                // (level_begin orders the stage writes before the reads).
-                level_begin<5>(L3, (npts + 1) >> 1);
-                for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
-                    int s3, pr;
-                    const bool v3 = level_item(L3, F3, s3, pr);
-                    const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1];
-                    const float p0 = r0.x, p1 = r0.y, p2 = r0.z;
-                    const int dp = __float_as_int(r0.w);
-                    const float qa = r1.x, qb = r1.y, dd = r1.z;
-                    const int mt = __float_as_int(r1.w);
-                    float wv = 0.f;
-                    int rl = 0, ur = 0;
-                    if (MODE == WALK_POINTS) {
-                        wv = W.stage[s3][2].x;
-                    } else {
-                        const float4 r2 = W.stage[s3][2];
-                        rl = __float_as_int(r2.y);
-                        ur = __float_as_int(r2.z) + 2 * pr;
+                if (SEGB) {
+                    // Segment table passes: count, or write the unit's
+                    // entries in this order.
+                    const bool has = npts > 0;
+                    const uint64_t bal = __ballot(has);
+                    if (MODE == WALK_SEGFILL) {
+                        const int rg2 = bperm_i(s2, rg);
+                        const long long pos =
+                            P.seg_off[unit] + scount + __popcll(bal & mask_below());
+                        // the count pass saw the same segments; the guard
+                        // only keeps a mismatch inside the unit's range
+                        if (has && pos < P.seg_off[unit + 1]) {
+                            reinterpret_cast<uint2 *>(P.seg)[pos] = make_uint2(
+                                (unsigned)rg2, (unsigned)jb | ((unsigned)npts << 16) |
+                                                   ((unsigned)(k2 - klo) << 22));
+                        }
                     }
-                    const int d0 = (dp & 1023) - 512, d1 = ((dp >> 10) & 1023) - 512,
-                              d2 = ((dp >> 20) & 1023) - 512;
-                    const int np = (mt >> 7) & 63, kk = mt >> 13;
-                    const int djA = (mt & 127) - 64 + 2 * pr;
-                    Pt pt[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        float cm1, sn;
-                        small_rot((float)(djA + h) * dd, cm1, sn);
-                        const float al = fmaf(qa, cm1, -(qb * sn));
-                        const float be = fmaf(qb, cm1, qa * sn);
-                        // Fractional coordinates about the reference cell: the
-                        // same FP32 operations in every brick, so ownership is
-                        // exact.
-                        const float ux = fmaf(be, e2[0], fmaf(al, e1[0], p0));
-                        const float uy = fmaf(be, e2[1], fmaf(al, e1[1], p1));
-                        const float uz = fmaf(be, e2[2], fmaf(al, e1[2], p2));
-                        Pt &t = pt[h];
-                        t.cx = cvt_floor(ux) + d0;
-                        t.cy = cvt_floor(uy) + d1;
-                        t.cz = cvt_floor(uz) + d2;
-                        t.fx = __builtin_amdgcn_fractf(ux);
-                        t.fy = __builtin_amdgcn_fractf(uy);
-                        t.fz = __builtin_amdgcn_fractf(uz);
-                        t.own = v3 && 2 * pr + h < np && (unsigned)t.cx < (unsigned)(hi[0] - lo[0]) &&
-                                (unsigned)t.cy < (unsigned)(hi[1] - lo[1]) &&
-                                (unsigned)t.cz < (unsigned)(hi[2] - lo[2]);
-                    }
-                    if (MODE == WALK_POINTS) {
-                        fn(pt[0], pt[1], wv, kk, klo);
-                    } else {
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-                            if (pt[h].own) {
-                                atomicMin(&B->rmin[rl], ur + h);
-                                atomicMax(&B->rmax[rl], ur + h);
-                            }
-                    }
+                    scount += __popcll(bal);
+                    continue;
                 }
+                const double rc2 = bperm_d(s2, rcd), rs2 = bperm_d(s2, rsd), in2 = bperm_d(s2, invd);
+                const float w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
+                const int ub = wrap ? jb + nj2 - jlo2 : jb - jlo2;   // offset of jb in the arc
+                segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rc2, rs2, in2,
+                                     w2, dl2, nj2, ls2, k2, jb, npts, ub, s2, klo, fn);
             }
             }  // pass2
-            if (MODE != WALK_POINTS) {
+            if (MODE == WALK_COUNT || MODE == WALK_FILL) {
                 wave_sync();
                 const int umin = B->rmin[lane], umax = B->rmax[lane];
                 const bool has = v1 && umax >= 0;
@@ -495,6 +570,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
         const float tot = wave_sum_dpp((float)ucount);
         if (lane == 0) P.tab_cnt[unit] = (int)tot;
     }
+    if (MODE == WALK_SEGCOUNT && lane == 0) P.seg_cnt[unit] = (int)scount;
 }
 
 }  // namespace
@@ -504,7 +580,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
 // ---------------------------------------------------------------------------
 constexpr int FWD_WAVES = 16;
 
-template <int IMG_DT, bool TAB>
+template <int IMG_DT, int TM>
 __global__ void __launch_bounds__(FWD_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
                int *__restrict__ klo_out)
@@ -569,7 +645,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                 racc = fmaf(sum, wv, racc);
             }
         };
-        walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
+        walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
                                            1.f, 1.f, klo, gather);
         if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
@@ -656,7 +732,7 @@ __device__ __forceinline__ void field_scale(double bound, float &g1, float &g2, 
     unscale = 1.0 / ((double)g1 * (double)g2);
 }
 
-template <bool TAB, bool CALIB>
+template <int TM, bool CALIB>
 __global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(3, 3)))
 srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc,
                float *__restrict__ rcal)
@@ -713,7 +789,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     if (a.own) scatter1(a, (wv * g1) * g2);
                     if (c.own) scatter1(c, (wv * g1) * g2);
                 };
-                walk_unit<false, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
                                                    nullptr, nullptr, 1.f, 1.f, klo, scatter);
             } else {
                 auto scatter1 = [&](const Pt &t, float wv) {
@@ -738,7 +814,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     if (a.own) scatter1(a, wv);
                     if (c.own) scatter1(c, wv);
                 };
-                walk_unit<true, TAB, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                walk_unit<true, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
                                                   nullptr, gp, g1, g2, klo, scatter);
             }
         }
@@ -801,38 +877,60 @@ arc_build_kernel(Problem P)
     auto none = [](const Pt &, const Pt &, float, int, int) {};
     for (int q = wave; q < P.nq; q += WAVES) {
         int klo = 0;
-        walk_unit<false, false, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
+        walk_unit<false, (MODE >= WALK_SEGCOUNT ? TM_ARC : TM_BOUNDS), MODE>(
+            P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
                                       nullptr, 1.f, 1.f, klo, none);
     }
+}
+
+template <int TM>
+static void fwd_launch(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
+                       hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz), block(FWD_WAVES * WAVE);
+    if (img_dtype == 0)
+        hipLaunchKernelGGL((srt_fwd_kernel<0, TM>), grid, block, 0, s, P, img, part, klo);
+    else
+        hipLaunchKernelGGL((srt_fwd_kernel<1, TM>), grid, block, 0, s, P, img, part, klo);
+}
+
+static int table_mode(const Problem &P)
+{
+    return P.seg != nullptr ? TM_SEG : (P.tab_arc != nullptr ? TM_ARC : TM_BOUNDS);
 }
 
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
                           hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(FWD_WAVES * WAVE);
-    const bool tab = P.tab_arc != nullptr;
-    if (img_dtype == 0) {
-        if (tab)
-            hipLaunchKernelGGL((srt_fwd_kernel<0, true>), grid, block, 0, s, P, img, part, klo);
-        else
-            hipLaunchKernelGGL((srt_fwd_kernel<0, false>), grid, block, 0, s, P, img, part, klo);
-    } else {
-        if (tab)
-            hipLaunchKernelGGL((srt_fwd_kernel<1, true>), grid, block, 0, s, P, img, part, klo);
-        else
-            hipLaunchKernelGGL((srt_fwd_kernel<1, false>), grid, block, 0, s, P, img, part, klo);
+    switch (table_mode(P)) {
+    case TM_SEG: fwd_launch<TM_SEG>(P, img, img_dtype, part, klo, s); break;
+    case TM_ARC: fwd_launch<TM_ARC>(P, img, img_dtype, part, klo, s); break;
+    default: fwd_launch<TM_BOUNDS>(P, img, img_dtype, part, klo, s); break;
     }
     return hipGetLastError();
+}
+
+template <bool CALIB>
+static void adj_launch(const Problem &P, const float *gp, double *acc, float *r, hipStream_t s)
+{
+    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
+    switch (table_mode(P)) {
+    case TM_SEG:
+        hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        break;
+    case TM_ARC:
+        hipLaunchKernelGGL((srt_adj_kernel<TM_ARC, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        break;
+    default:
+        hipLaunchKernelGGL((srt_adj_kernel<TM_BOUNDS, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        break;
+    }
 }
 
 hipError_t launch_srt_adj(const Problem &P, const float *gp, double *acc, void *img,
                           int img_dtype, hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
-    if (P.tab_arc != nullptr)
-        hipLaunchKernelGGL((srt_adj_kernel<true, false>), grid, block, 0, s, P, gp, acc, nullptr);
-    else
-        hipLaunchKernelGGL((srt_adj_kernel<false, false>), grid, block, 0, s, P, gp, acc, nullptr);
+    adj_launch<false>(P, gp, acc, nullptr, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_adj_gather(P, acc, img, img_dtype, s);
@@ -840,21 +938,20 @@ hipError_t launch_srt_adj(const Problem &P, const float *gp, double *acc, void *
 
 hipError_t launch_adj_calibrate(const Problem &P, float *r, hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
-    if (P.tab_arc != nullptr)
-        hipLaunchKernelGGL((srt_adj_kernel<true, true>), grid, block, 0, s, P, nullptr, nullptr, r);
-    else
-        hipLaunchKernelGGL((srt_adj_kernel<false, true>), grid, block, 0, s, P, nullptr, nullptr, r);
+    adj_launch<true>(P, nullptr, nullptr, r, s);
     return hipGetLastError();
 }
 
-hipError_t launch_arc_build(const Problem &P, int fill, hipStream_t s)
+hipError_t launch_arc_build(const Problem &P, int mode, hipStream_t s)
 {
     dim3 grid(P.nbx * P.nby * P.nbz), block(WAVES * WAVE);
-    if (fill)
-        hipLaunchKernelGGL(arc_build_kernel<WALK_FILL>, grid, block, 0, s, P);
-    else
-        hipLaunchKernelGGL(arc_build_kernel<WALK_COUNT>, grid, block, 0, s, P);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(arc_build_kernel<WALK_COUNT>, grid, block, 0, s, P); break;
+    case 1: hipLaunchKernelGGL(arc_build_kernel<WALK_FILL>, grid, block, 0, s, P); break;
+    case 2: hipLaunchKernelGGL(arc_build_kernel<WALK_SEGCOUNT>, grid, block, 0, s, P); break;
+    case 3: hipLaunchKernelGGL(arc_build_kernel<WALK_SEGFILL>, grid, block, 0, s, P); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ class _Geom(ctypes.Structure):
 
 
 class _Options(ctypes.Structure):
-    _fields_ = [("arc_table_bytes", ctypes.c_int64)]
+    _fields_ = [("arc_table_bytes", ctypes.c_int64), ("segment_table_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -124,9 +124,10 @@ def _dtype_code(t) -> int:
 class Plan:
     """Tables and workspace for one geometry on one device (oat_plan)."""
 
-    def __init__(self, geom: Geometry, device: int = 0, arc_table="auto"):
-        """arc_table: "auto" (build it if it fits in 40% of free device
-        memory), False / 0 (never), or a byte budget (oat_plan_options)."""
+    def __init__(self, geom: Geometry, device: int = 0, arc_table="auto", segment_table="auto"):
+        """arc_table, segment_table: "auto" (build it if it fits in 40% of
+        free device memory), False / 0 (never), or a byte budget
+        (oat_plan_options).  The segment table needs the arc table."""
         self.geom = geom
         self.device = int(device)
         self._xyz = np.ascontiguousarray(geom.det_xyz, dtype=np.float64).reshape(-1, 3)
@@ -137,13 +138,14 @@ class Plan:
                         self._xyz.shape[0], self._xyz.ctypes.data_as(dp),
                         self._area.ctypes.data_as(dp) if self._area is not None else dp(),
                         geom.n_t, geom.dt, geom.t0, geom.c0, geom.gamma)
-        if arc_table == "auto" or arc_table is None:
-            budget = -1
-        elif arc_table is False:
-            budget = 0
-        else:
-            budget = int(arc_table)
-        self._opt = _Options(budget)
+        def budget(v):
+            if v == "auto" or v is None:
+                return -1
+            if v is False:
+                return 0
+            return int(v)
+
+        self._opt = _Options(budget(arc_table), budget(segment_table))
         h = ctypes.c_void_p()
         _check(lib().oat_plan_create_ex(ctypes.byref(self._g), self.device,
                                         ctypes.byref(self._opt), ctypes.byref(h)))
@@ -162,10 +164,11 @@ class Plan:
             pass
 
     def stats(self) -> dict:
-        v = (ctypes.c_int64 * 10)()
-        _check(lib().oat_plan_stats(self._h, v, 10))
+        v = (ctypes.c_int64 * 13)()
+        _check(lib().oat_plan_stats(self._h, v, 13))
         keys = ("rings", "bricks", "brick", "window", "workspace_bytes", "table_bytes",
-                "arc_table_bytes", "arc_table_entries", "arc_table_build_us", "adj_calibration_us")
+                "arc_table_bytes", "arc_table_entries", "arc_table_build_us", "adj_calibration_us",
+                "segment_table_bytes", "segment_table_entries", "segment_table_build_us")
         return dict(zip(keys, [int(x) for x in v]))
 
     def _prep(self, t, shape):

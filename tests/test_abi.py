@@ -75,10 +75,14 @@ def test_negative_table_budget_is_rejected():
     p = oat._Geom(g.nx, g.ny, g.nz, g.dx, g.x0, g.y0, g.z0, xyz.shape[0], xyz.ctypes.data_as(dp),
                   dp(), g.n_t, g.dt, g.t0, g.c0, g.gamma)
     h = ctypes.c_void_p()
-    opt = oat._Options(-2)
+    opt = oat._Options(-2, -1)
     assert oat.lib().oat_plan_create_ex(ctypes.byref(p), 0, ctypes.byref(opt),
                                         ctypes.byref(h)) == oat.OAT_ERR_ARG
     assert not h.value and "arc_table_bytes" in oat.last_error()
+    opt = oat._Options(-1, -3)
+    assert oat.lib().oat_plan_create_ex(ctypes.byref(p), 0, ctypes.byref(opt),
+                                        ctypes.byref(h)) == oat.OAT_ERR_ARG
+    assert not h.value and "segment_table_bytes" in oat.last_error()
 
 
 def test_null_arguments():

@@ -156,7 +156,12 @@ RAGGED = [
 ]
 
 
-@pytest.mark.parametrize("table", [True, False])
+TABLES = {"segments": dict(arc_table="auto", segment_table="auto"),
+          "arcs": dict(arc_table="auto", segment_table=False),
+          "bounds": dict(arc_table=False, segment_table=False)}
+
+
+@pytest.mark.parametrize("table", list(TABLES))
 @pytest.mark.parametrize("case", range(len(RAGGED)))
 def test_ragged_grids(case, table, Plan):
     c = RAGGED[case]
@@ -166,13 +171,15 @@ def test_ragged_grids(case, table, Plan):
                           synth.centred_origin(ny, c["dx"]) + c["off"][1],
                           synth.centred_origin(nz, c["dx"]) + c["off"][2], det, c["K"], c["dt"],
                           c["t0"], 1.5, 1.3)
-    _say(f"[gpu] ragged case {case} arc table {table} {c}")
+    _say(f"[gpu] ragged case {case} tables {table} {c}")
     gd = geom.as_dict()
     rng = np.random.default_rng(case)
     img = rng.uniform(0, 1, size=geom.shape)
     img = img.astype(np.float32).astype(np.float64)
-    plan = Plan(geom, 0, arc_table="auto" if table else False)
-    assert (plan.stats()["arc_table_bytes"] > 0) == table
+    plan = Plan(geom, 0, **TABLES[table])
+    st = plan.stats()
+    assert (st["arc_table_bytes"] > 0) == (table != "bounds")
+    assert (st["segment_table_bytes"] > 0) == (table == "segments")
     g = _np(plan.project(_t(img), srt_only=True))
     assert rel(g, ref.srt(gd, img)) < 1e-6
     p = _np(plan.project(_t(img)))
@@ -219,30 +226,34 @@ def test_repeat_runs(Plan):
 
 
 @pytest.mark.parametrize("seed", [0, 3])
-def test_arc_table_and_arc_bounds_agree(seed, Plan):
-    """The plan's arc table (tight arcs of the owned points) and the kernels'
-    own arc bounds enumerate the same points: G and G^T agree to FP32
-    summation order, and both match the oracle."""
+def test_table_paths_agree(seed, Plan):
+    """The plan's segment table, its arc table (tight arcs of the owned
+    points) and the kernels' own arc bounds enumerate the same points: G
+    agrees to FP32 summation order, G^T bit for bit (the same integer terms
+    and the same calibrated scales), and all match the oracle."""
     geom, _, img = synth.config_small(seed)
-    _say(f"[gpu] arc table vs arc bounds seed {seed}")
-    pt = Plan(geom, 0)
+    _say(f"[gpu] segment table vs arc table vs arc bounds seed {seed}")
+    ps = Plan(geom, 0)
+    pt = Plan(geom, 0, segment_table=False)
     pn = Plan(geom, 0, arc_table=False)
-    st, sn = pt.stats(), pn.stats()
+    ss, st, sn = ps.stats(), pt.stats(), pn.stats()
+    assert ss["segment_table_bytes"] > 0 and ss["segment_table_entries"] > 0
     assert st["arc_table_bytes"] > 0 and st["arc_table_entries"] > 0
-    assert sn["arc_table_bytes"] == 0
+    assert st["segment_table_bytes"] == 0
+    assert sn["arc_table_bytes"] == 0 and sn["segment_table_bytes"] == 0
     assert Plan(geom, 0, arc_table=1).stats()["arc_table_bytes"] == 0   # budget too small
+    assert Plan(geom, 0, segment_table=1).stats()["segment_table_bytes"] == 0
     x = _t(img)
-    gt, gn = _np(pt.project(x, srt_only=True)), _np(pn.project(x, srt_only=True))
-    e = rel(gt, gn)
-    _say(f"  G table vs bounds rel {e:.3e}")
-    assert e < 1e-6
+    gs, gt, gn = (_np(p.project(x, srt_only=True)) for p in (ps, pt, pn))
+    e1, e2 = rel(gs, gn), rel(gt, gn)
+    _say(f"  G segments vs bounds rel {e1:.3e}, arcs vs bounds rel {e2:.3e}")
+    assert e1 < 1e-6 and e2 < 1e-6
     assert rel(gn, ref.srt(geom.as_dict(), img)) < 1e-6
     rng = np.random.default_rng(400 + seed)
     y = _t(rng.normal(size=(geom.n_det, geom.n_t)))
-    at, an = _np(pt.backproject(y, srt_only=True)), _np(pn.backproject(y, srt_only=True))
-    e = rel(at, an)
-    _say(f"  G^T table vs bounds rel {e:.3e}")
-    assert e < 1e-6
+    a_s, a_t, a_n = (_np(p.backproject(y, srt_only=True)) for p in (ps, pt, pn))
+    _say(f"  G^T segments vs bounds rel {rel(a_s, a_n):.3e}, arcs vs bounds rel {rel(a_t, a_n):.3e}")
+    assert np.array_equal(a_s, a_n) and np.array_equal(a_t, a_n)
 
 
 def test_backproject_with_wide_dynamic_range(Plan):
