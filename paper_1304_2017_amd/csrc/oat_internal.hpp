@@ -19,15 +19,9 @@ constexpr int BOX3 = BOX * BOX * BOX;          // dense box in HBM (G^T brick ou
 constexpr int WAVES = 8;                      // waves per workgroup (srt kernels)
 constexpr int WAVE = 64;
 constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
-// G^T: ADJ_WAVES waves per brick workgroup; transducers in windows of
-// ADJ_WINDOW = ADJ_ROUNDS transducers per wave, one fixed-point scale and one
-// flush of the LDS box per window.
-constexpr int ADJ_WAVES = 12;
-#ifndef OAT_ADJ_ROUNDS
-#define OAT_ADJ_ROUNDS 4
-#endif
-constexpr int ADJ_ROUNDS = OAT_ADJ_ROUNDS;
-constexpr int ADJ_WINDOW = ADJ_WAVES * ADJ_ROUNDS;
+// G^T takes the transducers in windows of ADJ_WINDOW, with one fixed-point
+// scale and one flush of its LDS box per window.
+constexpr int ADJ_WINDOW = 48;
 __host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).

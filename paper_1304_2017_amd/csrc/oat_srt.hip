@@ -13,6 +13,8 @@
 // Every point's position is a deterministic function of (q, k, i, j) and
 // the same code evaluates it in both kernels, so each point belongs to
 // exactly one brick of G and the adjoint uses the identical point set.
+#include <type_traits>
+
 #include "oat_internal.hpp"
 #include "oat_geom.hpp"
 
@@ -152,15 +154,20 @@ __device__ __forceinline__ bool level_item(Level &L, int F, int &src, int &local
 constexpr int CAP1 = 64;   // candidate rings per shell per pass (64 * 64 bits)
 constexpr int CAP2 = 16;   // segments per ring per pass (64 * 16 bits)
 
-// Per-wave LDS scratch.
-struct WaveLds {
-    float4 stage[64][3];   // per-segment data handed from level 2 to level 3
+// Per-wave LDS scratch of the point level: per-segment data handed to the
+// points, and the level-3 head bitmap and producer table.
+struct SegLds {
+    float4 stage[64][3];
+    unsigned bits3[64];
+    int prod3[64];
+};
+
+// Per-wave LDS scratch of the full walk (shell and ring levels too).
+struct WaveLds : SegLds {
     unsigned bits1[128];
     unsigned bits2[32];
-    unsigned bits3[64];
     int prod1[64];
     int prod2[64];
-    int prod3[64];
 };
 
 // Cell box of brick b: cells lo .. hi-1 per axis.  The bricks partition the
@@ -212,7 +219,7 @@ struct BuildLds {
 // are the arc-table passes' offset of jb in the ring's arc and the ring's
 // level-1 lane.
 template <int MODE, class Fn>
-__device__ __forceinline__ void segment_points(const Problem &P, WaveLds &W, BuildLds *B,
+__device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, BuildLds *B,
                                                const int lo[3], const int hi[3],
                                                const double uq[3], const double e3[3],
                                                const double e1d[3], const double e2d[3],
@@ -322,9 +329,9 @@ __device__ __forceinline__ void segment_points(const Problem &P, WaveLds &W, Bui
 // WALK_POINTS mode fn is called per window of 64 lanes with the lane's two
 // consecutive points of one segment (Pt each), their weight, their shell
 // index and the unit's first shell.
-template <bool ADJ, int TM, int MODE, class Fn>
+template <bool ADJ, int TM, int MODE, class WL, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
-                                          const int hi[3], WaveLds &W, BuildLds *B,
+                                          const int hi[3], WL &W, BuildLds *B,
                                           const float *gp, float gscale, float gscale2,
                                           int &klo_out, Fn &&fn)
 {
@@ -373,9 +380,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                                  rr.inv_nj, w2, rr.delta, rr.nj, rr.lshift, k2, jb, npts, 0, 0,
                                  klo, fn);
         }
-        return;
-    }
-
+    } else {
     ArcUnit U;
     if (!TAB) arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
     const float D = TAB ? 0.f : sqrtf(U.rhov2 + U.V3 * U.V3);
@@ -571,6 +576,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
         if (lane == 0) P.tab_cnt[unit] = (int)tot;
     }
     if (MODE == WALK_SEGCOUNT && lane == 0) P.seg_cnt[unit] = (int)scount;
+    }  // TM != TM_SEG
 }
 
 }  // namespace
@@ -659,7 +665,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // ---------------------------------------------------------------------------
 // G^T: each brick takes the same cells (hence the same points) as in G and
 // accumulates their trilinear weights w g' psi in an LDS box of fixed-point
-// integers, 12 waves sharing the box.
+// integers, 12 or 16 waves sharing the box.
 //
 // One 64-bit word per cell column holds two 32-bit fields: node x in the low
 // half and node x + 1 in the high half, so a point adds its 8 corner weights
@@ -670,8 +676,8 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // range the word decodes exactly: lo = low 32 bits (signed), hi = (word - lo)
 // >> 32 (arithmetic).
 //
-// The transducers are taken in windows of ADJ_WINDOW = ADJ_WAVES * ADJ_ROUNDS
-// (wave w takes transducers window * ADJ_WINDOW + w + ADJ_WAVES r).  A window's
+// The transducers are taken in windows of ADJ_WINDOW = 48 (with NW waves,
+// wave w takes transducers window * 48 + w + NW r, r < 48 / NW).  A window's
 // weights are multiplied by S = 0.99 * 2^31 / (R G) and rounded to the nearest
 // integer (v_cvt_rpi_i32_f32), where
 //   R(brick, window) = max over box nodes of sum psi w over the window's
@@ -732,21 +738,27 @@ __device__ __forceinline__ void field_scale(double bound, float &g1, float &g2, 
     unscale = 1.0 / ((double)g1 * (double)g2);
 }
 
-template <int TM, bool CALIB>
-__global__ void __launch_bounds__(ADJ_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(3, 3)))
+template <int TM, bool CALIB, int NW>
+__global__ void __launch_bounds__(NW *WAVE) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc,
                float *__restrict__ rcal)
 {
+    // The segment-table walk needs only the point level's LDS, which leaves
+    // room for 16 waves beside the box.
+    static_assert(ADJ_WINDOW % NW == 0, "window must be whole rounds");
+    static_assert(NW <= 12 || TM == TM_SEG, "16 waves fit the LDS only on the segment path");
+    constexpr int ROUNDS = ADJ_WINDOW / NW;
+    using WL = typename std::conditional<TM == TM_SEG, SegLds, WaveLds>::type;
     __shared__ unsigned long long box[BOX_WORDS];
-    __shared__ WaveLds wl[ADJ_WAVES];
-    __shared__ unsigned long long wred[ADJ_WAVES];
+    __shared__ WL wl[NW];
+    __shared__ unsigned long long wred[NW];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
     for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
     __syncthreads();
     const int wave = threadIdx.x / WAVE, lane = lane_id();
-    WaveLds &W = wl[wave];
+    WL &W = wl[wave];
     const int nwin = adj_windows(P.nq);
     for (int win = 0; win < nwin; ++win) {
         const int q0 = win * ADJ_WINDOW;
@@ -761,8 +773,8 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
             for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
             field_scale((double)P.adj_r[(size_t)b * nwin + win] * (double)m, g1, g2, unscale);
         }
-        for (int r = 0; r < ADJ_ROUNDS; ++r) {
-            const int q = q0 + r * ADJ_WAVES + wave;
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int q = q0 + r * NW + wave;
             if (q >= P.nq) break;
             int klo = 0;
             if (CALIB) {
@@ -830,7 +842,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
             __syncthreads();
             if (threadIdx.x == 0) {
                 unsigned long long mm = 0ull;
-                for (int w = 0; w < ADJ_WAVES; ++w) mm = max(mm, wred[w]);
+                for (int w = 0; w < NW; ++w) mm = max(mm, wred[w]);
                 // rounded up: (float) may round down, and each of the at most
                 // 2^20 terms of a node lost at most half a unit
                 const double r = ((double)mm + 1048576.0) * unscale;
@@ -910,19 +922,26 @@ hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, floa
     return hipGetLastError();
 }
 
+// 16 waves on the segment path, 12 otherwise; the calibration always takes
+// 12 (its per-node box needs more registers), which does not change R: a
+// window's node sums do not depend on how its transducers are split among
+// the waves.
 template <bool CALIB>
 static void adj_launch(const Problem &P, const float *gp, double *acc, float *r, hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(ADJ_WAVES * WAVE);
+    dim3 grid(P.nbx * P.nby * P.nbz), b12(12 * WAVE), b16(16 * WAVE);
     switch (table_mode(P)) {
     case TM_SEG:
-        hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        if (CALIB)
+            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, true, 12>), grid, b12, 0, s, P, gp, acc, r);
+        else
+            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, false, 16>), grid, b16, 0, s, P, gp, acc, r);
         break;
     case TM_ARC:
-        hipLaunchKernelGGL((srt_adj_kernel<TM_ARC, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        hipLaunchKernelGGL((srt_adj_kernel<TM_ARC, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r);
         break;
     default:
-        hipLaunchKernelGGL((srt_adj_kernel<TM_BOUNDS, CALIB>), grid, block, 0, s, P, gp, acc, r);
+        hipLaunchKernelGGL((srt_adj_kernel<TM_BOUNDS, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r);
         break;
     }
 }
