@@ -240,49 +240,45 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
     double cr, sr;
     sincos_turns_d((double)jref * in2, cr, sr);
     float Pl[3];
-    int dpk = 0;
+    int dc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double pa = fma(rc2, e3[a], uq[a]) + rs2 * fma(cr, e1d[a], sr * e2d[a]);
         const double ph = floor(pa);
         Pl[a] = (float)(pa - ph);
         // clamped offsets only occur for points far outside the box
-        const int db = min(max((int)ph - lo[a], -512), 511) + 512;
-        dpk |= db << (10 * a);
+        dc[a] = min(max((int)ph - lo[a], -512), 511);
     }
     const float xa = (float)(rs2 * cr), xb = (float)(rs2 * sr);
     const int np = v2 ? npts : 0;
-    // jb - jref in [-16, 16], npts <= 32, shell index < 4096
+    // jb - jref in [-16, 16], npts <= 32, shell index < 4096 (n_t <= 4096)
     const int meta = (jb - jref + 64) | (np << 7) | (k2 << 13);
     // The segment's data goes to the wave's LDS stage, where the lanes of its
     // points read it (a broadcast read; cheaper than one bpermute per value
-    // on this part).
+    // on this part).  The cell offsets are stored unpacked: the point level
+    // reads them with the same three 16-byte reads.
     wave_sync();
-    W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(dpk));
-    W.stage[lane][1] = make_float4(xa, xb, dl2, __int_as_float(meta));
-    W.stage[lane][2] = make_float4(w2, __int_as_float(rl), __int_as_float(ub), 0.f);
+    W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(meta));
+    W.stage[lane][1] = make_float4(xa, xb, dl2, w2);
+    W.stage[lane][2] = make_float4(__int_as_float(dc[0]), __int_as_float(dc[1]),
+                                   __int_as_float(dc[2]), __int_as_float(rl | (ub << 8)));
     // Level 3: each lane takes two consecutive points of a segment
     // (level_begin orders the stage writes before the reads).
     level_begin<5>(L3, (np + 1) >> 1);
     for (int F3 = 0; F3 < L3.total; F3 += WAVE) {
         int s3, pr;
         const bool v3 = level_item(L3, F3, s3, pr);
-        const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1];
+        const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1], r2 = W.stage[s3][2];
         const float p0 = r0.x, p1 = r0.y, p2 = r0.z;
-        const int dp = __float_as_int(r0.w);
-        const float qa = r1.x, qb = r1.y, dd = r1.z;
-        const int mt = __float_as_int(r1.w);
-        float wv = 0.f;
+        const int mt = __float_as_int(r0.w);
+        const float qa = r1.x, qb = r1.y, dd = r1.z, wv = r1.w;
+        const int d0 = __float_as_int(r2.x), d1 = __float_as_int(r2.y), d2 = __float_as_int(r2.z);
         int rlp = 0, ur = 0;
-        if (MODE == WALK_POINTS) {
-            wv = W.stage[s3][2].x;
-        } else {
-            const float4 r2 = W.stage[s3][2];
-            rlp = __float_as_int(r2.y);
-            ur = __float_as_int(r2.z) + 2 * pr;
+        if (MODE != WALK_POINTS) {
+            const int ru = __float_as_int(r2.w);
+            rlp = ru & 255;
+            ur = (ru >> 8) + 2 * pr;
         }
-        const int d0 = (dp & 1023) - 512, d1 = ((dp >> 10) & 1023) - 512,
-                  d2 = ((dp >> 20) & 1023) - 512;
         const int npp = (mt >> 7) & 63, kk = mt >> 13;
         const int djA = (mt & 127) - 64 + 2 * pr;
         Pt pt[2];
@@ -808,12 +804,13 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     unsigned long long *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
                                              __umul24((unsigned)t.cy, BOX_SY) + t.cx;
                     unsigned long long *pz = pb + BOX_SZ;
-                    const float gx = 1.f - t.fx, gy = 1.f - t.fy, gz = 1.f - t.fz;
-                    const float w00 = gy * gz * wv, w01 = t.fy * gz * wv, w10 = gy * t.fz * wv,
-                                w11 = t.fy * t.fz * wv;
+                    // trilinear corner weights, (1 - f) v formed as v - f v
+                    const float a = fmaf(-t.fz, wv, wv), c = t.fz * wv;
+                    const float w00 = fmaf(-t.fy, a, a), w01 = t.fy * a, w10 = fmaf(-t.fy, c, c),
+                                w11 = t.fy * c;
                     // fields (node x, node x + 1) of one word
                     auto add2 = [&](unsigned long long *p, float wyz) {
-                        const int l = cvt_rne(gx * wyz), h = cvt_rne(t.fx * wyz);
+                        const int l = cvt_rne(fmaf(-t.fx, wyz, wyz)), h = cvt_rne(t.fx * wyz);
                         atomicAdd(p, (unsigned long long)(long long)l +
                                          ((unsigned long long)(unsigned)h << 32));
                     };
