@@ -8,7 +8,7 @@
  *
  *   oat_project      p = H alpha = D G alpha   Sec. II.B.1: Eq. (dis_srt) then Eq. (dis_g2p),
  *                                              point-like transducers (H^e = I)
- *   oat_backproject  alpha' = H^T y = G^T D^T y   Sec. II.C, the exact adjoint of oat_project
+ *   oat_backproject  alpha' = H^T y = G^T D^T y   Sec. II.B.3, the exact adjoint of oat_project
  *   oat_fbp          alpha_fbp from p          Sec. III.B, Eq. (disfbp)
  *
  * Units: lengths in mm, times in microseconds.

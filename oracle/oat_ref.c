@@ -13,7 +13,7 @@
  *   G    discrete spherical Radon transform       Sec. II.B.1, Eq. (dis_srt),
  *                                                  Appendix Eqs. (srtlocal)-(srtdislocal)
  *   D    time derivative of g/t                   Eq. (g2p) and Eq. (dis_g2p)
- *   D^T, G^T  exact adjoints                      Sec. II.C (adjoint operators)
+ *   D^T, G^T  exact adjoints                      Sec. II.B.3 (adjoint operators)
  *   FBP  discretised spherical-surface FBP        Eq. (fbp), Eq. (linearint), Eq. (disfbp)
  *
  * Units: lengths in mm, times in us.  Image alpha[iz][iy][ix], node
@@ -221,7 +221,7 @@ static void scatter_point(void *vctx, double x, double y, double z, double w)
 }
 
 /* alpha'[n] = sum_{q,k} g'[q,k] sum_{i,j} w_{k,i} psi_n(x_{q,k,i,j})
- * (adjoint of G, Sec. II.C).  Only rows listed in qsel are used; gp is
+ * (adjoint of G, Sec. II.B.3).  Only rows listed in qsel are used; gp is
  * nsel x K.  Each thread scatters into its own image, the images are then
  * summed in thread order. */
 void ref_srt_adj_rows(const ref_geom *G, const double *gp, const int *qsel,
@@ -289,7 +289,7 @@ void ref_diff(const ref_geom *G, int nrows, const double *g, double *p)
 }
 
 /* g'_k = Gamma/(4 pi c0^2)/(2 dt) * (y_{k-1} - y_{k+1}) / t_k, zero where
- * t_k <= 0 and y_{-1} = y_K = 0: the transpose of ref_diff (Sec. II.C). */
+ * t_k <= 0 and y_{-1} = y_K = 0: the transpose of ref_diff (Sec. II.B.3). */
 void ref_diff_adj(const ref_geom *G, int nrows, const double *y, double *gp)
 {
     double coef = G->gamma / (4.0 * M_PI * G->c0 * G->c0) / (2.0 * G->dt);

@@ -3,6 +3,9 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
 CPU-baseline leg of the benchmark, never by the product package.
 
+The transducer-response functions at the end (eir, eir_adj, deconvolve) are
+plain numpy.
+
 All arrays are numpy float64, C-contiguous.  Geometry is passed as a dict
 with keys nx, ny, nz, dx, x0, y0, z0, det_xyz (Q x 3), det_area (Q or None),
 n_t, dt, t0, c0, gamma.
@@ -180,3 +183,84 @@ def max_threads():
 def set_threads(n: int):
     """OpenMP threads of later calls (timing only)."""
     lib().ref_set_threads(int(n))
+
+
+# ---------------------------------------------------------------------------
+# Transducer electrical impulse response (EIR), plain numpy in FP64.
+# ---------------------------------------------------------------------------
+def eir_matrix(h, K):
+    """K x K matrix of Eq. (EIR): M[k, kappa] = h[k - 1 - kappa], with
+    h[m] = 0 outside [0, len(h)).  (The printed index k - 1 - kappa delays the
+    response by one sample; taken as printed.)"""
+    h = np.asarray(h, dtype=np.float64)
+    k = np.arange(K)[:, None]
+    kappa = np.arange(K)[None, :]
+    m = k - 1 - kappa
+    inside = (m >= 0) & (m < h.size)
+    return np.where(inside, h[np.clip(m, 0, h.size - 1)], 0.0)
+
+
+def eir(h, p):
+    """H^e p, Eq. (EIR), applied to every row of p [Q][K]."""
+    p = np.asarray(p, dtype=np.float64)
+    return p @ eir_matrix(h, p.shape[-1]).T
+
+
+def eir_adj(h, u):
+    """H^e^T u from the adjoint formula of Sec. II.B.3:
+    p'[k] = sum_kappa h[kappa - 1 - k] u[kappa], for every row of u."""
+    h = np.asarray(h, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    K = u.shape[-1]
+    k = np.arange(K)[:, None]
+    kappa = np.arange(K)[None, :]
+    m = kappa - 1 - k
+    inside = (m >= 0) & (m < h.size)
+    A = np.where(inside, h[np.clip(m, 0, h.size - 1)], 0.0)   # A[k, kappa]
+    return u @ A.T
+
+
+def hann(f, fc):
+    """Hann window of the deconvolution (Sec. IV.B, experimental data):
+    W(f) = (1 - cos(pi (fc - |f|) / fc)) / 2 for |f| <= fc, 0 beyond."""
+    af = np.abs(np.asarray(f, dtype=np.float64))
+    return np.where(af <= fc, 0.5 * (1.0 - np.cos(np.pi * (fc - af) / fc)), 0.0)
+
+
+def deconv_length(K):
+    """FFT length of the deconvolution: the power of two >= 2K, so the
+    division undoes the linear (not circular) convolution of a K-sample
+    record."""
+    n = 1
+    while n < 2 * K:
+        n *= 2
+    return n
+
+
+def deconvolve(h, u, dt, fc):
+    """Fourier deconvolution with a Hann window (Sec. IV.B): per row of u,
+    p~(f) = u~(f) W(f) / h~(f), h~ the transform of Eq. (EIR)'s response
+    (one-sample delay included); bins with h~ = 0 give 0.  Rows are zero-padded
+    to deconv_length(K); the first K samples of the inverse are returned."""
+    u = np.asarray(u, dtype=np.float64)
+    K = u.shape[-1]
+    N = deconv_length(K)
+    hd = np.zeros(N)
+    hd[1:1 + len(h)] = h
+    Ht = np.fft.fft(hd)
+    W = hann(np.fft.fftfreq(N, d=dt), fc)
+    Ut = np.fft.fft(u, n=N, axis=-1)
+    nz = Ht != 0
+    filt = np.zeros(N, dtype=np.complex128)
+    filt[nz] = W[nz] / Ht[nz]
+    return np.fft.ifft(Ut * filt, axis=-1).real[..., :K]
+
+
+def project_eir(geom, h, alpha, rows=None):
+    """H^e D G alpha (Eq. (EIR) after Eq. (dis_g2p)), the listed rows."""
+    return eir(h, project(geom, alpha, rows=rows))
+
+
+def backproject_eir(geom, h, y, rows=None):
+    """G^T D^T H^e^T y using the listed rows of y."""
+    return backproject(geom, eir_adj(h, y), rows=rows)

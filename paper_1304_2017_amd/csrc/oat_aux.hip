@@ -1,5 +1,5 @@
 // Data-side kernels on gfx950: the reduction of G's brick partials fused
-// with D (Eq. (dis_g2p)), its transpose D^T (Sec. II.C), the gather of G^T's
+// with D (Eq. (dis_g2p)), its transpose D^T (Sec. II.B.3), the gather of G^T's
 // brick boxes into the image, and the voxel-driven filtered backprojection
 // of Eq. (disfbp).
 #include "oat_internal.hpp"

@@ -2,7 +2,7 @@
 // gfx950 (CDNA4, wave64).
 //
 // G  (Eq. (dis_srt)): g[q,k] = sum_{i,j} w_{k,i} Psi(alpha; x_{q,k,i,j})
-// G^T (adjoint, Sec. II.C): alpha'_n = sum_{q,k,i,j} w_{k,i} g'[q,k] psi_n(x_{q,k,i,j})
+// G^T (adjoint, Sec. II.B.3): alpha'_n = sum_{q,k,i,j} w_{k,i} g'[q,k] psi_n(x_{q,k,i,j})
 //
 // The image is cut into bricks of BRICK^3 cells.  A workgroup owns one brick
 // and keeps its (BRICK+2)^3 nodes in LDS: the image values for G, a 64-bit

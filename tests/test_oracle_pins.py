@@ -143,7 +143,7 @@ def test_project_matches_dense_DG(tiny):
 
 
 # ---------------------------------------------------------------------------
-# Adjoint identities (Sec. II.C): <Hx, y> = <x, H^T y> in FP64.
+# Adjoint identities (Sec. II.B.3): <Hx, y> = <x, H^T y> in FP64.
 # ---------------------------------------------------------------------------
 def test_adjoint_identities_fp64():
     geom, _, _ = synth.config_small(0)
