@@ -255,6 +255,34 @@ def learned_run(n_phantoms, epochs, iters):
                       loss_first_epoch=loss_first, loss_last_epoch=loss_last))), flush=True)
 
 
+def eir_run(reps):
+    """H and H^T with a 64-tap EIR (Eq. (EIR)), and the Hann-window
+    deconvolution (f_c = 5 MHz) followed by FBP, at the 256^3 / 2048 / 1024
+    workload; one JSON line."""
+    import torch
+    from paper_1304_2017_amd import synth
+    from paper_1304_2017_amd.oat import Plan
+    geom, _, img = synth.config_large(0, dtype=np.float32)
+    plan = Plan(geom, 0)
+    x = torch.from_numpy(img).cuda()
+    p = torch.empty(plan.data_shape, device="cuda")
+    a = torch.empty(plan.image_shape, device="cuda")
+    d = torch.empty(plan.data_shape, device="cuda")
+    t_h0 = time_op(lambda: plan.project(x, out=p), reps)
+    t_ht0 = time_op(lambda: plan.backproject(p, out=a), reps)
+    h = synth.gamma_pulse(64, geom.dt, 0.1)
+    plan.set_eir(h)
+    t_h = time_op(lambda: plan.project(x, out=p), reps)
+    t_ht = time_op(lambda: plan.backproject(p, out=a), reps)
+    t_dec = time_op(lambda: plan.deconvolve(p, 5.0, out=d), reps)
+    t_fbp = time_op(lambda: plan.fbp(d, out=a), reps)
+    print(json.dumps(dict(
+        workload="256^3 / 2048 transducers / 1024 samples, 64-tap gamma-pulse EIR (tau 0.1 us)",
+        H_ms=t_h * 1e3, HT_ms=t_ht * 1e3, H_no_eir_ms=t_h0 * 1e3, HT_no_eir_ms=t_ht0 * 1e3,
+        deconvolve_ms=t_dec * 1e3, fbp_ms=t_fbp * 1e3, fft_length=2 * 1024, f_cut_mhz=5.0,
+        reps=reps)), flush=True)
+
+
 def matrix(reps):
     """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
     transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
@@ -311,6 +339,8 @@ def main():
                     help="train the learned preconditioner and time PLS-TV plain vs learned")
     ap.add_argument("--phantoms", type=int, default=64, help="training phantoms (--learned)")
     ap.add_argument("--epochs", type=int, default=5, help="training epochs (--learned)")
+    ap.add_argument("--eir", action="store_true",
+                    help="time H, H^T with a 64-tap EIR and the deconvolution + FBP at 256^3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -329,6 +359,9 @@ def main():
         return
     if args.learned:
         learned_run(args.phantoms, args.epochs, args.iters)
+        return
+    if args.eir:
+        eir_run(max(args.steps, 3))
         return
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")

@@ -6,10 +6,13 @@
  * reconstruction in three-dimensional optoacoustic tomography on graphics
  * processing units"):
  *
- *   oat_project      p = H alpha = D G alpha   Sec. II.B.1: Eq. (dis_srt) then Eq. (dis_g2p),
- *                                              point-like transducers (H^e = I)
- *   oat_backproject  alpha' = H^T y = G^T D^T y   Sec. II.B.3, the exact adjoint of oat_project
+ *   oat_project      p = H alpha = H^e D G alpha   Sec. II.B.1: Eq. (dis_srt), Eq. (dis_g2p),
+ *                                              then Eq. (EIR) if the plan has an EIR
+ *                                              (point-like transducers otherwise: H^e = I)
+ *   oat_backproject  alpha' = H^T y = G^T D^T H^e^T y   Sec. II.B.3, the exact adjoint
  *   oat_fbp          alpha_fbp from p          Sec. III.B, Eq. (disfbp)
+ *   oat_deconvolve   p from measured u         Sec. IV.B: Fourier deconvolution of the
+ *                                              EIR with a Hann window, before oat_fbp
  *
  * Units: lengths in mm, times in microseconds.
  *
@@ -169,6 +172,31 @@ int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void
  * outside [0, n_t).  pres: device [n_det][n_t]; img: device [nz][ny][nx]. */
 int oat_fbp(oat_plan *plan, const void *pres, oat_dtype pres_dtype, void *img,
             oat_dtype img_dtype, uint32_t flags, void *stream);
+
+/* Electrical impulse response of the transducers, Eq. (EIR):
+ * [H^e p]_{q,k} = sum_{kappa=0}^{n_t-1} h[k-1-kappa] p_{q,kappa}, with h[m] = 0
+ * outside [0, n_taps) (the printed index, a one-sample delay).  From then on
+ * oat_project returns H^e D G alpha and oat_backproject G^T D^T H^e^T y, with
+ * H^e^T from the adjoint formula of Sec. II.B.3 (OAT_FLAG_SRT_ONLY still
+ * returns G and G^T alone).  h: host array of n_taps finite doubles,
+ * h[m] = dt h^e(m dt), copied; 1 <= n_taps <= n_t.  n_taps = 0 removes the
+ * EIR (h may be NULL).  Synchronous: waits for the device, so no call on the
+ * plan may be in flight.  Sums are FP64, with one rounding to the output
+ * type.  OAT_ERR_ARG on bad sizes or non-finite taps. */
+int oat_plan_set_eir(oat_plan *plan, const double *h, int n_taps);
+
+/* Fourier deconvolution of the plan's EIR with a Hann window (Sec. IV.B),
+ * per transducer row: p~(f) = u~(f) W(f) / h~(f), where
+ *   W(f) = (1 - cos(pi (f_cut - |f|) / f_cut)) / 2 for |f| <= f_cut, 0 beyond,
+ *   h~   = the transform of the response of Eq. (EIR), one-sample delay included,
+ * and bins where h~ = 0 give 0.  Each record is zero-padded to N = the power
+ * of two >= 2 n_t, so the division undoes the linear (not circular)
+ * convolution, and the first n_t samples of the inverse transform are
+ * returned.  Transforms in FP64.  f_cut in cycles per time unit (MHz when
+ * times are in microseconds), > 0.  u, p: device [n_det][n_t], may not
+ * alias.  Asynchronous on `stream`.  OAT_ERR_ARG when the plan has no EIR. */
+int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oat_dtype p_dtype,
+                   double f_cut, uint32_t flags, void *stream);
 
 /* Thread-local, NUL-terminated description of the last non-OK status
  * returned on this thread ("" if none).  Valid until the next call. */

@@ -127,5 +127,15 @@ hipError_t launch_adj_gather(const Problem &P, const double *acc, void *img, int
                              hipStream_t s);
 hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img,
                       int img_dtype, hipStream_t s);
+// EIR (oat_eir.hip): H^e (adjoint = 0) or its transpose on every data row;
+// the transform of the delayed response on the N-point grid and the FFT
+// twiddles; the Hann-window deconvolution (F is a workspace of N values).
+hipError_t launch_eir(const Problem &P, const void *in, int in_dt, void *out, int out_dt,
+                      const double *h, int taps, int adjoint, hipStream_t s);
+hipError_t launch_eir_spectrum(const double *h, int taps, int N, double2 *Ht, double2 *tw,
+                               hipStream_t s);
+hipError_t launch_deconvolve(const Problem &P, const void *u, int u_dt, void *p, int p_dt,
+                             const double2 *Ht, const double2 *tw, double2 *F, int N, double fc,
+                             hipStream_t s);
 
 }  // namespace oat

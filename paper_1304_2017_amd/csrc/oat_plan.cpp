@@ -70,6 +70,12 @@ struct oat_plan {
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
+    double *d_eir_h = nullptr;        // EIR taps [eir_taps]
+    double2 *d_eir_spec = nullptr;    // transform of the delayed EIR [eir_n]
+    double2 *d_eir_tw = nullptr;      // FFT twiddles [eir_n / 2]
+    double2 *d_eir_filt = nullptr;    // deconvolution filter of a call [eir_n]
+    float *d_eirbuf = nullptr;        // D G img before H^e / H^e^T y before D^T  [Q][K]
+    int eir_taps = 0, eir_n = 0;
     long long *d_seg_off = nullptr;   // segment table (see Problem)
     unsigned *d_seg = nullptr;
     int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0, calib_us = 0;
@@ -279,7 +285,8 @@ void oat_plan_destroy(oat_plan *plan)
     void *bufs[] = {plan->d_det, plan->d_shell, plan->d_ring, plan->d_part,
                     plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
                     plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
-                    plan->d_seg};
+                    plan->d_seg, plan->d_eir_h, plan->d_eir_spec, plan->d_eir_tw,
+                    plan->d_eir_filt, plan->d_eirbuf};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -597,10 +604,15 @@ int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    const bool srt_only = (flags & OAT_FLAG_SRT_ONLY) != 0;
+    const bool eir = plan->eir_taps > 0 && !srt_only;
     hipError_t e = launch_srt_fwd(plan->P, img, (int)img_dtype, plan->d_part, plan->d_klo, s);
     if (e == hipSuccess)
-        e = launch_srt_reduce(plan->P, plan->d_part, plan->d_klo, data, (int)data_dtype,
-                              (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
+        e = launch_srt_reduce(plan->P, plan->d_part, plan->d_klo, eir ? plan->d_eirbuf : data,
+                              eir ? 0 : (int)data_dtype, srt_only ? 0 : 1, s);
+    if (e == hipSuccess && eir)
+        e = launch_eir(plan->P, plan->d_eirbuf, 0, data, (int)data_dtype, plan->d_eir_h,
+                       plan->eir_taps, 0, s);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_project: launch");
     return OAT_OK;
@@ -615,8 +627,15 @@ int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_diff_adj(plan->P, data, (int)data_dtype, plan->d_gp,
-                                   (flags & OAT_FLAG_SRT_ONLY) ? 0 : 1, s);
+    const bool srt_only = (flags & OAT_FLAG_SRT_ONLY) != 0;
+    const bool eir = plan->eir_taps > 0 && !srt_only;
+    hipError_t e = hipSuccess;
+    if (eir)
+        e = launch_eir(plan->P, data, (int)data_dtype, plan->d_eirbuf, 0, plan->d_eir_h,
+                       plan->eir_taps, 1, s);
+    if (e == hipSuccess)
+        e = launch_diff_adj(plan->P, eir ? (const void *)plan->d_eirbuf : data,
+                            eir ? 0 : (int)data_dtype, plan->d_gp, srt_only ? 0 : 1, s);
     if (e == hipSuccess)
         e = launch_srt_adj(plan->P, plan->d_gp, plan->d_acc, img, (int)img_dtype, s);
     (void)hipSetDevice(prev);
@@ -635,6 +654,75 @@ int oat_fbp(oat_plan *plan, const void *pres, oat_dtype pres_dtype, void *img, o
                               (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_fbp: launch");
+    return OAT_OK;
+}
+
+int oat_plan_set_eir(oat_plan *plan, const double *h, int n_taps)
+{
+    if (!plan) return fail(OAT_ERR_ARG, "oat_plan_set_eir: null plan");
+    if (n_taps < 0 || n_taps > plan->P.nt || (n_taps > 0 && !h))
+        return fail(OAT_ERR_ARG, "oat_plan_set_eir: need 0 <= n_taps <= n_t and taps");
+    for (int m = 0; m < n_taps; ++m)
+        if (!std::isfinite(h[m])) return fail(OAT_ERR_ARG, "oat_plan_set_eir: taps must be finite");
+    int prev;
+    int rc = with_device(plan, prev);
+    if (rc) return rc;
+    if (n_taps == 0) {
+        plan->eir_taps = 0;
+        (void)hipSetDevice(prev);
+        return OAT_OK;
+    }
+    const int K = plan->P.nt;
+    int N = 1;
+    while (N < 2 * K) N *= 2;
+    hipError_t e = hipSuccess;
+    if (!plan->d_eir_h) {
+        auto al = [&](void **p, size_t b) {
+            if (e == hipSuccess) e = hipMalloc(p, b);
+        };
+        al((void **)&plan->d_eir_h, sizeof(double) * (size_t)K);
+        al((void **)&plan->d_eir_spec, sizeof(double2) * (size_t)N);
+        al((void **)&plan->d_eir_tw, sizeof(double2) * (size_t)(N / 2));
+        al((void **)&plan->d_eir_filt, sizeof(double2) * (size_t)N);
+        al((void **)&plan->d_eirbuf, sizeof(float) * (size_t)plan->P.nq * K);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipSetDevice(prev);
+            return fail(OAT_ERR_NOMEM, "oat_plan_set_eir: hipMalloc");
+        }
+        plan->ws_bytes += (int64_t)(sizeof(float) * (size_t)plan->P.nq * K +
+                                    sizeof(double2) * (size_t)(2 * N + N / 2));
+        plan->table_bytes += (int64_t)(sizeof(double) * (size_t)K);
+    }
+    // The previous EIR may still be in use by calls queued on other streams.
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(plan->d_eir_h, h, sizeof(double) * (size_t)n_taps, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_eir_spectrum(plan->d_eir_h, n_taps, N, plan->d_eir_spec, plan->d_eir_tw, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_plan_set_eir");
+    plan->eir_taps = n_taps;
+    plan->eir_n = N;
+    return OAT_OK;
+}
+
+int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oat_dtype p_dtype,
+                   double f_cut, uint32_t flags, void *stream)
+{
+    int rc = check_common(plan, u, u_dtype, p, p_dtype, flags, 0u, "oat_deconvolve");
+    if (rc) return rc;
+    if (plan->eir_taps == 0) return fail(OAT_ERR_ARG, "oat_deconvolve: the plan has no EIR");
+    if (!(f_cut > 0.0) || !std::isfinite(f_cut))
+        return fail(OAT_ERR_ARG, "oat_deconvolve: f_cut must be > 0");
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    hipError_t e = launch_deconvolve(plan->P, u, (int)u_dtype, p, (int)p_dtype, plan->d_eir_spec,
+                                     plan->d_eir_tw, plan->d_eir_filt, plan->eir_n, f_cut,
+                                     (hipStream_t)stream);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_deconvolve: launch");
     return OAT_OK;
 }
 

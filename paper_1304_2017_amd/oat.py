@@ -29,6 +29,7 @@ OAT_FLAG_SRT_ONLY = 1
 
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
             "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",
+            "oat_plan_set_eir", "oat_deconvolve",
             # include/oat_cnn.h
             "oat_conv3d_forward", "oat_conv3d_backward_weight_workspace",
             "oat_conv3d_backward_weight", "oat_adam_step", "oat_mse_workspace", "oat_mse")
@@ -65,6 +66,12 @@ def lib():
     """Load liboat.so; raises if it has not been built (no fallback)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime; it must be loaded before this
+        # library so both use the same one (loaded after, it finds no GPU).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(_LIB_PATH):
             raise ImportError(
                 f"{_LIB_PATH} is missing: build it with `python -m paper_1304_2017_amd.build`")
@@ -81,6 +88,11 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_uint32, vp]
             f.restype = ctypes.c_int
+        L.oat_plan_set_eir.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        L.oat_plan_set_eir.restype = ctypes.c_int
+        L.oat_deconvolve.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_uint32, vp]
+        L.oat_deconvolve.restype = ctypes.c_int
         L.oat_last_error.argtypes = []
         L.oat_last_error.restype = ctypes.c_char_p
         L.oat_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -130,6 +142,7 @@ class Plan:
         (oat_plan_options).  The segment table needs the arc table."""
         self.geom = geom
         self.device = int(device)
+        self._eir = None
         self._xyz = np.ascontiguousarray(geom.det_xyz, dtype=np.float64).reshape(-1, 3)
         self._area = (None if geom.det_area is None
                       else np.ascontiguousarray(geom.det_area, dtype=np.float64))
@@ -231,4 +244,22 @@ class Plan:
         _check(lib().oat_fbp(self._h, ctypes.c_void_p(pres.data_ptr()), _dtype_code(pres),
                              ctypes.c_void_p(out.data_ptr()), _dtype_code(out), 0,
                              self._stream(stream)))
+        return out
+
+    def set_eir(self, h):
+        """Electrical impulse response h[m] = dt h^e(m dt) (Eq. (EIR)); None or
+        an empty sequence removes it (oat_plan_set_eir; synchronous)."""
+        taps = np.zeros(0) if h is None else np.ascontiguousarray(h, dtype=np.float64).ravel()
+        _check(lib().oat_plan_set_eir(self._h, taps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      int(taps.size)))
+        self._eir = taps.copy() if taps.size else None
+
+    def deconvolve(self, u, f_cut: float, out=None, out_dtype=None, stream=None):
+        """Hann-window Fourier deconvolution of the plan's EIR (Sec. IV.B),
+        cutoff f_cut in cycles per time unit (MHz for microseconds)."""
+        u = self._prep(u, self.data_shape)
+        out = self._out(out, self.data_shape, out_dtype, u)
+        _check(lib().oat_deconvolve(self._h, ctypes.c_void_p(u.data_ptr()), _dtype_code(u),
+                                    ctypes.c_void_p(out.data_ptr()), _dtype_code(out),
+                                    float(f_cut), 0, self._stream(stream)))
         return out

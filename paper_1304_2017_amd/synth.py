@@ -372,3 +372,13 @@ def config_d_phantoms(count: int = 64, seed: int = 0, dtype=np.float32):
         ells = random_ellipsoids(rng, int(rng.integers(15, 61)), geom, 0.3, 3.0, 0.0, 1.0)
         out.append(voxelise_ellipsoids(geom, ells, dtype=dtype))
     return geom, out
+
+
+def gamma_pulse(taps: int, dt: float, tau: float) -> np.ndarray:
+    """A synthetic transducer electrical impulse response for Eq. (EIR):
+    h[m] = dt h(m dt) with the causal low-pass pulse h(t) = t/tau^2 exp(-t/tau)
+    (unit area; its transform 1/(1 + i 2 pi f tau)^2 has no zeros).  The
+    paper's measured EIR is not available; this stands in for it."""
+    t = np.arange(taps) * dt
+    return dt * t / tau ** 2 * np.exp(-t / tau)
+

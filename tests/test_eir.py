@@ -13,6 +13,7 @@ import sys
 
 import numpy as np
 import pytest
+import torch  # before the library: one HIP runtime for both
 
 from oracle import ref
 from paper_1304_2017_amd import synth
@@ -20,11 +21,7 @@ from paper_1304_2017_amd import synth
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_simulation_setup.json")
 
 
-def gamma_pulse(L, dt, tau):
-    """A causal low-pass response h(t) = t/tau^2 exp(-t/tau), sampled as
-    h[m] = dt h(m dt); its transform 1/(1 + i 2 pi f tau)^2 has no zeros."""
-    t = np.arange(L) * dt
-    return dt * t / tau ** 2 * np.exp(-t / tau)
+gamma_pulse = synth.gamma_pulse
 
 
 # --------------------------------------------------------------------------
@@ -144,3 +141,167 @@ def test_paper_simulation_setup():
     rings = np.unique(np.round(theta, 9))
     assert rings.size == g["subset_rings"]
     assert np.allclose(rings, (np.arange(g["subset_rings"]) + 0.5) * np.pi / g["subset_rings"])
+
+
+# --------------------------------------------------------------------------
+# The library's EIR paths against the oracle (GPU)
+# --------------------------------------------------------------------------
+gpu = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _t(x, dtype=None):
+    import torch
+    return torch.tensor(np.asarray(x), dtype=torch.float64).to(dtype or torch.float32).cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def small_eir():
+    from paper_1304_2017_amd.oat import Plan
+    geom = synth.config_small(0)[0]
+    plan = Plan(geom, 0)
+    h = gamma_pulse(24, geom.dt, 0.3)
+    plan.set_eir(h)
+    return geom, plan, h
+
+
+@gpu
+def test_project_and_backproject_with_eir(small_eir):
+    import torch
+    geom, plan, h = small_eir
+    gd = geom.as_dict()
+    rng = np.random.default_rng(5)
+    img = rng.uniform(0, 1, size=geom.shape).astype(np.float32).astype(np.float64)
+    _say("[gpu] H and H^T with a 24-tap EIR, 32^3")
+    e = rel(_np(plan.project(_t(img))), ref.project_eir(gd, h, img))
+    y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
+    eT = rel(_np(plan.backproject(_t(y))), ref.backproject_eir(gd, h, y))
+    # G alone is unchanged by the EIR
+    eg = rel(_np(plan.project(_t(img), srt_only=True)), ref.srt(gd, img))
+    # adjoint identity through the library
+    x = _t(img, torch.float64).float()
+    yy = _t(y, torch.float64).float()
+    Hx = plan.project(x).double()
+    lhs = float((Hx * yy.double()).sum())
+    rhs = float((x.double() * plan.backproject(yy).double()).sum())
+    scale = float(Hx.norm() * yy.double().norm())
+    _say(f"  H rel {e:.3e}  H^T rel {eT:.3e}  G rel {eg:.3e}  "
+         f"|<Hx,y>-<x,H^T y>| / (|Hx||y|) {abs(lhs - rhs) / scale:.3e}")
+    assert e < 1e-5 and eT < 1e-5 and eg < 1e-6
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+@gpu
+def test_eir_with_bf16_storage(small_eir):
+    import torch
+    geom, plan, h = small_eir
+    gd = geom.as_dict()
+    rng = np.random.default_rng(6)
+    img = rng.uniform(0, 1, size=geom.shape)
+    xb = _t(img, torch.bfloat16)
+    e = rel(_np(plan.project(xb, out_dtype=torch.bfloat16)), ref.project_eir(gd, h, _np(xb)))
+    _say(f"[gpu] H with EIR, BF16 storage: rel {e:.3e}")
+    assert e < 2e-3
+
+
+@gpu
+def test_deconvolve_matches_oracle(small_eir):
+    import torch
+    geom, plan, h = small_eir
+    rng = np.random.default_rng(7)
+    u = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
+    fc = 2.5                                   # MHz; sampling at 10 MHz
+    p = plan.deconvolve(_t(u), fc)
+    p2 = plan.deconvolve(_t(u), fc)
+    e = rel(_np(p), ref.deconvolve(h, u, geom.dt, fc))
+    _say(f"[gpu] deconvolution rel {e:.3e}")
+    assert e < 1e-6
+    assert torch.equal(p, p2)
+    ub = _t(u, torch.bfloat16)
+    eb = rel(_np(plan.deconvolve(ub, fc, out_dtype=torch.bfloat16)),
+             ref.deconvolve(h, _np(ub), geom.dt, fc))
+    assert eb < 2e-3
+
+
+@gpu
+def test_deconvolution_then_fbp(small_eir):
+    """FBP of deconvolved EIR-filtered data, against the oracle's
+    deconvolution and FBP."""
+    geom, plan, h = small_eir
+    gd = geom.as_dict()
+    _, balls, _ = synth.config_small(0)
+    p_true = synth.nwave_balls(geom, balls)
+    u = ref.eir(h, p_true).astype(np.float32).astype(np.float64)
+    got = _np(plan.fbp(plan.deconvolve(_t(u), 2.5)))
+    want = ref.fbp(gd, ref.deconvolve(h, u, geom.dt, 2.5))
+    e = rel(got, want)
+    _say(f"[gpu] deconvolution + FBP rel {e:.3e}")
+    assert e < 1e-5
+
+
+@gpu
+def test_eir_arguments_and_removal(small_eir):
+    from paper_1304_2017_amd import oat
+    geom, plan, h = small_eir
+    L = oat.lib()
+    too_many = np.zeros(geom.n_t + 1)
+    dp = too_many.ctypes.data_as(oat.ctypes.POINTER(oat.ctypes.c_double))
+    assert L.oat_plan_set_eir(plan._h, dp, geom.n_t + 1) == oat.OAT_ERR_ARG
+    bad = np.array([1.0, np.nan])
+    assert L.oat_plan_set_eir(plan._h, bad.ctypes.data_as(oat.ctypes.POINTER(oat.ctypes.c_double)),
+                              2) == oat.OAT_ERR_ARG
+    u = _t(np.zeros((geom.n_det, geom.n_t)))
+    with pytest.raises(oat.OatError):
+        plan.deconvolve(u, 0.0)
+    # removing the EIR restores H = D G, and deconvolution then refuses
+    rng = np.random.default_rng(8)
+    img = rng.uniform(0, 1, size=geom.shape).astype(np.float32).astype(np.float64)
+    plan.set_eir(None)
+    try:
+        assert rel(_np(plan.project(_t(img))), ref.project(geom.as_dict(), img)) < 1e-5
+        with pytest.raises(oat.OatError):
+            plan.deconvolve(u, 2.5)
+    finally:
+        plan.set_eir(h)
+
+
+@gpu
+def test_full_size_eir_rows():
+    """256^3 / 2048 / 1024 with a 64-tap EIR: H on sampled rows, H^T with
+    data on two transducers, and the deconvolution of every row."""
+    import torch
+    from paper_1304_2017_amd.oat import Plan
+    geom, _, img = synth.config_large(0, dtype=np.float32)
+    plan = Plan(geom, 0)
+    h = gamma_pulse(64, geom.dt, 0.1)
+    plan.set_eir(h)
+    gd = geom.as_dict()
+    rows = np.array([5, 1400], dtype=np.int32)
+    _say("[gpu-full] H with EIR, rows 5 and 1400")
+    p = _np(plan.project(torch.from_numpy(img).cuda()))
+    e = rel(p[rows], ref.project_eir(gd, h, img.astype(np.float64), rows=rows))
+    y = np.zeros((geom.n_det, geom.n_t), dtype=np.float32)
+    y[rows] = np.random.default_rng(9).normal(size=(2, geom.n_t)).astype(np.float32)
+    a = _np(plan.backproject(torch.from_numpy(y).cuda()))
+    eT = rel(a, ref.backproject_eir(gd, h, y[rows].astype(np.float64), rows=rows))
+    u = np.random.default_rng(10).normal(size=(geom.n_det, geom.n_t)).astype(np.float32)
+    d = _np(plan.deconvolve(torch.from_numpy(u).cuda(), 5.0))
+    ed = rel(d, ref.deconvolve(h, u.astype(np.float64), geom.dt, 5.0))
+    _say(f"  H rel {e:.3e}  H^T rel {eT:.3e}  deconvolution rel {ed:.3e}")
+    assert e < 1e-5 and eT < 1e-5 and ed < 1e-6
