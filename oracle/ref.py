@@ -264,3 +264,71 @@ def project_eir(geom, h, alpha, rows=None):
 def backproject_eir(geom, h, y, rows=None):
     """G^T D^T H^e^T y using the listed rows of y."""
     return backproject(geom, eir_adj(h, y), rows=rows)
+
+
+# ---------------------------------------------------------------------------
+# Spherical-voxel imaging model (Sec. II.B.2), point-like transducers, plain
+# numpy in FP64.
+# ---------------------------------------------------------------------------
+def sph_freqs(n_f, f_min, df):
+    """Frequency samples f_l = f_min + l df, l = 0 .. n_f - 1 (the listings'
+    form; Eq. (dis_sph) is the case f_min = 0)."""
+    return f_min + df * np.arange(n_f, dtype=np.float64)
+
+
+def sph_p0(f, geom):
+    """Eq. (p0f) with beta c0^3 / Cp = Gamma c0 and an ideal EIR (h^e = 1):
+    p0(f) = -j Gamma c0 / f [ dx/(2 c0) cos(pi f dx / c0) - sin(pi f dx / c0) / (2 pi f) ],
+    0 at f = 0 (its limit)."""
+    f = np.asarray(f, dtype=np.float64)
+    c0, dx, gam = geom["c0"], geom["dx"], geom["gamma"]
+    out = np.zeros(f.shape, dtype=np.complex128)
+    nz = f != 0
+    fn = f[nz]
+    br = dx / (2 * c0) * np.cos(np.pi * fn * dx / c0) - np.sin(np.pi * fn * dx / c0) / (2 * np.pi * fn)
+    out[nz] = -1j * gam * c0 / fn * br
+    return out
+
+
+def _nodes(geom):
+    nx, ny, nz = geom["nx"], geom["ny"], geom["nz"]
+    dx = geom["dx"]
+    z, y, x = np.meshgrid(geom["z0"] + dx * np.arange(nz), geom["y0"] + dx * np.arange(ny),
+                          geom["x0"] + dx * np.arange(nx), indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)   # [N][3], flat index of [nz][ny][nx]
+
+
+def sph_project(geom, alpha, n_f, f_min, df):
+    """Eq. (dis_sph) for point-like transducers (the surface integral over
+    S_q divided by S_q is its value at r_q):
+    u[q, l] = p0(f_l) sum_n alpha_n exp(-j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+    d_qn = |r_q - r_n|.  alpha [nz][ny][nx] real -> u [Q][n_f] complex."""
+    r = _nodes(geom)
+    a = np.asarray(alpha, dtype=np.float64).ravel()
+    f = sph_freqs(n_f, f_min, df)
+    p0 = sph_p0(f, geom)
+    rq = np.asarray(geom["det_xyz"], dtype=np.float64).reshape(-1, 3)
+    u = np.zeros((rq.shape[0], n_f), dtype=np.complex128)
+    for q in range(rq.shape[0]):
+        d = np.linalg.norm(r - rq[q], axis=1)
+        E = np.exp(-2j * np.pi * np.outer(f, d) / geom["c0"])          # [n_f][N]
+        u[q] = p0 * (E @ (a / (2 * np.pi * d)))
+    return u
+
+
+def sph_backproject(geom, u, n_f, f_min, df):
+    """Eq. (sphbwd): [H^T u]_n = sum_{q,l} u[q,l] conj(p0(f_l)) conj(h_q(r_n, f_l)),
+    h_q(r_n, f) = exp(-j 2 pi f d_qn / c0) / (2 pi d_qn).  Returns its real
+    part [nz][ny][nx] (the image is real, so this is the adjoint of
+    sph_project over real images)."""
+    r = _nodes(geom)
+    f = sph_freqs(n_f, f_min, df)
+    p0c = np.conj(sph_p0(f, geom))
+    rq = np.asarray(geom["det_xyz"], dtype=np.float64).reshape(-1, 3)
+    u = np.asarray(u, dtype=np.complex128).reshape(rq.shape[0], n_f)
+    out = np.zeros(r.shape[0], dtype=np.complex128)
+    for q in range(rq.shape[0]):
+        d = np.linalg.norm(r - rq[q], axis=1)
+        Ec = np.exp(2j * np.pi * np.outer(f, d) / geom["c0"])          # conj of h's phase
+        out += ((u[q] * p0c) @ Ec) / (2 * np.pi * d)
+    return out.real.reshape(geom["nz"], geom["ny"], geom["nx"])
