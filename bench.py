@@ -283,6 +283,34 @@ def eir_run(reps):
         reps=reps)), flush=True)
 
 
+def sph_run(reps):
+    """The spherical-voxel model at its workload (64^3, 2048 transducers,
+    256 frequencies in (0, 5] MHz): H_sph and H_sph^T times, terms per
+    second, and the fraction of the VALU peak at 6 operations per term (a
+    complex rotation and a weighted complex add); one JSON line."""
+    import torch
+    from paper_1304_2017_amd import synth
+    from paper_1304_2017_amd.oat import Plan
+    geom, img = synth.config_sph()
+    plan = Plan(geom, 0)
+    n_f, df = 256, 5.0 / 256
+    x = torch.from_numpy(img).cuda()
+    u = torch.empty((geom.n_det, n_f), device="cuda", dtype=torch.complex64)
+    a = torch.empty(plan.image_shape, device="cuda")
+    t_f = time_op(lambda: plan.sph_project(x, n_f, df, df, out=u), reps)
+    t_b = time_op(lambda: plan.sph_backproject(u, df, df, out=a), reps)
+    nnz = int(np.count_nonzero(img))
+    terms_f = float(nnz) * geom.n_det * n_f
+    terms_b = float(geom.n_vox) * geom.n_det * n_f
+    peak = 256 * 64 * 2.4e9
+    print(json.dumps(dict(
+        workload="64^3 (0.4 mm), 2048 hemisphere transducers, 256 frequencies f_l = (l+1) * 5/256 MHz",
+        H_sph_ms=t_f * 1e3, H_sph_T_ms=t_b * 1e3, nonzero_voxels=nnz, voxels=geom.n_vox,
+        H_sph_terms_per_s=terms_f / t_f, H_sph_T_terms_per_s=terms_b / t_b,
+        H_sph_valu_frac=6 * terms_f / t_f / peak, H_sph_T_valu_frac=6 * terms_b / t_b / peak,
+        reps=reps)), flush=True)
+
+
 def matrix(reps):
     """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
     transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
@@ -339,6 +367,8 @@ def main():
                     help="train the learned preconditioner and time PLS-TV plain vs learned")
     ap.add_argument("--phantoms", type=int, default=64, help="training phantoms (--learned)")
     ap.add_argument("--epochs", type=int, default=5, help="training epochs (--learned)")
+    ap.add_argument("--sph", action="store_true",
+                    help="time the spherical-voxel model H_sph and H_sph^T at 64^3 / 2048 / 256")
     ap.add_argument("--eir", action="store_true",
                     help="time H, H^T with a 64-tap EIR and the deconvolution + FBP at 256^3")
     args = ap.parse_args()
@@ -362,6 +392,9 @@ def main():
         return
     if args.eir:
         eir_run(max(args.steps, 3))
+        return
+    if args.sph:
+        sph_run(max(args.steps, 3))
         return
     dev = torch.device("cuda", 0)
     log("[bench] building 256^3 workload")

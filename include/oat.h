@@ -13,6 +13,9 @@
  *   oat_fbp          alpha_fbp from p          Sec. III.B, Eq. (disfbp)
  *   oat_deconvolve   p from measured u         Sec. IV.B: Fourier deconvolution of the
  *                                              EIR with a Hann window, before oat_fbp
+ *   oat_sph_project  u~ = H_sph alpha          Sec. II.B.2: the spherical-voxel model,
+ *   oat_sph_backproject  H_sph^T u~            Eq. (dis_sph) and Eq. (sphbwd), in the
+ *                                              temporal-frequency domain
  *
  * Units: lengths in mm, times in microseconds.
  *
@@ -197,6 +200,26 @@ int oat_plan_set_eir(oat_plan *plan, const double *h, int n_taps);
  * alias.  Asynchronous on `stream`.  OAT_ERR_ARG when the plan has no EIR. */
 int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oat_dtype p_dtype,
                    double f_cut, uint32_t flags, void *stream);
+
+/* Spherical-voxel model (Sec. II.B.2), point-like transducers (the surface
+ * integral over S_q divided by S_q is its value at r_q), ideal EIR:
+ *   u~[q][l] = p0(f_l) sum_n alpha_n exp(-j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+ *   p0(f) = -j Gamma c0 / f [dx/(2 c0) cos(pi f dx / c0) - sin(pi f dx / c0) / (2 pi f)]
+ *   (Eq. (p0f) with beta c0^3 / Cp = Gamma c0; p0(0) = 0), d_qn = |r_q - r_n|,
+ * f_l = f_min + l df for l = 0 .. n_f - 1 (the listings' frequency grid).
+ * alpha_n is the voxel's absorbed-energy density; r_n are the plan's nodes.
+ * img: device [nz][ny][nx] (oat_dtype); u: device [n_det][n_f] complex FP32,
+ * interleaved (re, im).  Every term is evaluated (a dense sum); phases and
+ * sums are FP64, exponentials FP32.  1 <= n_f <= 8192, f_min >= 0, df > 0,
+ * flags = 0.  oat_sph_project keeps a workspace in the plan and may allocate
+ * it on the first call with a larger n_f.  Results are deterministic. */
+int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,
+                    double f_min, double df, uint32_t flags, void *stream);
+
+/* Eq. (sphbwd): img[n] = Re sum_{q,l} u~[q][l] conj(p0(f_l)) exp(+j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+ * the adjoint of oat_sph_project over real images.  Same arguments. */
+int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, double df,
+                        void *img, oat_dtype img_dtype, uint32_t flags, void *stream);
 
 /* Thread-local, NUL-terminated description of the last non-OK status
  * returned on this thread ("" if none).  Valid until the next call. */

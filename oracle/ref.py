@@ -298,30 +298,34 @@ def _nodes(geom):
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)   # [N][3], flat index of [nz][ny][nx]
 
 
-def sph_project(geom, alpha, n_f, f_min, df):
+def sph_project(geom, alpha, n_f, f_min, df, rows=None):
     """Eq. (dis_sph) for point-like transducers (the surface integral over
     S_q divided by S_q is its value at r_q):
     u[q, l] = p0(f_l) sum_n alpha_n exp(-j 2 pi f_l d_qn / c0) / (2 pi d_qn),
-    d_qn = |r_q - r_n|.  alpha [nz][ny][nx] real -> u [Q][n_f] complex."""
+    d_qn = |r_q - r_n|.  alpha [nz][ny][nx] real -> u [Q][n_f] complex, or the
+    listed rows only."""
     r = _nodes(geom)
     a = np.asarray(alpha, dtype=np.float64).ravel()
     f = sph_freqs(n_f, f_min, df)
     p0 = sph_p0(f, geom)
     rq = np.asarray(geom["det_xyz"], dtype=np.float64).reshape(-1, 3)
-    u = np.zeros((rq.shape[0], n_f), dtype=np.complex128)
-    for q in range(rq.shape[0]):
+    qs = np.arange(rq.shape[0]) if rows is None else np.asarray(rows)
+    u = np.zeros((qs.size, n_f), dtype=np.complex128)
+    for i, q in enumerate(qs):
         d = np.linalg.norm(r - rq[q], axis=1)
         E = np.exp(-2j * np.pi * np.outer(f, d) / geom["c0"])          # [n_f][N]
-        u[q] = p0 * (E @ (a / (2 * np.pi * d)))
+        u[i] = p0 * (E @ (a / (2 * np.pi * d)))
     return u
 
 
-def sph_backproject(geom, u, n_f, f_min, df):
+def sph_backproject(geom, u, n_f, f_min, df, voxels=None):
     """Eq. (sphbwd): [H^T u]_n = sum_{q,l} u[q,l] conj(p0(f_l)) conj(h_q(r_n, f_l)),
     h_q(r_n, f) = exp(-j 2 pi f d_qn / c0) / (2 pi d_qn).  Returns its real
     part [nz][ny][nx] (the image is real, so this is the adjoint of
-    sph_project over real images)."""
+    sph_project over real images), or at the listed flat voxel indices."""
     r = _nodes(geom)
+    if voxels is not None:
+        r = r[np.asarray(voxels)]
     f = sph_freqs(n_f, f_min, df)
     p0c = np.conj(sph_p0(f, geom))
     rq = np.asarray(geom["det_xyz"], dtype=np.float64).reshape(-1, 3)
@@ -331,4 +335,6 @@ def sph_backproject(geom, u, n_f, f_min, df):
         d = np.linalg.norm(r - rq[q], axis=1)
         Ec = np.exp(2j * np.pi * np.outer(f, d) / geom["c0"])          # conj of h's phase
         out += ((u[q] * p0c) @ Ec) / (2 * np.pi * d)
+    if voxels is not None:
+        return out.real
     return out.real.reshape(geom["nz"], geom["ny"], geom["nx"])

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liboat.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-DEVICE_SOURCES = ["oat_srt.hip", "oat_aux.hip", "oat_cnn.hip", "oat_eir.hip"]
+DEVICE_SOURCES = ["oat_srt.hip", "oat_aux.hip", "oat_cnn.hip", "oat_eir.hip", "oat_sph.hip"]
 HOST_SOURCES = ["oat_plan.cpp"]
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -22,6 +22,8 @@ constexpr int WMAX = 256;                    // largest shell window per (brick,
 // G^T takes the transducers in windows of ADJ_WINDOW, with one fixed-point
 // scale and one flush of its LDS box per window.
 constexpr int ADJ_WINDOW = 48;
+// Spherical-voxel forward: voxel chunks summed separately, then in order.
+constexpr int SPH_CHUNKS = 64;
 __host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).
@@ -77,6 +79,7 @@ struct Problem {
     // FP64 problem statement for FBP's floor decisions (same formula as the
     // problem statement: kt = (|r_n - r_q| / c0 - t0) / dt, r_n = r_0 + dx * n)
     double x0, y0, z0, dxd, c0d, t0d, dtd;
+    double gammad;         // Gamma (spherical-voxel model)
     float w_max;           // largest ring weight
     float r_sup;           // radius of the image support sphere / dx
     float *gp_rowmax;      // [nq] max |g'| per transducer over reachable samples (D^T kernel)
@@ -137,5 +140,11 @@ hipError_t launch_eir_spectrum(const double *h, int taps, int N, double2 *Ht, do
 hipError_t launch_deconvolve(const Problem &P, const void *u, int u_dt, void *p, int p_dt,
                              const double2 *Ht, const double2 *tw, double2 *F, int N, double fc,
                              hipStream_t s);
+// Spherical-voxel model (oat_sph.hip); part holds sph_workspace_bytes.
+size_t sph_workspace_bytes(const Problem &P, int n_f);
+hipError_t launch_sph_project(const Problem &P, const void *img, int img_dt, float2 *u, int n_f,
+                              double f_min, double df, double2 *part, hipStream_t s);
+hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, double f_min,
+                                  double df, void *img, int img_dt, hipStream_t s);
 
 }  // namespace oat

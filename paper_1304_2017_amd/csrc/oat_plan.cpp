@@ -76,6 +76,8 @@ struct oat_plan {
     double2 *d_eir_filt = nullptr;    // deconvolution filter of a call [eir_n]
     float *d_eirbuf = nullptr;        // D G img before H^e / H^e^T y before D^T  [Q][K]
     int eir_taps = 0, eir_n = 0;
+    double2 *d_sph_part = nullptr;    // spherical-voxel chunk sums
+    size_t sph_part_bytes = 0;
     long long *d_seg_off = nullptr;   // segment table (see Problem)
     unsigned *d_seg = nullptr;
     int64_t tab_bytes = 0, tab_entries = 0, tab_build_us = 0, calib_us = 0;
@@ -286,7 +288,7 @@ void oat_plan_destroy(oat_plan *plan)
                     plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
                     plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
                     plan->d_seg, plan->d_eir_h, plan->d_eir_spec, plan->d_eir_tw,
-                    plan->d_eir_filt, plan->d_eirbuf};
+                    plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -474,6 +476,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.c0d = g->c0;
     P.t0d = g->t0;
     P.dtd = g->dt;
+    P.gammad = g->gamma;
 
     const int nbricks = P.nbx * P.nby * P.nbz;
 
@@ -723,6 +726,65 @@ int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oa
                                      (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_deconvolve: launch");
+    return OAT_OK;
+}
+
+static int check_sph(oat_plan *plan, const void *a, const void *b, int img_dt, int n_f,
+                     double f_min, double df, uint32_t flags, const char *who)
+{
+    if (!plan) return fail(OAT_ERR_ARG, std::string(who) + ": null plan");
+    if (!a || !b) return fail(OAT_ERR_ARG, std::string(who) + ": null buffer");
+    if (a == b) return fail(OAT_ERR_ARG, std::string(who) + ": input and output alias");
+    if (img_dt != OAT_F32 && img_dt != OAT_BF16)
+        return fail(OAT_ERR_DTYPE, std::string(who) + ": unknown dtype");
+    if (flags) return fail(OAT_ERR_ARG, std::string(who) + ": unknown flag");
+    if (n_f < 1 || n_f > 8192 || !(f_min >= 0.0) || !std::isfinite(f_min) || !(df > 0.0) ||
+        !std::isfinite(df))
+        return fail(OAT_ERR_ARG, std::string(who) + ": need 1 <= n_f <= 8192, f_min >= 0, df > 0");
+    return OAT_OK;
+}
+
+int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,
+                    double f_min, double df, uint32_t flags, void *stream)
+{
+    int rc = check_sph(plan, img, u, (int)img_dtype, n_f, f_min, df, flags, "oat_sph_project");
+    if (rc) return rc;
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    const size_t need = sph_workspace_bytes(plan->P, n_f);
+    hipError_t e = hipSuccess;
+    if (need > plan->sph_part_bytes) {
+        // grows once per larger n_f; earlier calls may still use the old buffer
+        e = hipDeviceSynchronize();
+        if (e == hipSuccess && plan->d_sph_part) e = hipFree(plan->d_sph_part);
+        plan->d_sph_part = nullptr;
+        plan->sph_part_bytes = 0;
+        if (e == hipSuccess) e = hipMalloc((void **)&plan->d_sph_part, need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipSetDevice(prev);
+            return fail(OAT_ERR_NOMEM, "oat_sph_project: hipMalloc");
+        }
+        plan->sph_part_bytes = need;
+    }
+    e = launch_sph_project(plan->P, img, (int)img_dtype, (float2 *)u, n_f, f_min, df,
+                           plan->d_sph_part, (hipStream_t)stream);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_sph_project: launch");
+    return OAT_OK;
+}
+
+int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, double df,
+                        void *img, oat_dtype img_dtype, uint32_t flags, void *stream)
+{
+    int rc = check_sph(plan, u, img, (int)img_dtype, n_f, f_min, df, flags, "oat_sph_backproject");
+    if (rc) return rc;
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    hipError_t e = launch_sph_backproject(plan->P, (const float2 *)u, n_f, f_min, df, img,
+                                          (int)img_dtype, (hipStream_t)stream);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_sph_backproject: launch");
     return OAT_OK;
 }
 

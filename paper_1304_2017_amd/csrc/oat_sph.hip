@@ -1,0 +1,240 @@
+// Spherical-voxel imaging model on gfx950 (Sec. II.B.2): H_sph of
+// Eq. (dis_sph) with p0 of Eq. (p0f), and its adjoint, Eq. (sphbwd), for
+// point-like transducers (the surface integral over S_q divided by S_q is the
+// value at r_q) and an ideal EIR:
+//   u[q, l] = p0(f_l) sum_n alpha_n exp(-j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+//   f_l = f_min + l df,   d_qn = |r_q - r_n|.
+// Every (transducer, frequency, voxel) term is evaluated: a dense sum, bound
+// by the VALU.  Distances and phases are FP64 (a phase of hundreds of turns
+// must keep ~1e-7 turn); the complex exponentials are an accurate FP32
+// sincos of the phase's fractional turn plus a short FP32 rotation
+// recurrence along l; sums are FP64.
+#include "oat_dtype.hpp"
+#include "oat_geom.hpp"
+#include "oat_internal.hpp"
+
+#pragma clang fp contract(off)
+
+namespace oat {
+
+namespace {
+
+constexpr int SPH_THREADS = 256;
+constexpr int SPH_FB = 8;        // frequencies per thread (forward)
+constexpr int SPH_TILE = 256;    // voxels staged per LDS tile (forward)
+constexpr int SPH_ANCHOR = 16;   // recurrence steps between exact phases (adjoint)
+
+__device__ __forceinline__ double frac_turn(double x) { return x - floor(x); }
+
+// Node n of the [nz][ny][nx] grid in FP64.
+__device__ __forceinline__ void node_pos(const Problem &P, long long n, double &x, double &y,
+                                         double &z)
+{
+    const long long ix = n % P.nx, iy = (n / P.nx) % P.ny, iz = n / ((long long)P.nx * P.ny);
+    x = P.x0 + (double)ix * P.dxd;
+    y = P.y0 + (double)iy * P.dxd;
+    z = P.z0 + (double)iz * P.dxd;
+}
+
+// Partial sums of one voxel chunk.  Thread: transducer q = blockIdx.x * QB +
+// t / LB, frequencies l0 = (t % LB) * SPH_FB ... + SPH_FB - 1.
+// part[chunk][q][l] = sum over the chunk's voxels (FP64 complex, no p0).
+__global__ void __launch_bounds__(SPH_THREADS)
+sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, double f_min,
+               double df, int LB, long long chunk_len, double2 *__restrict__ part)
+{
+    __shared__ double sx[SPH_TILE], sy[SPH_TILE], sz[SPH_TILE];
+    __shared__ float sa[SPH_TILE];
+    const int QB = SPH_THREADS / LB;
+    const int t = threadIdx.x;
+    const int q = blockIdx.x * QB + t / LB;
+    const int l0 = (t % LB) * SPH_FB;
+    const bool active = (t / LB) < QB && q < P.nq && l0 < n_f;
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    const long long n0 = (long long)blockIdx.y * chunk_len, n1 = min(N, n0 + chunk_len);
+    double rqx = 0.0, rqy = 0.0, rqz = 0.0;
+    if (q < P.nq) {
+        const DetRec &d = P.det[q];
+        rqx = d.r[0];
+        rqy = d.r[1];
+        rqz = d.r[2];
+    }
+    const double inv_c0 = 1.0 / P.c0d;
+    const double fa = f_min + df * (double)l0;   // first frequency of the thread
+    double ar[SPH_FB], ai[SPH_FB];
+#pragma unroll
+    for (int i = 0; i < SPH_FB; ++i) ar[i] = ai[i] = 0.0;
+    for (long long base = n0; base < n1; base += SPH_TILE) {
+        __syncthreads();
+        const long long n = base + t;
+        if (t < SPH_TILE) {
+            double x = 0.0, y = 0.0, z = 0.0;
+            float a = 0.f;
+            if (n < n1) {
+                node_pos(P, n, x, y, z);
+                a = load_val(img, (size_t)n, img_dt);
+            }
+            sx[t] = x;
+            sy[t] = y;
+            sz[t] = z;
+            sa[t] = a;
+        }
+        __syncthreads();
+        const int cnt = (int)min((long long)SPH_TILE, n1 - base);
+        if (!active) continue;
+        for (int j = 0; j < cnt; ++j) {
+            const float a = sa[j];
+            if (a == 0.f) continue;
+            const double vx = sx[j] - rqx, vy = sy[j] - rqy, vz = sz[j] - rqz;
+            const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
+            const double tau = dd * inv_c0;
+            float c, s, cz, szs;
+            sincos_turns((float)frac_turn(fa * tau), c, s);
+            sincos_turns((float)frac_turn(df * tau), cz, szs);
+            // exp(-j theta) = (c, -s); step exp(-j dtheta) = (cz, -szs)
+            float er = c, ei = -s;
+            const float zr = cz, zi = -szs;
+            const double w = (double)a / (6.283185307179586 * dd);
+#pragma unroll
+            for (int i = 0; i < SPH_FB; ++i) {
+                ar[i] = fma(w, (double)er, ar[i]);
+                ai[i] = fma(w, (double)ei, ai[i]);
+                const float nr = er * zr - ei * zi, ni = er * zi + ei * zr;
+                er = nr;
+                ei = ni;
+            }
+        }
+    }
+    if (active) {
+        double2 *dst = part + ((size_t)blockIdx.y * P.nq + q) * n_f;
+        for (int i = 0; i < SPH_FB && l0 + i < n_f; ++i) dst[l0 + i] = make_double2(ar[i], ai[i]);
+    }
+}
+
+// p0(f) of Eq. (p0f) with beta c0^3 / Cp = Gamma c0, ideal EIR; 0 at f = 0.
+__device__ __forceinline__ double2 sph_p0(const Problem &P, double f)
+{
+    if (f == 0.0) return make_double2(0.0, 0.0);
+    const double x = 3.141592653589793 * f * P.dxd / P.c0d;
+    const double br = P.dxd / (2.0 * P.c0d) * cos(x) - sin(x) / (6.283185307179586 * f);
+    return make_double2(0.0, -P.gammad * P.c0d / f * br);
+}
+
+// u[q][l] = p0(f_l) * sum over chunks (in chunk order) of part, as complex FP32.
+__global__ void __launch_bounds__(SPH_THREADS)
+sph_fwd_reduce_kernel(Problem P, const double2 *__restrict__ part, int nchunk, int n_f,
+                      double f_min, double df, float2 *__restrict__ u)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long total = (long long)P.nq * n_f;
+    if (i >= total) return;
+    const int l = (int)(i % n_f);
+    double sr = 0.0, si = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 v = part[(size_t)c * total + i];
+        sr += v.x;
+        si += v.y;
+    }
+    const double2 p0 = sph_p0(P, f_min + df * (double)l);
+    u[i] = make_float2((float)(p0.x * sr - p0.y * si), (float)(p0.x * si + p0.y * sr));
+}
+
+// One voxel per thread: out[n] = Re sum_q sum_l v[q,l] exp(+j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+// v[q,l] = u[q,l] conj(p0(f_l)), staged per transducer in LDS.
+template <int IMG_DT>
+__global__ void __launch_bounds__(SPH_THREADS)
+sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, double df,
+               void *__restrict__ img)
+{
+    extern __shared__ float2 sv[];   // [qt][n_f]
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (n < N) node_pos(P, n, x, y, z);
+    const double inv_c0 = 1.0 / P.c0d;
+    const int qt = max(1, 8192 / n_f);   // transducers per LDS tile (64 KB)
+    double acc = 0.0;
+    for (int q0 = 0; q0 < P.nq; q0 += qt) {
+        const int nq = min(qt, P.nq - q0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < nq * n_f; k += blockDim.x) {
+            const int l = k % n_f;
+            const float2 v = u[(size_t)q0 * n_f + k];
+            const double2 p = sph_p0(P, f_min + df * (double)l);   // v * conj(p0)
+            sv[k] = make_float2((float)(v.x * p.x + v.y * p.y), (float)(v.y * p.x - v.x * p.y));
+        }
+        __syncthreads();
+        if (n >= N) continue;
+        for (int j = 0; j < nq; ++j) {
+            const DetRec &d = P.det[q0 + j];
+            const double vx = x - d.r[0], vy = y - d.r[1], vz = z - d.r[2];
+            const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
+            const double tau = dd * inv_c0;
+            float cz, szs;
+            sincos_turns((float)frac_turn(df * tau), cz, szs);
+            const float2 *vq = sv + j * n_f;
+            double part = 0.0;
+            for (int l0 = 0; l0 < n_f; l0 += SPH_ANCHOR) {
+                float c, s;
+                sincos_turns((float)frac_turn((f_min + df * (double)l0) * tau), c, s);
+                float er = c, ei = s;   // exp(+j theta)
+                float sr = 0.f;
+                const int le = min(n_f, l0 + SPH_ANCHOR);
+                for (int l = l0; l < le; ++l) {
+                    const float2 v = vq[l];
+                    sr = fmaf(v.x, er, fmaf(-v.y, ei, sr));
+                    const float nr = er * cz - ei * szs, ni = er * szs + ei * cz;
+                    er = nr;
+                    ei = ni;
+                }
+                part += (double)sr;
+            }
+            acc = fma(part, 1.0 / (6.283185307179586 * dd), acc);
+        }
+    }
+    if (n < N) store_val(img, (size_t)n, IMG_DT, (float)acc);
+}
+
+}  // namespace
+
+size_t sph_workspace_bytes(const Problem &P, int n_f)
+{
+    return sizeof(double2) * (size_t)SPH_CHUNKS * P.nq * n_f;
+}
+
+hipError_t launch_sph_project(const Problem &P, const void *img, int img_dt, float2 *u, int n_f,
+                              double f_min, double df, double2 *part, hipStream_t s)
+{
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    const int LB = (n_f + SPH_FB - 1) / SPH_FB;
+    const int QB = SPH_THREADS / LB;
+    const long long chunk_len = (N + SPH_CHUNKS - 1) / SPH_CHUNKS;
+    const int nchunk = (int)((N + chunk_len - 1) / chunk_len);
+    dim3 grid((P.nq + QB - 1) / QB, nchunk);
+    hipLaunchKernelGGL(sph_fwd_kernel, grid, dim3(SPH_THREADS), 0, s, P, img, img_dt, n_f, f_min,
+                       df, LB, chunk_len, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long total = (long long)P.nq * n_f;
+    hipLaunchKernelGGL(sph_fwd_reduce_kernel, dim3((unsigned)((total + SPH_THREADS - 1) / SPH_THREADS)),
+                       dim3(SPH_THREADS), 0, s, P, part, nchunk, n_f, f_min, df, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, double f_min,
+                                  double df, void *img, int img_dt, hipStream_t s)
+{
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    const int qt = (8192 / n_f) > 1 ? 8192 / n_f : 1;
+    const size_t shm = sizeof(float2) * (size_t)qt * n_f;
+    dim3 grid((unsigned)((N + SPH_THREADS - 1) / SPH_THREADS));
+    if (img_dt == 0)
+        hipLaunchKernelGGL(sph_adj_kernel<0>, grid, dim3(SPH_THREADS), shm, s, P, u, n_f, f_min, df,
+                           img);
+    else
+        hipLaunchKernelGGL(sph_adj_kernel<1>, grid, dim3(SPH_THREADS), shm, s, P, u, n_f, f_min, df,
+                           img);
+    return hipGetLastError();
+}
+
+}  // namespace oat

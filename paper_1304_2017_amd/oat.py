@@ -29,7 +29,7 @@ OAT_FLAG_SRT_ONLY = 1
 
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
             "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",
-            "oat_plan_set_eir", "oat_deconvolve",
+            "oat_plan_set_eir", "oat_deconvolve", "oat_sph_project", "oat_sph_backproject",
             # include/oat_cnn.h
             "oat_conv3d_forward", "oat_conv3d_backward_weight_workspace",
             "oat_conv3d_backward_weight", "oat_adam_step", "oat_mse_workspace", "oat_mse")
@@ -93,6 +93,13 @@ def lib():
         L.oat_deconvolve.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_uint32, vp]
         L.oat_deconvolve.restype = ctypes.c_int
+        d = ctypes.c_double
+        L.oat_sph_project.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, d, d,
+                                      ctypes.c_uint32, vp]
+        L.oat_sph_project.restype = ctypes.c_int
+        L.oat_sph_backproject.argtypes = [vp, vp, ctypes.c_int, d, d, vp, ctypes.c_int,
+                                          ctypes.c_uint32, vp]
+        L.oat_sph_backproject.restype = ctypes.c_int
         L.oat_last_error.argtypes = []
         L.oat_last_error.restype = ctypes.c_char_p
         L.oat_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -253,6 +260,32 @@ class Plan:
         _check(lib().oat_plan_set_eir(self._h, taps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       int(taps.size)))
         self._eir = taps.copy() if taps.size else None
+
+    def sph_project(self, img, n_f: int, f_min: float, df: float, out=None, stream=None):
+        """Spherical-voxel model, Eq. (dis_sph): complex64 [n_det][n_f]."""
+        import torch
+        img = self._prep(img, self.image_shape)
+        if out is None:
+            out = torch.empty((self.geom.n_det, n_f), device=img.device, dtype=torch.complex64)
+        assert out.dtype == torch.complex64 and out.is_contiguous()
+        assert tuple(out.shape) == (self.geom.n_det, n_f)
+        _check(lib().oat_sph_project(self._h, ctypes.c_void_p(img.data_ptr()), _dtype_code(img),
+                                     ctypes.c_void_p(out.data_ptr()), int(n_f), float(f_min),
+                                     float(df), 0, self._stream(stream)))
+        return out
+
+    def sph_backproject(self, u, f_min: float, df: float, out=None, out_dtype=None, stream=None):
+        """Eq. (sphbwd) (real part): u complex64 [n_det][n_f] -> image."""
+        import torch
+        assert u.is_cuda and u.dtype == torch.complex64 and u.is_contiguous()
+        assert u.shape[0] == self.geom.n_det
+        n_f = int(u.shape[1])
+        if out is None:
+            out = torch.empty(self.image_shape, device=u.device, dtype=out_dtype or torch.float32)
+        _check(lib().oat_sph_backproject(self._h, ctypes.c_void_p(u.data_ptr()), n_f,
+                                         float(f_min), float(df), ctypes.c_void_p(out.data_ptr()),
+                                         _dtype_code(out), 0, self._stream(stream)))
+        return out
 
     def deconvolve(self, u, f_cut: float, out=None, out_dtype=None, stream=None):
         """Hann-window Fourier deconvolution of the plan's EIR (Sec. IV.B),

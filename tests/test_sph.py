@@ -69,3 +69,122 @@ def test_voxel_at_the_centre_of_a_transducer_sphere():
     gd = dict(geom.as_dict(), nx=1, ny=1, nz=1, x0=0.0, y0=0.0, z0=0.0)
     u = ref.sph_project(gd, np.ones((1, 1, 1)), 5, 0.5, 0.5)
     assert np.max(np.abs(u - u[0])) < 1e-13 * np.max(np.abs(u))
+
+
+# --------------------------------------------------------------------------
+# The library's H_sph and H_sph^T against the oracle (GPU)
+# --------------------------------------------------------------------------
+gpu = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _small_geom(nx=12, ny=10, nz=8):
+    g = synth.config_small(0)[0]
+    return synth.Geometry(nx, ny, nz, g.dx, synth.centred_origin(nx, g.dx),
+                          synth.centred_origin(ny, g.dx), synth.centred_origin(nz, g.dx),
+                          g.det_xyz, g.n_t, g.dt, g.t0, g.c0, 1.3)
+
+
+@pytest.fixture(scope="module")
+def small_sph():
+    from paper_1304_2017_amd.oat import Plan
+    geom = _small_geom()
+    return geom, Plan(geom, 0)
+
+
+@gpu
+@pytest.mark.parametrize("n_f,f0,df", [(40, 0.1, 0.1), (7, 0.0, 0.35), (130, 0.02, 0.038)])
+def test_sph_project_and_backproject(small_sph, n_f, f0, df):
+    geom, plan = small_sph
+    gd = geom.as_dict()
+    rng = np.random.default_rng(n_f)
+    a = rng.uniform(0, 1, size=geom.shape).astype(np.float32).astype(np.float64)
+    a[rng.uniform(size=geom.shape) < 0.3] = 0.0          # some empty voxels
+    u = plan.sph_project(torch.from_numpy(a).float().cuda(), n_f, f0, df)
+    u2 = plan.sph_project(torch.from_numpy(a).float().cuda(), n_f, f0, df)
+    torch.cuda.synchronize()
+    e = rel(u.cpu().numpy(), ref.sph_project(gd, a, n_f, f0, df))
+    y = (rng.normal(size=(geom.n_det, n_f)) + 1j * rng.normal(size=(geom.n_det, n_f)))
+    y = y.astype(np.complex64)
+    b = plan.sph_backproject(torch.from_numpy(y).cuda(), f0, df)
+    torch.cuda.synchronize()
+    eT = rel(b.double().cpu().numpy(), ref.sph_backproject(gd, y.astype(np.complex128), n_f, f0, df))
+    # adjoint identity through the library, scaled by the norms
+    uy = torch.from_numpy(y).cuda()
+    lhs = float(torch.real(torch.sum(torch.conj(uy.to(torch.complex128)) * u.to(torch.complex128))))
+    rhs = float(torch.sum(torch.from_numpy(a).cuda() * plan.sph_backproject(uy, f0, df).double()))
+    scale = float(u.abs().double().norm() * uy.abs().double().norm())
+    _say(f"[gpu] H_sph n_f {n_f}: rel {e:.3e}  H_sph^T rel {eT:.3e}  "
+         f"adjoint {abs(lhs - rhs) / scale:.3e}")
+    assert e < 1e-5 and eT < 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    assert torch.equal(u, u2)
+
+
+@gpu
+def test_sph_bf16_image(small_sph):
+    geom, plan = small_sph
+    rng = np.random.default_rng(3)
+    ab = torch.from_numpy(rng.uniform(0, 1, size=geom.shape)).to(torch.bfloat16)
+    u = plan.sph_project(ab.cuda(), 16, 0.2, 0.2)
+    torch.cuda.synchronize()
+    e = rel(u.cpu().numpy(), ref.sph_project(geom.as_dict(), ab.double().numpy(), 16, 0.2, 0.2))
+    y = torch.from_numpy((rng.normal(size=(geom.n_det, 16)) + 1j * rng.normal(size=(geom.n_det, 16)))
+                         .astype(np.complex64)).cuda()
+    b = plan.sph_backproject(y, 0.2, 0.2, out_dtype=torch.bfloat16)
+    torch.cuda.synchronize()
+    eb = rel(b.double().cpu().numpy(),
+             ref.sph_backproject(geom.as_dict(), y.cpu().numpy().astype(np.complex128), 16, 0.2, 0.2))
+    _say(f"[gpu] H_sph BF16 image rel {e:.3e}; H_sph^T BF16 output rel {eb:.3e}")
+    assert e < 1e-5 and eb < 2e-3
+
+
+@gpu
+def test_sph_arguments(small_sph):
+    from paper_1304_2017_amd import oat
+    geom, plan = small_sph
+    L = oat.lib()
+    x = torch.zeros(geom.shape, device="cuda")
+    u = torch.zeros((geom.n_det, 4), device="cuda", dtype=torch.complex64)
+    vp = oat.ctypes.c_void_p
+    assert L.oat_sph_project(plan._h, vp(x.data_ptr()), 0, vp(u.data_ptr()), 0, 0.0, 1.0, 0,
+                             None) == oat.OAT_ERR_ARG
+    assert L.oat_sph_project(plan._h, vp(x.data_ptr()), 0, vp(u.data_ptr()), 4, 0.0, -1.0, 0,
+                             None) == oat.OAT_ERR_ARG
+    assert L.oat_sph_backproject(plan._h, vp(u.data_ptr()), 4, 0.0, 1.0, vp(x.data_ptr()), 5, 0,
+                                 None) == oat.OAT_ERR_DTYPE
+
+
+@gpu
+def test_sph_at_64cube_2048_rows_and_voxels():
+    """64^3 at 0.4 mm, 2048 hemisphere transducers, 256 frequencies in
+    (0, 5] MHz (the benchmark's shape): sampled rows of H_sph and sampled
+    voxels of H_sph^T against the oracle."""
+    from paper_1304_2017_amd.oat import Plan
+    geom, img = synth.config_sph()
+    plan = Plan(geom, 0)
+    n_f, df = 256, 5.0 / 256
+    gd = geom.as_dict()
+    u = plan.sph_project(torch.from_numpy(img).float().cuda(), n_f, df, df)
+    torch.cuda.synchronize()
+    rows = np.array([0, 1023, 2047])
+    e = rel(u.cpu().numpy()[rows], ref.sph_project(gd, img.astype(np.float64), n_f, df, df, rows=rows))
+    rng = np.random.default_rng(4)
+    y = (rng.normal(size=(geom.n_det, n_f)) + 1j * rng.normal(size=(geom.n_det, n_f))).astype(np.complex64)
+    b = plan.sph_backproject(torch.from_numpy(y).cuda(), df, df)
+    torch.cuda.synchronize()
+    vox = rng.choice(geom.n_vox, 40, replace=False)
+    eT = rel(b.double().cpu().numpy().ravel()[vox],
+             ref.sph_backproject(gd, y.astype(np.complex128), n_f, df, df, voxels=vox))
+    _say(f"[gpu-full] H_sph 64^3/2048/256 rows rel {e:.3e}; H_sph^T voxels rel {eT:.3e}")
+    assert e < 1e-5 and eT < 1e-5
