@@ -210,7 +210,7 @@ int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oa
  * alpha_n is the voxel's absorbed-energy density; r_n are the plan's nodes.
  * img: device [nz][ny][nx] (oat_dtype); u: device [n_det][n_f] complex FP32,
  * interleaved (re, im).  Every term is evaluated (a dense sum); phases and
- * sums are FP64, exponentials FP32.  1 <= n_f <= 8192, f_min >= 0, df > 0,
+ * sums are FP64, exponentials FP32.  1 <= n_f <= 4096, f_min >= 0, df > 0,
  * flags = 0.  oat_sph_project keeps a workspace in the plan and may allocate
  * it on the first call with a larger n_f.  Results are deterministic. */
 int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,

@@ -738,9 +738,9 @@ static int check_sph(oat_plan *plan, const void *a, const void *b, int img_dt, i
     if (img_dt != OAT_F32 && img_dt != OAT_BF16)
         return fail(OAT_ERR_DTYPE, std::string(who) + ": unknown dtype");
     if (flags) return fail(OAT_ERR_ARG, std::string(who) + ": unknown flag");
-    if (n_f < 1 || n_f > 8192 || !(f_min >= 0.0) || !std::isfinite(f_min) || !(df > 0.0) ||
+    if (n_f < 1 || n_f > 4096 || !(f_min >= 0.0) || !std::isfinite(f_min) || !(df > 0.0) ||
         !std::isfinite(df))
-        return fail(OAT_ERR_ARG, std::string(who) + ": need 1 <= n_f <= 8192, f_min >= 0, df > 0");
+        return fail(OAT_ERR_ARG, std::string(who) + ": need 1 <= n_f <= 4096, f_min >= 0, df > 0");
     return OAT_OK;
 }
 

@@ -20,9 +20,10 @@ namespace oat {
 namespace {
 
 constexpr int SPH_THREADS = 256;
-constexpr int SPH_FB = 8;        // frequencies per thread (forward)
+constexpr int SPH_FB = 16;       // frequencies per thread (forward)
 constexpr int SPH_TILE = 256;    // voxels staged per LDS tile (forward)
 constexpr int SPH_ANCHOR = 16;   // recurrence steps between exact phases (adjoint)
+constexpr int SPH_VQ = 4096;     // staged u p0* values per adjoint tile (32 KB: 4 groups per CU)
 
 __device__ __forceinline__ double frac_turn(double x) { return x - floor(x); }
 
@@ -152,7 +153,7 @@ sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, d
     double x = 0.0, y = 0.0, z = 0.0;
     if (n < N) node_pos(P, n, x, y, z);
     const double inv_c0 = 1.0 / P.c0d;
-    const int qt = max(1, 8192 / n_f);   // transducers per LDS tile (64 KB)
+    const int qt = max(1, SPH_VQ / n_f);   // transducers per LDS tile (32 KB)
     double acc = 0.0;
     for (int q0 = 0; q0 < P.nq; q0 += qt) {
         const int nq = min(qt, P.nq - q0);
@@ -206,6 +207,8 @@ hipError_t launch_sph_project(const Problem &P, const void *img, int img_dt, flo
                               double f_min, double df, double2 *part, hipStream_t s)
 {
     const long long N = (long long)P.nx * P.ny * P.nz;
+    // n_f <= SPH_THREADS * SPH_FB (checked by the caller): a transducer's
+    // frequency blocks fit one workgroup.
     const int LB = (n_f + SPH_FB - 1) / SPH_FB;
     const int QB = SPH_THREADS / LB;
     const long long chunk_len = (N + SPH_CHUNKS - 1) / SPH_CHUNKS;
@@ -225,7 +228,7 @@ hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, do
                                   double df, void *img, int img_dt, hipStream_t s)
 {
     const long long N = (long long)P.nx * P.ny * P.nz;
-    const int qt = (8192 / n_f) > 1 ? 8192 / n_f : 1;
+    const int qt = (SPH_VQ / n_f) > 1 ? SPH_VQ / n_f : 1;
     const size_t shm = sizeof(float2) * (size_t)qt * n_f;
     dim3 grid((unsigned)((N + SPH_THREADS - 1) / SPH_THREADS));
     if (img_dt == 0)

@@ -163,6 +163,25 @@ def test_sph_arguments(small_sph):
                              None) == oat.OAT_ERR_ARG
     assert L.oat_sph_backproject(plan._h, vp(u.data_ptr()), 4, 0.0, 1.0, vp(x.data_ptr()), 5, 0,
                                  None) == oat.OAT_ERR_DTYPE
+    big = torch.zeros((geom.n_det, 4097), device="cuda", dtype=torch.complex64)
+    assert L.oat_sph_project(plan._h, vp(x.data_ptr()), 0, vp(big.data_ptr()), 4097, 0.0, 1.0, 0,
+                             None) == oat.OAT_ERR_ARG
+
+
+@gpu
+def test_sph_largest_frequency_count(small_sph):
+    """n_f = 4096, the largest accepted: one workgroup holds a transducer's
+    frequency blocks."""
+    geom, plan = small_sph
+    rng = np.random.default_rng(11)
+    a = np.zeros(geom.shape)
+    a[rng.uniform(size=geom.shape) < 0.05] = 1.0
+    u = plan.sph_project(torch.from_numpy(a).float().cuda(), 4096, 0.0, 0.002)
+    torch.cuda.synchronize()
+    rows = np.array([0, 37])
+    e = rel(u.cpu().numpy()[rows], ref.sph_project(geom.as_dict(), a, 4096, 0.0, 0.002, rows=rows))
+    _say(f"[gpu] H_sph n_f 4096: rel {e:.3e}")
+    assert e < 1e-5
 
 
 @gpu
