@@ -267,8 +267,9 @@ class Plan:
         img = self._prep(img, self.image_shape)
         if out is None:
             out = torch.empty((self.geom.n_det, n_f), device=img.device, dtype=torch.complex64)
-        assert out.dtype == torch.complex64 and out.is_contiguous()
-        assert tuple(out.shape) == (self.geom.n_det, n_f)
+        if out.dtype != torch.complex64:
+            raise TypeError("sph_project output must be complex64")
+        self._prep(out, (self.geom.n_det, n_f))
         _check(lib().oat_sph_project(self._h, ctypes.c_void_p(img.data_ptr()), _dtype_code(img),
                                      ctypes.c_void_p(out.data_ptr()), int(n_f), float(f_min),
                                      float(df), 0, self._stream(stream)))
@@ -277,11 +278,13 @@ class Plan:
     def sph_backproject(self, u, f_min: float, df: float, out=None, out_dtype=None, stream=None):
         """Eq. (sphbwd) (real part): u complex64 [n_det][n_f] -> image."""
         import torch
-        assert u.is_cuda and u.dtype == torch.complex64 and u.is_contiguous()
-        assert u.shape[0] == self.geom.n_det
+        if not isinstance(u, torch.Tensor) or u.dtype != torch.complex64 or u.dim() != 2:
+            raise TypeError("sph_backproject expects complex64 data of shape [n_det, n_f]")
         n_f = int(u.shape[1])
+        self._prep(u, (self.geom.n_det, n_f))
         if out is None:
             out = torch.empty(self.image_shape, device=u.device, dtype=out_dtype or torch.float32)
+        self._prep(out, self.image_shape)
         _check(lib().oat_sph_backproject(self._h, ctypes.c_void_p(u.data_ptr()), n_f,
                                          float(f_min), float(df), ctypes.c_void_p(out.data_ptr()),
                                          _dtype_code(out), 0, self._stream(stream)))

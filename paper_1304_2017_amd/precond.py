@@ -44,12 +44,20 @@ def conv3d(x: torch.Tensor, weight: torch.Tensor, bias: Optional[torch.Tensor], 
     ci, d, h, w = x.shape
     co = weight.shape[0]
     out_dtype = out_dtype or x.dtype
+    if tuple(weight.shape) != (co, ci, 27) or weight.dtype != torch.float32:
+        raise ValueError(f"weight must be float32 [{co}, {ci}, 27], got {weight.dtype} {tuple(weight.shape)}")
+    if bias is not None and (tuple(bias.shape) != (co,) or bias.dtype != torch.float32):
+        raise ValueError(f"bias must be float32 [{co}]")
     y = torch.empty((co, d, h, w), device=x.device, dtype=out_dtype)
-    if mask is not None:
-        assert mask.shape == y.shape and mask.dtype == out_dtype and mask.is_contiguous()
+    if mask is not None and (mask.shape != y.shape or mask.dtype != out_dtype
+                             or not mask.is_contiguous()):
+        raise ValueError("mask must be contiguous with the output's shape and dtype")
+    # the contiguous operands stay referenced until the launch is queued
+    xc, wc = x.contiguous(), weight.contiguous()
+    bc = bias.contiguous() if bias is not None else None
     oat._check(oat.lib().oat_conv3d_forward(
-        _ptr(x.contiguous()), _DT[x.dtype], ci, d, h, w, _ptr(weight.contiguous()),
-        _ptr(bias), co, _ptr(y), _DT[out_dtype], int(relu), _ptr(mask), _stream()))
+        _ptr(xc), _DT[x.dtype], ci, d, h, w, _ptr(wc),
+        _ptr(bc), co, _ptr(y), _DT[out_dtype], int(relu), _ptr(mask), _stream()))
     return y
 
 
@@ -63,8 +71,11 @@ def conv3d_weight_grad(x: torch.Tensor, dy: torch.Tensor):
     work = torch.empty(max(ws // 4, 1), device=x.device, dtype=torch.float32)
     dw = torch.empty((co, ci, 27), device=x.device, dtype=torch.float32)
     db = torch.empty((co,), device=x.device, dtype=torch.float32)
+    if tuple(dy.shape) != (co, d, h, w):
+        raise ValueError(f"dy must have shape {(co, d, h, w)}, got {tuple(dy.shape)}")
+    xc, dyc = x.contiguous(), dy.contiguous()
     oat._check(L.oat_conv3d_backward_weight(
-        _ptr(x.contiguous()), _DT[x.dtype], _ptr(dy.contiguous()), _DT[dy.dtype], ci, co, d, h, w,
+        _ptr(xc), _DT[x.dtype], _ptr(dyc), _DT[dy.dtype], ci, co, d, h, w,
         _ptr(dw), _ptr(db), _ptr(work), ws, _stream()))
     return dw, db
 
@@ -78,10 +89,13 @@ def flip_transpose(weight: torch.Tensor) -> torch.Tensor:
 def mse(y: torch.Tensor, target: torch.Tensor):
     """(loss as a device scalar, dloss/dy) in the library kernel."""
     L = oat.lib()
+    if y.shape != target.shape:
+        raise ValueError(f"mse: shapes {tuple(y.shape)} and {tuple(target.shape)} differ")
     loss = torch.empty((1,), device=y.device, dtype=torch.float32)
-    dy = torch.empty_like(y)
+    dy = torch.empty(y.shape, device=y.device, dtype=y.dtype)
     work = torch.empty(L.oat_mse_workspace() // 4, device=y.device, dtype=torch.float32)
-    oat._check(L.oat_mse(_ptr(y.contiguous()), _DT[y.dtype], _ptr(target.contiguous()),
+    yc, tc = y.contiguous(), target.contiguous()
+    oat._check(L.oat_mse(_ptr(yc), _DT[y.dtype], _ptr(tc),
                          _DT[target.dtype], y.numel(), _ptr(loss), _ptr(dy), _ptr(work), _stream()))
     return loss, dy
 
