@@ -147,12 +147,16 @@ def test_bf16_storage(small_bf16):
 
 
 # ---------------------------------------------------------------------------
-# Ragged grids, off-centre origins, t0 > 0, grids smaller than one brick.
+# Ragged grids, off-centre origins, t0 > 0, grids smaller than one brick, a
+# single node with the fewest samples allowed (3), whole bricks plus one
+# slice with samples at negative times (s = 0 there).
 # ---------------------------------------------------------------------------
 RAGGED = [
     dict(n=(37, 29, 23), dx=0.45, off=(0.3, -0.7, 0.2), Q=24, Rs=21.0, K=300, dt=0.08, t0=0.0),
     dict(n=(7, 5, 9), dx=0.8, off=(0.0, 0.0, 0.0), Q=10, Rs=15.0, K=200, dt=0.1, t0=2.0),
     dict(n=(41, 22, 3), dx=0.3, off=(-1.0, 0.5, 0.0), Q=16, Rs=18.0, K=400, dt=0.05, t0=5.0),
+    dict(n=(1, 1, 1), dx=0.5, off=(0.0, 0.0, 0.0), Q=3, Rs=5.0, K=3, dt=0.2, t0=3.0),
+    dict(n=(40, 20, 21), dx=0.5, off=(0.0, 0.0, 0.0), Q=8, Rs=22.0, K=260, dt=0.1, t0=-1.0),
 ]
 
 
