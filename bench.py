@@ -19,8 +19,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = non-packed FP32 VALU lane-ops/s.
-VALU_PEAK = 256 * 64 * 2.4e9
+# MI355X FP32 vector peak, 157.3 TFLOP/s (256 CUs at 2.4 GHz), with an FMA
+# counted as one lane-op: 7.86e13 lane-ops/s.  (A CU issues more than one
+# wave64 VALU instruction per cycle: the FBP kernel measures 1.24.)
+VALU_PEAK = 157.3e12 / 2
 HBM_PEAK = 8.0e12   # bytes/s
 # Algorithmic FP32 VALU operations of one quadrature point of G or G^T
 # (position 6 FMA, cos/sin of the azimuth 2 transcendental = 8 issue slots,
@@ -302,7 +304,7 @@ def sph_run(reps):
     nnz = int(np.count_nonzero(img))
     terms_f = float(nnz) * geom.n_det * n_f
     terms_b = float(geom.n_vox) * geom.n_det * n_f
-    peak = 256 * 64 * 2.4e9
+    peak = VALU_PEAK
     print(json.dumps(dict(
         workload="64^3 (0.4 mm), 2048 hemisphere transducers, 256 frequencies f_l = (l+1) * 5/256 MHz",
         H_sph_ms=t_f * 1e3, H_sph_T_ms=t_b * 1e3, nonzero_voxels=nnz, voxels=geom.n_vox,

@@ -147,15 +147,18 @@ adj_gather_kernel(Problem P, const double *__restrict__ acc, void *__restrict__ 
     store_val(img, ((size_t)z * P.ny + y) * P.nx + x, IMG_DT, (float)sum);
 }
 
-// FBP, Eq. (disfbp): one thread per voxel of a 16 x 16 x 1 tile, loop over
-// transducers in chunks.  For each chunk the samples a tile can touch,
-// k in [k_lo, k_lo + FBP_WIN), are staged in LDS per transducer (zero
-// outside [0, K)), so each update reads p_k and p_{k+1} with one LDS
-// access.  k~ is formed in FP32; when its fractional part lies within the
-// FP32 error bound of an integer, floor(k~) is decided in FP64 with the
-// problem statement's own formula, because Eq. (disfbp) switches its forward
-// difference at integer k~.
-constexpr int FBP_TX = 16, FBP_TY = 16;
+// FBP, Eq. (disfbp): a block takes a 16 x 16 x 8 tile of voxels, each thread
+// a column of FBP_TZ = 8 voxels along z, and loops over the transducers in
+// chunks; the transducer's data (position, weight, staged window) and the
+// x/y part of the squared distance are loaded or formed once per column.
+// For each chunk the samples a tile can touch, k in [k_lo, k_lo + win), are
+// staged in LDS per transducer (zero outside [0, K)), so each update reads
+// p_k and p_{k+1} with one LDS access.  k~ is formed in FP32; when its
+// fractional part lies within the FP32 error bound of an integer, floor(k~)
+// is decided exactly as the FP64 problem statement takes it (the plan's
+// threshold table), because Eq. (disfbp) switches its forward difference at
+// integer k~.
+constexpr int FBP_TX = 16, FBP_TY = 16, FBP_TZ = 8;
 constexpr int FBP_LDS = 8192;   // floats of staged samples per chunk
 
 template <int P_DT, int IMG_DT>
@@ -163,29 +166,41 @@ __global__ void __launch_bounds__(FBP_TX *FBP_TY)
 fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int win, int chunk)
 {
     __shared__ float sp[FBP_LDS];
-    __shared__ int2 sklo[FBP_LDS / 8];    // first staged sample, FP64-decision tolerance
+    __shared__ int2 sklo[FBP_LDS / 8];    // first staged sample, 1/2 - FP64-decision tolerance
     const int tx = threadIdx.x % FBP_TX, ty = threadIdx.x / FBP_TX;
-    const int ix = blockIdx.x * FBP_TX + tx, iy = blockIdx.y * FBP_TY + ty, iz = blockIdx.z;
-    const bool in = ix < P.nx && iy < P.ny;
-    const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+    const int ix = blockIdx.x * FBP_TX + tx, iy = blockIdx.y * FBP_TY + ty;
+    const int iz0 = blockIdx.z * FBP_TZ;
+    const float fx = (float)ix, fy = (float)iy;
+    float fz[FBP_TZ];
+#pragma unroll
+    for (int v = 0; v < FBP_TZ; ++v) fz[v] = (float)(iz0 + v);
     // tile centre and half-diagonal (grid units)
     const float cx = blockIdx.x * FBP_TX + 0.5f * (FBP_TX - 1), cy = blockIdx.y * FBP_TY + 0.5f * (FBP_TY - 1);
-    const float hd = 0.5f * sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1)));
+    const float cz = iz0 + 0.5f * (FBP_TZ - 1);
+    const float hd = 0.5f * sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1) +
+                                          (FBP_TZ - 1) * (FBP_TZ - 1)));
     const int K = P.nt;
-    float acc = 0.f;
+    // With fr = kt - k and inv = 1/(kt + tau) = ri c0 dt / dx, the two
+    // coefficients of Eq. (disfbp) are (1 - fr) inv - 1/2 and fr inv + 1/2,
+    // so a transducer adds w inv (p_k + fr (p_{k+1} - p_k)) + w (p_{k+1} - p_k) / 2.
+    // acc_a sums w ri (p_k + fr dp), acc_b sums w dp; the scale is applied once.
+    float acc_a[FBP_TZ], acc_b[FBP_TZ];
+#pragma unroll
+    for (int v = 0; v < FBP_TZ; ++v) acc_a[v] = acc_b[v] = 0.f;
     for (int q0 = 0; q0 < P.nq; q0 += chunk) {
         const int nq = min(chunk, P.nq - q0);
         __syncthreads();
         for (int j = threadIdx.x; j < nq; j += blockDim.x) {
             const DetRec &d = P.det[q0 + j];
-            const float vx = cx - d.uqf[0], vy = cy - d.uqf[1], vz = fz - d.uqf[2];
+            const float vx = cx - d.uqf[0], vy = cy - d.uqf[1], vz = cz - d.uqf[2];
             const float dc = sqrtf(vx * vx + vy * vy + vz * vz);
             // |FP32 kt - kt| <= 5e-7 (kt + tau) + 1e-6 (transducer position
             // rounded to FP32, the difference, the squared norm, rsqrt to
             // 1 ulp, the product); the tolerance is twice that at the tile's
             // largest kt.
             const float tol = fmaf(1e-6f, (dc + hd + 1.f) * P.sigma, 1e-5f);
-            sklo[j] = make_int2((int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2, __float_as_int(tol));
+            sklo[j] = make_int2((int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2,
+                                __float_as_int(0.5f - tol));
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nq * win; t += blockDim.x) {
@@ -202,44 +217,57 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
         __syncthreads();
         for (int j = 0; j < nq; ++j) {
             const DetRec &d = P.det[q0 + j];
-            const float vx = fx - d.uqf[0], vy = fy - d.uqf[1], vz = fz - d.uqf[2];
-            const float r2 = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
-            // r2 is hundreds of cells squared: the hardware rsqrt (1 ulp) needs
-            // no denormal scaling.
-            const float ri = __builtin_amdgcn_rsqf(r2);
-            const float kt = fmaf(r2 * ri, P.sigma, -P.tau);
-            float fr = __builtin_amdgcn_fractf(kt);
-            int ki = cvt_floor(kt);
-            // Within the tolerance of an integer, decide floor(kt) in FP64 from
-            // the problem statement in physical units (no contraction here).
+            const float vx = fx - d.uqf[0], vy = fy - d.uqf[1];
+            const float rxy = fmaf(vy, vy, vx * vx);
             const int2 sk = sklo[j];
-            const float tol = __int_as_float(sk.y);
-            if (fr < tol || fr > 1.f - tol) {
-                const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd, z = P.z0 + iz * P.dxd;
-                const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
-                const double dd = sqrt(wx * wx + wy * wy + wz * wz);
-                const double kt64 = (dd / P.c0d - P.t0d) / P.dtd;
-                ki = (int)floor(kt64);
-                fr = kt - (float)ki;
+            const float *row = sp + j * win;
+#pragma unroll
+            for (int v = 0; v < FBP_TZ; ++v) {
+                const float vz = fz[v] - d.uqf[2];
+                const float r2 = fmaf(vz, vz, rxy);
+                // r2 is hundreds of cells squared: the hardware rsqrt (1 ulp)
+                // needs no denormal scaling.
+                const float ri = __builtin_amdgcn_rsqf(r2);
+                const float kt = fmaf(r2 * ri, P.sigma, -P.tau);
+                float fr = __builtin_amdgcn_fractf(kt);
+                int ki = cvt_floor(kt);
+                // Within the tolerance of an integer m, floor(kt) of the FP64
+                // problem statement is m - 1 or m: decided by the FP64 squared
+                // distance in physical units (no contraction here) against the
+                // plan's threshold for m.  Outside m = -1 .. K both candidates
+                // select zero samples.
+                if (fabsf(fr - 0.5f) > __int_as_float(sk.y)) {
+                    const int m = fr > 0.5f ? ki + 1 : ki;
+                    if (m >= -1 && m <= K) {
+                        const double x = P.x0 + ix * P.dxd, y = P.y0 + iy * P.dxd,
+                                     z = P.z0 + (iz0 + v) * P.dxd;
+                        const double wx = x - d.r[0], wy = y - d.r[1], wz = z - d.r[2];
+                        const double r2d = wx * wx + wy * wy + wz * wz;
+                        ki = r2d >= P.fbp_thr[m + 1] ? m : m - 1;
+                        fr = kt - (float)ki;
+                    }
+                }
+                // ki - sk.x lies in 0 .. win - 2 (the window spans the tile's
+                // sample range with margins); the unsigned minimum only keeps
+                // the reads inside the row.
+                const unsigned li = min((unsigned)(ki - sk.x), (unsigned)(win - 2));
+                const float p0 = row[li], dp = row[li + 1] - p0;
+                acc_a[v] = fmaf(d.fbp_w * ri, fmaf(fr, dp, p0), acc_a[v]);
+                acc_b[v] = fmaf(d.fbp_w, dp, acc_b[v]);
             }
-            // With fr = kt - k and inv = 1/(kt + tau) the two coefficients of
-            // Eq. (disfbp) are (1 - fr) inv - 1/2 and fr inv + 1/2, so the term
-            // is inv (p_k + fr (p_{k+1} - p_k)) + (p_{k+1} - p_k) / 2.
-            const float inv = ri * P.inv_sigma;
-            int li = ki - sk.x;
-            li = min(max(li, 0), win - 2);
-            const float *pr = sp + j * win + li;
-            const float p0 = pr[0], dp = pr[1] - p0;
-            acc = fmaf(d.fbp_w, fmaf(inv, fmaf(fr, dp, p0), 0.5f * dp), acc);
         }
     }
-    if (in) {
-        const size_t n = ((size_t)iz * P.ny + iy) * P.nx + ix;
-        const float v = P.fbp_scale * acc;
-        if (IMG_DT == 0)
-            ((float *)img)[n] = v;
-        else
-            ((unsigned short *)img)[n] = to_bf16(v);
+    if (ix < P.nx && iy < P.ny) {
+#pragma unroll
+        for (int v = 0; v < FBP_TZ; ++v) {
+            if (iz0 + v >= P.nz) break;
+            const size_t n = ((size_t)(iz0 + v) * P.ny + iy) * P.nx + ix;
+            const float val = P.fbp_scale * fmaf(P.inv_sigma, acc_a[v], 0.5f * acc_b[v]);
+            if (IMG_DT == 0)
+                ((float *)img)[n] = val;
+            else
+                ((unsigned short *)img)[n] = to_bf16(val);
+        }
     }
 }
 
@@ -274,12 +302,13 @@ hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img, i
                       hipStream_t s)
 {
     // Samples a tile can touch per transducer: its diagonal in shells plus margins.
-    const float diag = sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1)));
+    const float diag = sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1) +
+                                     (FBP_TZ - 1) * (FBP_TZ - 1)));
     int win = (int)ceilf(diag * P.sigma) + 6;
     int chunk = FBP_LDS / win;
     if (chunk > FBP_LDS / 8) chunk = FBP_LDS / 8;
     if (chunk < 1) return hipErrorInvalidValue;
-    dim3 grid((P.nx + FBP_TX - 1) / FBP_TX, (P.ny + FBP_TY - 1) / FBP_TY, P.nz);
+    dim3 grid((P.nx + FBP_TX - 1) / FBP_TX, (P.ny + FBP_TY - 1) / FBP_TY, (P.nz + FBP_TZ - 1) / FBP_TZ);
     dim3 block(FBP_TX * FBP_TY);
     if (p_dtype == 0 && img_dtype == 0)
         hipLaunchKernelGGL((fbp_kernel<0, 0>), grid, block, 0, s, P, p, img, win, chunk);

@@ -259,15 +259,12 @@ OAT_HD void sincos_turns_d(double x, double &c, double &s)
     cp = fma(z2, cp, 4.1666666666666667e-02);
     cp = fma(z2, cp, -0.5);
     cp = fma(z2, cp, 1.0);
-    double cc, ss;
-    switch (q) {
-        case 0: cc = cp; ss = sp; break;
-        case 1: cc = -sp; ss = cp; break;
-        case 2: cc = -cp; ss = -sp; break;
-        default: cc = sp; ss = -cp; break;
-    }
-    c = cc;
-    s = ss;
+    // Quadrant q: (cos, sin) = (cp, sp) turned by q quarter turns, i.e.
+    // swapped with a sign for odd q, both negated for q >= 2 (selects only).
+    const bool odd = (q & 1) != 0, neg = (q & 2) != 0;
+    const double cc = odd ? -sp : cp, ss = odd ? cp : sp;
+    c = neg ? -cc : cc;
+    s = neg ? -ss : ss;
 }
 
 // Taylor parts of a small rotation d (|d| <= pi/8): cm1 = cos d - 1, sn = sin d.

@@ -80,6 +80,9 @@ struct Problem {
     // problem statement: kt = (|r_n - r_q| / c0 - t0) / dt, r_n = r_0 + dx * n)
     double x0, y0, z0, dxd, c0d, t0d, dtd;
     double gammad;         // Gamma (spherical-voxel model)
+    // [nt + 2]: entry m + 1 (m = -1 .. nt) is the smallest FP64 squared
+    // distance (mm^2) at which that floor reaches m (see oat_fbp_floor.hpp)
+    const double *fbp_thr;
     float w_max;           // largest ring weight
     float r_sup;           // radius of the image support sphere / dx
     float *gp_rowmax;      // [nq] max |g'| per transducer over reachable samples (D^T kernel)

@@ -12,6 +12,7 @@
 
 #include "oat.h"
 #include "oat_internal.hpp"
+#include "oat_fbp_floor.hpp"
 #include "oat_geom.hpp"
 
 using namespace oat;
@@ -67,6 +68,7 @@ struct oat_plan {
     double *d_acc = nullptr;     // G^T brick node sums [bricks][BOX^3]
     float *d_rowmax = nullptr;   // [Q] max reachable |D^T y| per transducer
     float *d_adjr = nullptr;     // [bricks][windows] G^T calibration
+    double *d_fbp_thr = nullptr; // [K + 2] FBP floor thresholds (Problem::fbp_thr)
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
@@ -288,7 +290,7 @@ void oat_plan_destroy(oat_plan *plan)
                     plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
                     plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
                     plan->d_seg, plan->d_eir_h, plan->d_eir_spec, plan->d_eir_tw,
-                    plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part};
+                    plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part, plan->d_fbp_thr};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -500,6 +502,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     size_t acc_b = sizeof(double) * (size_t)nbricks * BOX3;        // G^T brick node sums
     size_t rowmax_b = sizeof(float) * (size_t)Q;
     size_t adjr_b = sizeof(float) * (size_t)nbricks * adj_windows(Q);
+    const std::vector<double> fbp_thr = fbp_floor_thresholds(g->c0, g->t0, g->dt, K);
+    size_t thr_b = sizeof(double) * fbp_thr.size();
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
@@ -508,7 +512,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = alloc((void **)&plan->d_gp, gp_b, "gp")) != hipSuccess ||
         (e = alloc((void **)&plan->d_acc, acc_b, "brick node sums")) != hipSuccess ||
         (e = alloc((void **)&plan->d_rowmax, rowmax_b, "gp row max")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_adjr, adjr_b, "G^T calibration")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_adjr, adjr_b, "G^T calibration")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_fbp_thr, thr_b, "FBP floor thresholds")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -516,7 +521,9 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     }
     if ((e = hipMemcpy(plan->d_det, det.data(), det_b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(plan->d_shell, shell.data(), sh_b, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(plan->d_ring, ring.data(), ring_b, hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(plan->d_ring, ring.data(), ring_b, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(plan->d_fbp_thr, fbp_thr.data(), thr_b, hipMemcpyHostToDevice)) !=
+            hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMemcpy");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -526,6 +533,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.shell = plan->d_shell;
     P.ring = plan->d_ring;
     P.gp_rowmax = plan->d_rowmax;
+    P.fbp_thr = plan->d_fbp_thr;
     P.adj_r = nullptr;
     P.tab_off = nullptr;
     P.tab_run = nullptr;
@@ -535,7 +543,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.seg = nullptr;
     P.seg_cnt = nullptr;
     plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + acc_b + rowmax_b);
-    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b);
+    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b + thr_b);
     if (table_budget != 0) {
         int code = build_arc_table(plan, table_budget);
         if (code == OAT_OK && seg_budget != 0 && plan->d_tab_arc)

@@ -51,27 +51,37 @@ __device__ __forceinline__ double bperm_d(int src, double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Exclusive prefix sum over the wave of values below 2^BITS, and the total,
-// from one ballot per bit (no cross-lane data movement).
-template <int BITS>
-__device__ __forceinline__ int excl_scan_ballot(int v, int &total)
-{
-    const uint64_t below = (1ull << lane_id()) - 1ull;
-    int ex = 0, tot = 0;
-#pragma unroll
-    for (int b = 0; b < BITS; ++b) {
-        uint64_t m = __ballot((v >> b) & 1);
-        ex += __popcll(m & below) << b;
-        tot += __popcll(m) << b;
-    }
-    total = tot;
-    return ex;
-}
-
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Exclusive prefix sum over the wave of non-negative values below 2^BITS,
+// and the total; all 64 lanes must be active (every caller runs in
+// wave-uniform control flow of full waves).  Inclusive sums within each row
+// of 16 lanes by row shifts of 1, 2, 4 and 8 (a lane whose source lies
+// outside the row adds 0), then the row totals carried across rows by the
+// two row broadcasts.
+template <int BITS>
+__device__ __forceinline__ int excl_scan_wave(int v, int &total)
+{
+    static_assert(BITS <= 24, "the wave total must fit an int");
+    int s = v;
+    s += dpp_i<0x111, 0xF>(s);   // row_shr:1
+    s += dpp_i<0x112, 0xF>(s);   // row_shr:2
+    s += dpp_i<0x114, 0xF>(s);   // row_shr:4
+    s += dpp_i<0x118, 0xF>(s);   // row_shr:8
+    s += dpp_i<0x142, 0xA>(s);   // row_bcast:15 into rows 1 and 3
+    s += dpp_i<0x143, 0xC>(s);   // row_bcast:31 into rows 2 and 3
+    total = __builtin_amdgcn_readlane(s, 63);
+    return s - v;
 }
 
 // Sum over the 64 lanes with DPP row operations (no LDS traffic); the result
@@ -119,7 +129,7 @@ template <int BITS>
 __device__ __forceinline__ void level_begin(Level &L, int cnt)
 {
     int total;
-    int excl = excl_scan_ballot<BITS>(cnt, total);
+    int excl = excl_scan_wave<BITS>(cnt, total);
     L.total = total;
     L.base = 0;
     int nw = (total + 31) >> 5;
@@ -403,7 +413,7 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 r_n = (int)(run >> 16);
             }
             int tot;
-            r_ex = excl_scan_ballot<16>(r_n, tot) + run_base;
+            r_ex = excl_scan_wave<16>(r_n, tot) + run_base;
             run_base += tot;
         }
         if (TAB) {

@@ -109,3 +109,15 @@ def test_host_arc_geometry_is_a_superset(tmp_path):
         assert r.stdout.startswith("OK"), r.stdout
         rings, inside = map(int, r.stdout.split()[1:3])
         assert inside > 10000
+
+
+def test_host_fbp_floor_thresholds(tmp_path):
+    exe = tmp_path / "fbp_floor_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1304_2017_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "fbp_floor_check.cpp"), "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("OK"), r.stdout
+    assert int(r.stdout.split()[1]) > 1000000

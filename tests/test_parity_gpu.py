@@ -111,6 +111,37 @@ def test_fbp_matches_oracle(small):
     assert e < 1e-5
 
 
+def test_fbp_floor_at_exact_sample_times(Plan):
+    """Nodes whose FP64 sample position kt is an exact integer (c0 dt = 1/8
+    mm, transducers on the axes 20 mm from a node-centred grid): the FP32 kt
+    lands within its error bound of the integer and the FP64 floor decides.
+    A wrong decision moves a term by half a sample difference, far above the
+    element-wise bound used here."""
+    n, dx = 33, 0.5
+    o = synth.centred_origin(n, dx)
+    det = np.array([[0, 0, 20.0], [0, 0, -20.0], [20.0, 0, 0], [-20.0, 0, 0],
+                    [0, 20.0, 0], [0, -20.0, 0]])
+    geom = synth.Geometry(n, n, n, dx, o, o, o, det, 300, 0.125, 0.0, 1.0, 1.0,
+                          np.full(6, 4.0 * np.pi * 400.0 / 6))
+    gd = geom.as_dict()
+    x, y, z = geom.node_coords()
+    kt = np.zeros((6,) + geom.shape)
+    for q in range(6):
+        d = np.sqrt((x - det[q, 0]) ** 2 + (y - det[q, 1]) ** 2 + (z - det[q, 2]) ** 2)
+        kt[q] = (d / 1.0 - 0.0) / 0.125
+    exact = int(np.count_nonzero(kt == np.floor(kt)))
+    _say(f"[gpu] FBP at exact sample times: {exact} node-transducer pairs with integer kt")
+    assert exact > 1000
+    plan = Plan(geom, 0)
+    rng = np.random.default_rng(11)
+    pr = rng.normal(size=(6, 300)).astype(np.float32).astype(np.float64)
+    f = _np(plan.fbp(_t(pr)))
+    fr = ref.fbp(gd, pr)
+    err = float(np.max(np.abs(f - fr)))
+    _say(f"  max abs error {err:.3e} of max |f| {np.max(np.abs(fr)):.3e}")
+    assert err <= 1e-5 * float(np.max(np.abs(fr)))
+
+
 def test_adjoint_identity_on_gpu(small):
     geom, _, _, plan, seed = small
     _say(f"[gpu] adjoint 32^3 seed {seed}")
