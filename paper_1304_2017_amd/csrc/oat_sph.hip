@@ -6,9 +6,10 @@
 //   f_l = f_min + l df,   d_qn = |r_q - r_n|.
 // Every (transducer, frequency, voxel) term is evaluated: a dense sum, bound
 // by the VALU.  Distances and phases are FP64 (a phase of hundreds of turns
-// must keep ~1e-7 turn); the complex exponentials are an accurate FP32
-// sincos of the phase's fractional turn plus a short FP32 rotation
-// recurrence along l; sums are FP64.
+// must keep ~1e-7 turn); the complex exponentials are an accurate sincos of
+// the phase's fractional turn followed by short FP32 recurrences along l (a
+// rotation in the forward kernel, Horner's rule in the adjoint); sums are
+// FP64.
 #include "oat_dtype.hpp"
 #include "oat_geom.hpp"
 #include "oat_internal.hpp"
@@ -22,8 +23,9 @@ namespace {
 constexpr int SPH_THREADS = 256;
 constexpr int SPH_FB = 16;       // frequencies per thread (forward)
 constexpr int SPH_TILE = 256;    // voxels staged per LDS tile (forward)
-constexpr int SPH_ANCHOR = 16;   // recurrence steps between exact phases (adjoint)
+constexpr int SPH_ANCHOR = 16;   // frequencies per Horner block (adjoint)
 constexpr int SPH_VQ = 4096;     // staged u p0* values per adjoint tile (32 KB: 4 groups per CU)
+constexpr int SPH_NV = 2;        // consecutive voxels per adjoint thread
 
 __device__ __forceinline__ double frac_turn(double x) { return x - floor(x); }
 
@@ -140,60 +142,100 @@ sph_fwd_reduce_kernel(Problem P, const double2 *__restrict__ part, int nchunk, i
     u[i] = make_float2((float)(p0.x * sr - p0.y * si), (float)(p0.x * si + p0.y * sr));
 }
 
-// One voxel per thread: out[n] = Re sum_q sum_l v[q,l] exp(+j 2 pi f_l d_qn / c0) / (2 pi d_qn),
-// v[q,l] = u[q,l] conj(p0(f_l)), staged per transducer in LDS.
+// SPH_NV consecutive voxels per thread:
+//   out[n] = Re sum_q sum_l v[q,l] exp(+j 2 pi f_l d_qn / c0) / (2 pi d_qn),
+//   v[q,l] = u[q,l] conj(p0(f_l)), staged per transducer in LDS.
+// The frequencies are taken in blocks of SPH_ANCHOR.  Within a block,
+// sum_i v[l0+i] z^i with z = exp(+j 2 pi df d/c0) is formed by Horner's rule
+// in FP32 (S <- S z + v, four FMAs per term); the block's anchor
+// A = exp(+j 2 pi f_l0 d/c0) comes from an FP64 recurrence (the first anchor
+// and the block step are FP64 sin/cos of fractional turns), and Re(A S) is
+// added in FP64.  One staged read serves the thread's voxels.
 template <int IMG_DT>
 __global__ void __launch_bounds__(SPH_THREADS)
 sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, double df,
                void *__restrict__ img)
 {
-    extern __shared__ float2 sv[];   // [qt][n_f]
+    extern __shared__ float2 sv[];   // [qt][n_fp]: rows padded with zeros to whole blocks
+    constexpr int NV = SPH_NV;
     const long long N = (long long)P.nx * P.ny * P.nz;
-    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    double x = 0.0, y = 0.0, z = 0.0;
-    if (n < N) node_pos(P, n, x, y, z);
+    const long long nb = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * NV;
+    double x[NV], y[NV], z[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        x[v] = y[v] = z[v] = 0.0;
+        if (nb + v < N) node_pos(P, nb + v, x[v], y[v], z[v]);
+    }
     const double inv_c0 = 1.0 / P.c0d;
-    const int qt = max(1, SPH_VQ / n_f);   // transducers per LDS tile (32 KB)
-    double acc = 0.0;
+    const double dfa = df * SPH_ANCHOR;
+    const int n_fp = (n_f + SPH_ANCHOR - 1) / SPH_ANCHOR * SPH_ANCHOR;
+    const int qt = max(1, SPH_VQ / n_fp);   // transducers per LDS tile (32 KB)
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     for (int q0 = 0; q0 < P.nq; q0 += qt) {
         const int nq = min(qt, P.nq - q0);
         __syncthreads();
-        for (int k = threadIdx.x; k < nq * n_f; k += blockDim.x) {
-            const int l = k % n_f;
-            const float2 v = u[(size_t)q0 * n_f + k];
-            const double2 p = sph_p0(P, f_min + df * (double)l);   // v * conj(p0)
-            sv[k] = make_float2((float)(v.x * p.x + v.y * p.y), (float)(v.y * p.x - v.x * p.y));
+        for (int k = threadIdx.x; k < nq * n_fp; k += blockDim.x) {
+            const int jq = k / n_fp, l = k % n_fp;
+            float2 val = make_float2(0.f, 0.f);   // zero terms pad the last block
+            if (l < n_f) {
+                const float2 w = u[(size_t)(q0 + jq) * n_f + l];
+                const double2 p = sph_p0(P, f_min + df * (double)l);   // w * conj(p0)
+                val = make_float2((float)(w.x * p.x + w.y * p.y), (float)(w.y * p.x - w.x * p.y));
+            }
+            sv[k] = val;
         }
         __syncthreads();
-        if (n >= N) continue;
+        if (nb >= N) continue;
         for (int j = 0; j < nq; ++j) {
             const DetRec &d = P.det[q0 + j];
-            const double vx = x - d.r[0], vy = y - d.r[1], vz = z - d.r[2];
-            const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
-            const double tau = dd * inv_c0;
-            float cz, szs;
-            sincos_turns((float)frac_turn(df * tau), cz, szs);
-            const float2 *vq = sv + j * n_f;
-            double part = 0.0;
-            for (int l0 = 0; l0 < n_f; l0 += SPH_ANCHOR) {
-                float c, s;
-                sincos_turns((float)frac_turn((f_min + df * (double)l0) * tau), c, s);
-                float er = c, ei = s;   // exp(+j theta)
-                float sr = 0.f;
-                const int le = min(n_f, l0 + SPH_ANCHOR);
-                for (int l = l0; l < le; ++l) {
-                    const float2 v = vq[l];
-                    sr = fmaf(v.x, er, fmaf(-v.y, ei, sr));
-                    const float nr = er * cz - ei * szs, ni = er * szs + ei * cz;
-                    er = nr;
-                    ei = ni;
-                }
-                part += (double)sr;
+            float zr[NV], zi[NV];
+            double ar[NV], ai[NV], gr[NV], gi[NV], rd[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double vx = x[v] - d.r[0], vy = y[v] - d.r[1], vz = z[v] - d.r[2];
+                const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
+                const double tau = dd * inv_c0;
+                sincos_turns((float)frac_turn(df * tau), zr[v], zi[v]);
+                sincos_turns_d(frac_turn(f_min * tau), ar[v], ai[v]);
+                sincos_turns_d(frac_turn(dfa * tau), gr[v], gi[v]);
+                rd[v] = 1.0 / (6.283185307179586 * dd);
             }
-            acc = fma(part, 1.0 / (6.283185307179586 * dd), acc);
+            const float2 *vq = sv + j * n_fp;
+            double part[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) part[v] = 0.0;
+            for (int l0 = 0; l0 < n_fp; l0 += SPH_ANCHOR) {
+                float sr[NV], si[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sr[v] = si[v] = 0.f;
+#pragma unroll
+                for (int i = SPH_ANCHOR - 1; i >= 0; --i) {
+                    const float2 w = vq[l0 + i];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const float nr = fmaf(sr[v], zr[v], fmaf(-si[v], zi[v], w.x));
+                        const float ni = fmaf(sr[v], zi[v], fmaf(si[v], zr[v], w.y));
+                        sr[v] = nr;
+                        si[v] = ni;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    part[v] = fma(ar[v], (double)sr[v], fma(-ai[v], (double)si[v], part[v]));
+                    const double tr = ar[v] * gr[v] - ai[v] * gi[v];
+                    ai[v] = ar[v] * gi[v] + ai[v] * gr[v];
+                    ar[v] = tr;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = fma(part[v], rd[v], acc[v]);
         }
     }
-    if (n < N) store_val(img, (size_t)n, IMG_DT, (float)acc);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (nb + v < N) store_val(img, (size_t)(nb + v), IMG_DT, (float)acc[v]);
 }
 
 }  // namespace
@@ -228,9 +270,11 @@ hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, do
                                   double df, void *img, int img_dt, hipStream_t s)
 {
     const long long N = (long long)P.nx * P.ny * P.nz;
-    const int qt = (SPH_VQ / n_f) > 1 ? SPH_VQ / n_f : 1;
-    const size_t shm = sizeof(float2) * (size_t)qt * n_f;
-    dim3 grid((unsigned)((N + SPH_THREADS - 1) / SPH_THREADS));
+    const int n_fp = (n_f + SPH_ANCHOR - 1) / SPH_ANCHOR * SPH_ANCHOR;
+    const int qt = (SPH_VQ / n_fp) > 1 ? SPH_VQ / n_fp : 1;
+    const size_t shm = sizeof(float2) * (size_t)qt * n_fp;
+    const long long threads = (N + SPH_NV - 1) / SPH_NV;
+    dim3 grid((unsigned)((threads + SPH_THREADS - 1) / SPH_THREADS));
     if (img_dt == 0)
         hipLaunchKernelGGL(sph_adj_kernel<0>, grid, dim3(SPH_THREADS), shm, s, P, u, n_f, f_min, df,
                            img);
