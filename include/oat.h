@@ -101,6 +101,13 @@ typedef struct oat_plan oat_plan;
  * oat_backproject returns G^T y (D and D^T are skipped). */
 #define OAT_FLAG_SRT_ONLY 1u
 
+/* Ask for bit-stable output (ordered reductions).  Every operator of this
+ * library already gives bit-identical results for identical inputs (G sums
+ * its partials in a fixed order, G^T adds exact fixed-point integers, FBP
+ * and the EIR and deconvolution kernels have no atomics), so the flag is
+ * accepted and changes nothing. */
+#define OAT_FLAG_DETERMINISTIC 2u
+
 /* Validate the geometry, build the quadrature tables in FP64 on the host,
  * upload them and allocate the workspace on `device`.
  * Returns OAT_ERR_GEOMETRY when a transducer lies inside the sphere that
@@ -197,7 +204,8 @@ int oat_plan_set_eir(oat_plan *plan, const double *h, int n_taps);
  * convolution, and the first n_t samples of the inverse transform are
  * returned.  Transforms in FP64.  f_cut in cycles per time unit (MHz when
  * times are in microseconds), > 0.  u, p: device [n_det][n_t], may not
- * alias.  Asynchronous on `stream`.  OAT_ERR_ARG when the plan has no EIR. */
+ * alias.  flags: 0 or OAT_FLAG_DETERMINISTIC.  Asynchronous on `stream`.
+ * OAT_ERR_ARG when the plan has no EIR. */
 int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oat_dtype p_dtype,
                    double f_cut, uint32_t flags, void *stream);
 
@@ -211,8 +219,9 @@ int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oa
  * img: device [nz][ny][nx] (oat_dtype); u: device [n_det][n_f] complex FP32,
  * interleaved (re, im).  Every term is evaluated (a dense sum); phases and
  * sums are FP64, exponentials FP32.  1 <= n_f <= 4096, f_min >= 0, df > 0,
- * flags = 0.  oat_sph_project keeps a workspace in the plan and may allocate
- * it on the first call with a larger n_f.  Results are deterministic. */
+ * flags: 0 or OAT_FLAG_DETERMINISTIC.  oat_sph_project keeps a workspace
+ * in the plan and may allocate it on the first call with a larger n_f.
+ * Results are deterministic. */
 int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,
                     double f_min, double df, uint32_t flags, void *stream);
 

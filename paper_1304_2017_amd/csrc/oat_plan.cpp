@@ -609,8 +609,8 @@ static int with_device(oat_plan *plan, int &prev)
 int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data,
                 oat_dtype data_dtype, uint32_t flags, void *stream)
 {
-    int rc = check_common(plan, img, img_dtype, data, data_dtype, flags, OAT_FLAG_SRT_ONLY,
-                          "oat_project");
+    int rc = check_common(plan, img, img_dtype, data, data_dtype, flags,
+                          OAT_FLAG_SRT_ONLY | OAT_FLAG_DETERMINISTIC, "oat_project");
     if (rc) return rc;
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
@@ -632,7 +632,8 @@ int oat_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *data
 int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void *img,
                     oat_dtype img_dtype, uint32_t flags, void *stream)
 {
-    int rc = check_common(plan, data, data_dtype, img, img_dtype, flags, OAT_FLAG_SRT_ONLY,
+    int rc = check_common(plan, data, data_dtype, img, img_dtype, flags,
+                          OAT_FLAG_SRT_ONLY | OAT_FLAG_DETERMINISTIC,
                           "oat_backproject");
     if (rc) return rc;
     int prev;
@@ -657,7 +658,8 @@ int oat_backproject(oat_plan *plan, const void *data, oat_dtype data_dtype, void
 int oat_fbp(oat_plan *plan, const void *pres, oat_dtype pres_dtype, void *img, oat_dtype img_dtype,
             uint32_t flags, void *stream)
 {
-    int rc = check_common(plan, pres, pres_dtype, img, img_dtype, flags, 0u, "oat_fbp");
+    int rc = check_common(plan, pres, pres_dtype, img, img_dtype, flags, OAT_FLAG_DETERMINISTIC,
+                          "oat_fbp");
     if (rc) return rc;
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
@@ -722,7 +724,8 @@ int oat_plan_set_eir(oat_plan *plan, const double *h, int n_taps)
 int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oat_dtype p_dtype,
                    double f_cut, uint32_t flags, void *stream)
 {
-    int rc = check_common(plan, u, u_dtype, p, p_dtype, flags, 0u, "oat_deconvolve");
+    int rc = check_common(plan, u, u_dtype, p, p_dtype, flags, OAT_FLAG_DETERMINISTIC,
+                          "oat_deconvolve");
     if (rc) return rc;
     if (plan->eir_taps == 0) return fail(OAT_ERR_ARG, "oat_deconvolve: the plan has no EIR");
     if (!(f_cut > 0.0) || !std::isfinite(f_cut))
@@ -745,7 +748,7 @@ static int check_sph(oat_plan *plan, const void *a, const void *b, int img_dt, i
     if (a == b) return fail(OAT_ERR_ARG, std::string(who) + ": input and output alias");
     if (img_dt != OAT_F32 && img_dt != OAT_BF16)
         return fail(OAT_ERR_DTYPE, std::string(who) + ": unknown dtype");
-    if (flags) return fail(OAT_ERR_ARG, std::string(who) + ": unknown flag");
+    if (flags & ~OAT_FLAG_DETERMINISTIC) return fail(OAT_ERR_ARG, std::string(who) + ": unknown flag");
     if (n_f < 1 || n_f > 4096 || !(f_min >= 0.0) || !std::isfinite(f_min) || !(df > 0.0) ||
         !std::isfinite(df))
         return fail(OAT_ERR_ARG, std::string(who) + ": need 1 <= n_f <= 4096, f_min >= 0, df > 0");

@@ -373,13 +373,16 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
         // 64 segment entries per window: (ring, jb | npts << 16 | (k - klo) << 22).
         const long long s0 = P.seg_off[unit], s1 = P.seg_off[unit + 1];
         const uint2 *seg = reinterpret_cast<const uint2 *>(P.seg);
+        // The next window's entries are loaded while this window runs.
+        uint2 nxt = s0 + lane < s1 ? seg[s0 + lane] : make_uint2(0u, 0u);
         for (long long c = s0; c < s1; c += WAVE) {
-            const long long ei = c + lane;
-            const bool v2 = ei < s1;
-            const uint2 ent = v2 ? seg[ei] : make_uint2(0u, 0u);
+            const bool v2 = c + lane < s1;
+            const uint2 ent = nxt;
+            const RingRec rr = P.ring[ent.x];
+            const long long en = c + WAVE + lane;
+            nxt = en < s1 ? seg[en] : make_uint2(0u, 0u);
             const int jb = (int)(ent.y & 0xffffu), npts = (int)((ent.y >> 16) & 63u);
             const int k2 = klo + (int)(ent.y >> 22);
-            const RingRec rr = P.ring[ent.x];
             float w2 = rr.w;
             if (ADJ && v2) w2 = w2 * ((gp[(size_t)q * P.nt + k2] * gscale) * gscale2);
             segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rr.rc, rr.rs,

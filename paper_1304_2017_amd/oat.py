@@ -26,6 +26,7 @@ OAT_ERR_INTERNAL = -6
 OAT_F32 = 0
 OAT_BF16 = 1
 OAT_FLAG_SRT_ONLY = 1
+OAT_FLAG_DETERMINISTIC = 2
 
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
             "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",

@@ -255,9 +255,28 @@ def test_repeat_runs(Plan):
     y = torch.randn((geom.n_det, geom.n_t), device=_dev())
     c = plan.backproject(y).clone()
     d = plan.backproject(y).clone()
+    f1 = plan.fbp(y).clone()
+    f2 = plan.fbp(y).clone()
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert torch.equal(c, d)
+    assert torch.equal(f1, f2)
+    # OAT_FLAG_DETERMINISTIC is accepted and changes nothing
+    from paper_1304_2017_amd import oat
+    L, h, s0 = oat.lib(), plan._h, oat.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out_d = torch.empty_like(a)
+    out_i = torch.empty_like(c)
+    out_f = torch.empty_like(f1)
+    P = lambda t: oat.ctypes.c_void_p(t.data_ptr())
+    assert L.oat_project(h, P(x), oat.OAT_F32, P(out_d), oat.OAT_F32,
+                         oat.OAT_FLAG_DETERMINISTIC, s0) == oat.OAT_OK
+    assert L.oat_backproject(h, P(y), oat.OAT_F32, P(out_i), oat.OAT_F32,
+                             oat.OAT_FLAG_DETERMINISTIC, s0) == oat.OAT_OK
+    assert L.oat_fbp(h, P(y), oat.OAT_F32, P(out_f), oat.OAT_F32,
+                     oat.OAT_FLAG_DETERMINISTIC, s0) == oat.OAT_OK
+    assert L.oat_fbp(h, P(y), oat.OAT_F32, P(out_f), oat.OAT_F32, 4, s0) == oat.OAT_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(out_d, a) and torch.equal(out_i, c) and torch.equal(out_f, f1)
 
 
 @pytest.mark.parametrize("seed", [0, 3])
