@@ -46,8 +46,10 @@ __global__ void __launch_bounds__(SPH_THREADS)
 sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, double f_min,
                double df, int LB, long long chunk_len, double2 *__restrict__ part)
 {
+    static_assert(SPH_TILE == SPH_THREADS && SPH_THREADS % 64 == 0, "one voxel per thread per tile");
     __shared__ double sx[SPH_TILE], sy[SPH_TILE], sz[SPH_TILE];
     __shared__ float sa[SPH_TILE];
+    __shared__ int wcnt[SPH_THREADS / 64];
     const int QB = SPH_THREADS / LB;
     const int t = threadIdx.x;
     const int q = blockIdx.x * QB + t / LB;
@@ -68,26 +70,37 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
 #pragma unroll
     for (int i = 0; i < SPH_FB; ++i) ar[i] = ai[i] = 0.0;
     for (long long base = n0; base < n1; base += SPH_TILE) {
+        // Stage the tile's non-zero voxels (their terms are the only
+        // non-zero ones), compacted in voxel order: wave ballots give each
+        // voxel its rank, so the sums keep the order of the voxels.
         __syncthreads();
         const long long n = base + t;
-        if (t < SPH_TILE) {
-            double x = 0.0, y = 0.0, z = 0.0;
-            float a = 0.f;
-            if (n < n1) {
-                node_pos(P, n, x, y, z);
-                a = load_val(img, (size_t)n, img_dt);
-            }
-            sx[t] = x;
-            sy[t] = y;
-            sz[t] = z;
-            sa[t] = a;
+        const float a_n = n < n1 ? load_val(img, (size_t)n, img_dt) : 0.f;
+        const bool keep = a_n != 0.f;
+        const uint64_t bal = __ballot(keep);
+        const int wv = t >> 6, ln = t & 63;
+        if (ln == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = 0, cnt = 0;
+#pragma unroll
+        for (int w = 0; w < SPH_THREADS / 64; ++w) {
+            const int c = wcnt[w];
+            off += w < wv ? c : 0;
+            cnt += c;
+        }
+        if (keep) {
+            const int pos = off + __popcll(bal & ((1ull << ln) - 1ull));
+            double x, y, z;
+            node_pos(P, n, x, y, z);
+            sx[pos] = x;
+            sy[pos] = y;
+            sz[pos] = z;
+            sa[pos] = a_n;
         }
         __syncthreads();
-        const int cnt = (int)min((long long)SPH_TILE, n1 - base);
         if (!active) continue;
         for (int j = 0; j < cnt; ++j) {
             const float a = sa[j];
-            if (a == 0.f) continue;
             const double vx = sx[j] - rqx, vy = sy[j] - rqy, vz = sz[j] - rqz;
             const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
             const double tau = dd * inv_c0;
