@@ -23,6 +23,7 @@ namespace {
 constexpr int SPH_THREADS = 256;
 constexpr int SPH_FB = 16;       // frequencies per thread (forward)
 constexpr int SPH_TILE = 256;    // voxels staged per LDS tile (forward)
+constexpr int SPH_SHARE = 1024;  // (transducer, voxel) values shared per step (forward)
 constexpr int SPH_ANCHOR = 16;   // frequencies per Horner block (adjoint)
 constexpr int SPH_VQ = 4096;     // staged u p0* values per adjoint tile (32 KB: 4 groups per CU)
 constexpr int SPH_NV = 2;        // consecutive voxels per adjoint thread
@@ -50,6 +51,8 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
     __shared__ double sx[SPH_TILE], sy[SPH_TILE], sz[SPH_TILE];
     __shared__ float sa[SPH_TILE];
     __shared__ int wcnt[SPH_THREADS / 64];
+    __shared__ double stau[SPH_SHARE], sw[SPH_SHARE];
+    __shared__ float2 sstep[SPH_SHARE];
     const int QB = SPH_THREADS / LB;
     const int t = threadIdx.x;
     const int q = blockIdx.x * QB + t / LB;
@@ -57,13 +60,6 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
     const bool active = (t / LB) < QB && q < P.nq && l0 < n_f;
     const long long N = (long long)P.nx * P.ny * P.nz;
     const long long n0 = (long long)blockIdx.y * chunk_len, n1 = min(N, n0 + chunk_len);
-    double rqx = 0.0, rqy = 0.0, rqz = 0.0;
-    if (q < P.nq) {
-        const DetRec &d = P.det[q];
-        rqx = d.r[0];
-        rqy = d.r[1];
-        rqz = d.r[2];
-    }
     const double inv_c0 = 1.0 / P.c0d;
     const double fa = f_min + df * (double)l0;   // first frequency of the thread
     double ar[SPH_FB], ai[SPH_FB];
@@ -97,27 +93,50 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
             sz[pos] = z;
             sa[pos] = a_n;
         }
-        __syncthreads();
-        if (!active) continue;
-        for (int j = 0; j < cnt; ++j) {
-            const float a = sa[j];
-            const double vx = sx[j] - rqx, vy = sy[j] - rqy, vz = sz[j] - rqz;
-            const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
-            const double tau = dd * inv_c0;
-            float c, s, cz, szs;
-            sincos_turns((float)frac_turn(fa * tau), c, s);
-            sincos_turns((float)frac_turn(df * tau), cz, szs);
-            // exp(-j theta) = (c, -s); step exp(-j dtheta) = (cz, -szs)
-            float er = c, ei = -s;
-            const float zr = cz, zi = -szs;
-            const double w = (double)a / (6.283185307179586 * dd);
+        // Per (transducer, voxel) values shared by the transducer's LB
+        // threads, formed once for SUB voxels at a time: tau = d/c0, the
+        // weight a/(2 pi d) and the frequency step exp(-j 2 pi df tau).
+        const int SUB = min(SPH_TILE, SPH_SHARE / QB);
+        for (int s0 = 0; s0 < cnt; s0 += SUB) {
+            const int m = min(SUB, cnt - s0);
+            __syncthreads();
+            for (int idx = t; idx < QB * m; idx += SPH_THREADS) {
+                const int ql = idx / m, jj = idx % m;
+                const int qq = blockIdx.x * QB + ql;
+                double tq = 0.0, wq = 0.0;
+                float cz = 1.f, szs = 0.f;
+                if (qq < P.nq) {
+                    const DetRec &d = P.det[qq];
+                    const double vx = sx[s0 + jj] - d.r[0], vy = sy[s0 + jj] - d.r[1],
+                                 vz = sz[s0 + jj] - d.r[2];
+                    const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
+                    tq = dd * inv_c0;
+                    wq = (double)sa[s0 + jj] / (6.283185307179586 * dd);
+                    sincos_turns((float)frac_turn(df * tq), cz, szs);
+                }
+                stau[idx] = tq;
+                sw[idx] = wq;
+                sstep[idx] = make_float2(cz, -szs);   // exp(-j dtheta)
+            }
+            __syncthreads();
+            if (!active) continue;
+            const int row = (t / LB) * m;
+            for (int jj = 0; jj < m; ++jj) {
+                const double tau = stau[row + jj], w = sw[row + jj];
+                const float2 zs = sstep[row + jj];
+                float c, sn;
+                sincos_turns((float)frac_turn(fa * tau), c, sn);
+                // exp(-j theta) = (c, -sn)
+                float er = c, ei = -sn;
+                const float zr = zs.x, zi = zs.y;
 #pragma unroll
-            for (int i = 0; i < SPH_FB; ++i) {
-                ar[i] = fma(w, (double)er, ar[i]);
-                ai[i] = fma(w, (double)ei, ai[i]);
-                const float nr = er * zr - ei * zi, ni = er * zi + ei * zr;
-                er = nr;
-                ei = ni;
+                for (int i = 0; i < SPH_FB; ++i) {
+                    ar[i] = fma(w, (double)er, ar[i]);
+                    ai[i] = fma(w, (double)ei, ai[i]);
+                    const float nr = er * zr - ei * zi, ni = er * zi + ei * zr;
+                    er = nr;
+                    ei = ni;
+                }
             }
         }
     }
