@@ -219,9 +219,11 @@ int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oa
  * img: device [nz][ny][nx] (oat_dtype); u: device [n_det][n_f] complex FP32,
  * interleaved (re, im).  Every term is evaluated (a dense sum); phases and
  * sums are FP64, exponentials FP32.  1 <= n_f <= 4096, f_min >= 0, df > 0,
- * flags: 0 or OAT_FLAG_DETERMINISTIC.  oat_sph_project keeps a workspace
- * in the plan and may allocate it on the first call with a larger n_f.
- * Results are deterministic. */
+ * flags: 0 or OAT_FLAG_DETERMINISTIC.  The two calls share a workspace in
+ * the plan and may allocate or grow it: oat_sph_project for a larger n_f,
+ * oat_sph_backproject for an image of fewer than 512K voxels, whose
+ * transducers it splits into slices of FP64 partial images (added in slice
+ * order).  Results are deterministic. */
 int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,
                     double f_min, double df, uint32_t flags, void *stream);
 

@@ -147,7 +147,12 @@ hipError_t launch_deconvolve(const Problem &P, const void *u, int u_dt, void *p,
 size_t sph_workspace_bytes(const Problem &P, int n_f);
 hipError_t launch_sph_project(const Problem &P, const void *img, int img_dt, float2 *u, int n_f,
                               double f_min, double df, double2 *part, hipStream_t s);
+// Adjoint: small images split the transducers into sph_adj_slices(P) slices
+// whose FP64 partial images go to work (sph_adj_workspace_bytes; none for
+// one slice).
+int sph_adj_slices(const Problem &P);
+size_t sph_adj_workspace_bytes(const Problem &P);
 hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, double f_min,
-                                  double df, void *img, int img_dt, hipStream_t s);
+                                  double df, void *img, int img_dt, double *work, hipStream_t s);
 
 }  // namespace oat

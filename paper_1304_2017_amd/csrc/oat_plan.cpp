@@ -78,7 +78,7 @@ struct oat_plan {
     double2 *d_eir_filt = nullptr;    // deconvolution filter of a call [eir_n]
     float *d_eirbuf = nullptr;        // D G img before H^e / H^e^T y before D^T  [Q][K]
     int eir_taps = 0, eir_n = 0;
-    double2 *d_sph_part = nullptr;    // spherical-voxel chunk sums
+    double2 *d_sph_part = nullptr;    // spherical-voxel workspace (chunk / slice sums)
     size_t sph_part_bytes = 0;
     long long *d_seg_off = nullptr;   // segment table (see Problem)
     unsigned *d_seg = nullptr;
@@ -755,6 +755,25 @@ static int check_sph(oat_plan *plan, const void *a, const void *b, int img_dt, i
     return OAT_OK;
 }
 
+// The spherical-voxel workspace (forward chunk sums, adjoint slice sums),
+// grown to `need` bytes; earlier calls may still use the old buffer, so a
+// growth waits for the device first.  The device is current.
+static int ensure_sph_workspace(oat_plan *plan, size_t need, const char *who)
+{
+    if (need <= plan->sph_part_bytes) return OAT_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && plan->d_sph_part) e = hipFree(plan->d_sph_part);
+    plan->d_sph_part = nullptr;
+    plan->sph_part_bytes = 0;
+    if (e == hipSuccess) e = hipMalloc((void **)&plan->d_sph_part, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(OAT_ERR_NOMEM, std::string(who) + ": hipMalloc");
+    }
+    plan->sph_part_bytes = need;
+    return OAT_OK;
+}
+
 int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *u, int n_f,
                     double f_min, double df, uint32_t flags, void *stream)
 {
@@ -762,24 +781,12 @@ int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *
     if (rc) return rc;
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
-    const size_t need = sph_workspace_bytes(plan->P, n_f);
-    hipError_t e = hipSuccess;
-    if (need > plan->sph_part_bytes) {
-        // grows once per larger n_f; earlier calls may still use the old buffer
-        e = hipDeviceSynchronize();
-        if (e == hipSuccess && plan->d_sph_part) e = hipFree(plan->d_sph_part);
-        plan->d_sph_part = nullptr;
-        plan->sph_part_bytes = 0;
-        if (e == hipSuccess) e = hipMalloc((void **)&plan->d_sph_part, need);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            (void)hipSetDevice(prev);
-            return fail(OAT_ERR_NOMEM, "oat_sph_project: hipMalloc");
-        }
-        plan->sph_part_bytes = need;
+    if ((rc = ensure_sph_workspace(plan, sph_workspace_bytes(plan->P, n_f), "oat_sph_project"))) {
+        (void)hipSetDevice(prev);
+        return rc;
     }
-    e = launch_sph_project(plan->P, img, (int)img_dtype, (float2 *)u, n_f, f_min, df,
-                           plan->d_sph_part, (hipStream_t)stream);
+    hipError_t e = launch_sph_project(plan->P, img, (int)img_dtype, (float2 *)u, n_f, f_min, df,
+                                      plan->d_sph_part, (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_sph_project: launch");
     return OAT_OK;
@@ -792,8 +799,14 @@ int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, do
     if (rc) return rc;
     int prev;
     if ((rc = with_device(plan, prev))) return rc;
+    if ((rc = ensure_sph_workspace(plan, sph_adj_workspace_bytes(plan->P),
+                                   "oat_sph_backproject"))) {
+        (void)hipSetDevice(prev);
+        return rc;
+    }
     hipError_t e = launch_sph_backproject(plan->P, (const float2 *)u, n_f, f_min, df, img,
-                                          (int)img_dtype, (hipStream_t)stream);
+                                          (int)img_dtype, (double *)plan->d_sph_part,
+                                          (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_sph_backproject: launch");
     return OAT_OK;

@@ -186,7 +186,7 @@ sph_fwd_reduce_kernel(Problem P, const double2 *__restrict__ part, int nchunk, i
 template <int IMG_DT>
 __global__ void __launch_bounds__(SPH_THREADS)
 sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, double df,
-               void *__restrict__ img)
+               void *__restrict__ img, double *__restrict__ slice_sum, int q_per_slice)
 {
     extern __shared__ float2 sv[];   // [qt][n_fp]: rows padded with zeros to whole blocks
     constexpr int NV = SPH_NV;
@@ -205,8 +205,10 @@ sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, d
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    for (int q0 = 0; q0 < P.nq; q0 += qt) {
-        const int nq = min(qt, P.nq - q0);
+    // Transducers of this slice (blockIdx.y); with one slice, all of them.
+    const int qb = (int)blockIdx.y * q_per_slice, qe = min(P.nq, qb + q_per_slice);
+    for (int q0 = qb; q0 < qe; q0 += qt) {
+        const int nq = min(qt, qe - q0);
         __syncthreads();
         for (int k = threadIdx.x; k < nq * n_fp; k += blockDim.x) {
             const int jq = k / n_fp, l = k % n_fp;
@@ -266,8 +268,25 @@ sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, d
         }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-        if (nb + v < N) store_val(img, (size_t)(nb + v), IMG_DT, (float)acc[v]);
+    for (int v = 0; v < NV; ++v) {
+        if (nb + v >= N) continue;
+        if (slice_sum)
+            slice_sum[(size_t)blockIdx.y * N + nb + v] = acc[v];
+        else
+            store_val(img, (size_t)(nb + v), IMG_DT, (float)acc[v]);
+    }
+}
+
+// img[n] = sum over the slices, in slice order, of slice_sum[slice][n].
+__global__ void __launch_bounds__(SPH_THREADS)
+sph_adj_sum_kernel(const double *__restrict__ slice_sum, int slices, long long N,
+                   void *__restrict__ img, int img_dt)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double acc = 0.0;
+    for (int sl = 0; sl < slices; ++sl) acc += slice_sum[(size_t)sl * N + n];
+    store_val(img, (size_t)n, img_dt, (float)acc);
 }
 
 }  // namespace
@@ -298,21 +317,50 @@ hipError_t launch_sph_project(const Problem &P, const void *img, int img_dt, flo
     return hipGetLastError();
 }
 
+// Transducer slices of the adjoint: a grid of fewer than 1024 workgroups
+// (a small image) takes the transducers in up to 4 slices along grid y, so
+// the device holds more waves; their FP64 partial images are then added in
+// slice order.
+int sph_adj_slices(const Problem &P)
+{
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    const long long blocks = ((N + SPH_NV - 1) / SPH_NV + SPH_THREADS - 1) / SPH_THREADS;
+    if (blocks >= 1024) return 1;
+    long long sl = (1024 + blocks - 1) / blocks;
+    if (sl > 4) sl = 4;
+    if (sl > P.nq) sl = P.nq;
+    return (int)sl;
+}
+
+size_t sph_adj_workspace_bytes(const Problem &P)
+{
+    const int S = sph_adj_slices(P);
+    return S > 1 ? sizeof(double) * (size_t)S * P.nx * P.ny * P.nz : 0;
+}
+
 hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, double f_min,
-                                  double df, void *img, int img_dt, hipStream_t s)
+                                  double df, void *img, int img_dt, double *work, hipStream_t s)
 {
     const long long N = (long long)P.nx * P.ny * P.nz;
     const int n_fp = (n_f + SPH_ANCHOR - 1) / SPH_ANCHOR * SPH_ANCHOR;
     const int qt = (SPH_VQ / n_fp) > 1 ? SPH_VQ / n_fp : 1;
     const size_t shm = sizeof(float2) * (size_t)qt * n_fp;
     const long long threads = (N + SPH_NV - 1) / SPH_NV;
-    dim3 grid((unsigned)((threads + SPH_THREADS - 1) / SPH_THREADS));
+    const int S = sph_adj_slices(P);
+    if (S > 1 && !work) return hipErrorInvalidValue;
+    const int qps = (P.nq + S - 1) / S;
+    double *slice_sum = S > 1 ? work : nullptr;
+    dim3 grid((unsigned)((threads + SPH_THREADS - 1) / SPH_THREADS), (unsigned)S);
     if (img_dt == 0)
         hipLaunchKernelGGL(sph_adj_kernel<0>, grid, dim3(SPH_THREADS), shm, s, P, u, n_f, f_min, df,
-                           img);
+                           img, slice_sum, qps);
     else
         hipLaunchKernelGGL(sph_adj_kernel<1>, grid, dim3(SPH_THREADS), shm, s, P, u, n_f, f_min, df,
-                           img);
+                           img, slice_sum, qps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    hipLaunchKernelGGL(sph_adj_sum_kernel, dim3((unsigned)((N + SPH_THREADS - 1) / SPH_THREADS)),
+                       dim3(SPH_THREADS), 0, s, slice_sum, S, N, img, img_dt);
     return hipGetLastError();
 }
 
