@@ -207,3 +207,36 @@ def test_sph_at_64cube_2048_rows_and_voxels():
              ref.sph_backproject(gd, y.astype(np.complex128), n_f, df, df, voxels=vox))
     _say(f"[gpu-full] H_sph 64^3/2048/256 rows rel {e:.3e}; H_sph^T voxels rel {eT:.3e}")
     assert e < 1e-5 and eT < 1e-5
+
+
+@gpu
+def test_sph_adjoint_without_slices():
+    """An image of 128 x 64 x 64 = 2^19 voxels fills 1024 workgroups, so the
+    adjoint takes all transducers in one pass and stores directly (smaller
+    images split them into slices of FP64 partial images): sampled voxels
+    against the oracle, and the adjoint identity on the whole image."""
+    from paper_1304_2017_amd.oat import Plan
+    nx, ny, nz, dx = 128, 64, 64, 0.4
+    geom = synth.Geometry(nx, ny, nz, dx, synth.centred_origin(nx, dx), synth.centred_origin(ny, dx),
+                          synth.centred_origin(nz, dx), synth.fibonacci_sphere(48, 40.0), 256, 0.05,
+                          0.0, 1.5, 1.0)
+    assert geom.n_vox == 1 << 19
+    plan = Plan(geom, 0, arc_table=False, segment_table=False)
+    n_f, f0, df = 24, 0.2, 0.2
+    gd = geom.as_dict()
+    rng = np.random.default_rng(8)
+    y = (rng.normal(size=(geom.n_det, n_f)) + 1j * rng.normal(size=(geom.n_det, n_f))).astype(np.complex64)
+    b = plan.sph_backproject(torch.from_numpy(y).cuda(), f0, df)
+    x = torch.from_numpy(rng.uniform(0, 1, size=geom.shape).astype(np.float32)).cuda()
+    u = plan.sph_project(x, n_f, f0, df)
+    torch.cuda.synchronize()
+    vox = rng.choice(geom.n_vox, 60, replace=False)
+    eT = rel(b.double().cpu().numpy().ravel()[vox],
+             ref.sph_backproject(gd, y.astype(np.complex128), n_f, f0, df, voxels=vox))
+    lhs = float(np.real(np.vdot(y.astype(np.complex128), u.cpu().numpy().astype(np.complex128))))
+    rhs = float(np.dot(x.double().cpu().numpy().ravel(), b.double().cpu().numpy().ravel()))
+    scale = float(np.linalg.norm(u.cpu().numpy()) * np.linalg.norm(y))
+    _say(f"[gpu] H_sph^T 128x64x64 (one slice) voxels rel {eT:.3e}; "
+         f"adjoint {abs(lhs - rhs) / scale:.3e}")
+    assert eT < 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * scale
