@@ -114,12 +114,13 @@ __global__ void __launch_bounds__(256) diff_adj_kernel(Problem P, const void *__
 // G^T output.  A brick's box holds the nodes of its cells, one node below
 // its first owned node through its last owned node, so node c (per axis)
 // receives the box of its owner brick c / BRICK and, when c is the last node
-// of that brick, the box of the next brick, where c is box node 0.  The at
-// most 8 contributions are added in a fixed order: the result is
+// of that brick, the box of the next brick, where c is box node 0.  Each box
+// comes in `slices` parts (one per slice of the transducer windows).  The at
+// most 8 x slices contributions are added in a fixed order: the result is
 // deterministic.
 template <int IMG_DT>
 __global__ void __launch_bounds__(256)
-adj_gather_kernel(Problem P, const double *__restrict__ acc, void *__restrict__ img)
+adj_gather_kernel(Problem P, const double *__restrict__ acc, int slices, void *__restrict__ img)
 {
     const int x = blockIdx.x * 64 + threadIdx.x % 64;
     const int y = blockIdx.y * 4 + threadIdx.x / 64;
@@ -137,12 +138,14 @@ adj_gather_kernel(Problem P, const double *__restrict__ acc, void *__restrict__ 
         off[a][1] = 0;
         cnt[a] = (r == BRICK - 1 && b0 + 1 < nb[a]) ? 2 : 1;
     }
+    const size_t slice_len = (size_t)P.nbx * P.nby * P.nbz * BOX3;
     double sum = 0.0;
     for (int iz = 0; iz < cnt[2]; ++iz)
         for (int iy = 0; iy < cnt[1]; ++iy)
             for (int ix = 0; ix < cnt[0]; ++ix) {
                 const size_t b = ((size_t)bi[2][iz] * P.nby + bi[1][iy]) * P.nbx + bi[0][ix];
-                sum += acc[b * BOX3 + (off[2][iz] * BOX + off[1][iy]) * BOX + off[0][ix]];
+                const size_t i = b * BOX3 + (off[2][iz] * BOX + off[1][iy]) * BOX + off[0][ix];
+                for (int sl = 0; sl < slices; ++sl) sum += acc[sl * slice_len + i];
             }
     store_val(img, ((size_t)z * P.ny + y) * P.nx + x, IMG_DT, (float)sum);
 }
@@ -291,10 +294,11 @@ hipError_t launch_adj_gather(const Problem &P, const double *acc, void *img, int
                              hipStream_t s)
 {
     dim3 grid((P.nx + 63) / 64, (P.ny + 3) / 4, P.nz), block(256);
+    const int sl = adj_slices(P.nbx * P.nby * P.nbz, P.nq);
     if (img_dtype == 0)
-        hipLaunchKernelGGL(adj_gather_kernel<0>, grid, block, 0, s, P, acc, img);
+        hipLaunchKernelGGL(adj_gather_kernel<0>, grid, block, 0, s, P, acc, sl, img);
     else
-        hipLaunchKernelGGL(adj_gather_kernel<1>, grid, block, 0, s, P, acc, img);
+        hipLaunchKernelGGL(adj_gather_kernel<1>, grid, block, 0, s, P, acc, sl, img);
     return hipGetLastError();
 }
 

@@ -26,6 +26,34 @@ constexpr int ADJ_WINDOW = 48;
 constexpr int SPH_CHUNKS = 64;
 __host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }
 
+// Slices of a brick's work (G: transducers, G^T: transducer windows) as
+// separate workgroups.  G and G^T run one workgroup per CU, so the grid runs
+// in rounds of 256 workgroups and a partly empty last round leaves CUs idle:
+// take the count (1..4, at least min_items items per slice) whose grid fills
+// its last round best, a smaller count winning ties within 0.5%, and return
+// the number of non-empty slices of ceil(items / count) items.
+inline int brick_slices(int nbricks, int items, int min_items)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int sl = 1; sl <= 4; ++sl) {
+        if (sl > 1 && items / sl < min_items) break;
+        const long long g = (long long)nbricks * sl;
+        const double eff = (double)g / (double)(((g + 255) / 256) * 256);
+        if (eff > best_eff + 0.005) {
+            best = sl;
+            best_eff = eff;
+        }
+    }
+    const int per = (items + best - 1) / best;
+    return (items + per - 1) / per;
+}
+// G: transducers per slice >= 64.  G^T: windows per slice >= 4; each slice
+// keeps its own FP64 brick sums ([slice][brick][BOX3]; the same slicing for
+// every table mode).
+inline int fwd_slices(int nbricks, int nq) { return brick_slices(nbricks, nq, 64); }
+inline int adj_slices(int nbricks, int nq) { return brick_slices(nbricks, adj_windows(nq), 4); }
+
 // Per-transducer record (grid units: positions are (r - r_0)/dx).
 struct alignas(16) DetRec {
     double uq[3];      // transducer position

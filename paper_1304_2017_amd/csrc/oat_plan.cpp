@@ -499,7 +499,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     size_t part_b = sizeof(float) * (size_t)nbricks * Q * P.window;
     size_t klo_b = sizeof(int) * (size_t)nbricks * Q;
     size_t gp_b = sizeof(float) * (size_t)Q * K;
-    size_t acc_b = sizeof(double) * (size_t)nbricks * BOX3;        // G^T brick node sums
+    // G^T brick node sums, one set per slice of the transducer windows
+    size_t acc_b = sizeof(double) * (size_t)adj_slices(nbricks, Q) * nbricks * BOX3;
     size_t rowmax_b = sizeof(float) * (size_t)Q;
     size_t adjr_b = sizeof(float) * (size_t)nbricks * adj_windows(Q);
     const std::vector<double> fbp_thr = fbp_floor_thresholds(g->c0, g->t0, g->dt, K);

@@ -598,7 +598,7 @@ constexpr int FWD_WAVES = 16;
 template <int IMG_DT, int TM>
 __global__ void __launch_bounds__(FWD_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(4, 4)))
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
-               int *__restrict__ klo_out)
+               int *__restrict__ klo_out, int q_per_slice)
 {
     __shared__ float box[BOX_WORDS];
     __shared__ WaveLds wl[FWD_WAVES];
@@ -627,7 +627,9 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     const int lane = lane_id();
     WaveLds &W = wl[wave];
     double *gw = gwin[wave];
-    for (int q = wave; q < P.nq; q += FWD_WAVES) {
+    // Transducers of this workgroup's slice (blockIdx.y) of the brick's.
+    const int qe = min(P.nq, ((int)blockIdx.y + 1) * q_per_slice);
+    for (int q = (int)blockIdx.y * q_per_slice + wave; q < qe; q += FWD_WAVES) {
         for (int j = lane; j < P.window; j += WAVE) gw[j] = 0.0;
         wave_sync();
         int klo = 0;
@@ -750,7 +752,7 @@ __device__ __forceinline__ void field_scale(double bound, float &g1, float &g2, 
 template <int TM, bool CALIB, int NW>
 __global__ void __launch_bounds__(NW *WAVE) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc,
-               float *__restrict__ rcal)
+               float *__restrict__ rcal, int win_per_slice)
 {
     // The segment-table walk needs only the point level's LDS, which leaves
     // room for 16 waves beside the box.
@@ -769,7 +771,10 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
     const int wave = threadIdx.x / WAVE, lane = lane_id();
     WL &W = wl[wave];
     const int nwin = adj_windows(P.nq);
-    for (int win = 0; win < nwin; ++win) {
+    // Windows of this workgroup's slice (blockIdx.y); each slice has its own
+    // FP64 brick sums.
+    const int w0 = (int)blockIdx.y * win_per_slice, w1 = min(nwin, w0 + win_per_slice);
+    for (int win = w0; win < w1; ++win) {
         const int q0 = win * ADJ_WINDOW;
         float g1, g2;
         double unscale;
@@ -859,7 +864,8 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                 rcal[(size_t)b * nwin + win] = (float)r * (1.f + 1.f / 1024.f);
             }
         } else {
-            double *dst = acc + (size_t)b * BOX3;
+            double *dst =
+                acc + ((size_t)blockIdx.y * (P.nbx * P.nby * P.nbz) + b) * BOX3;
             for (int t = threadIdx.x; t < BOX3; t += blockDim.x) {
                 const int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
                 const unsigned long long *row = box + z * BOX_SZ + y * BOX_SY;
@@ -871,7 +877,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     v += (wd - l) >> 32;
                 }
                 const double a = (double)v * unscale;
-                dst[t] = win == 0 ? a : dst[t] + a;
+                dst[t] = win == w0 ? a : dst[t] + a;
             }
         }
         __syncthreads();
@@ -909,11 +915,12 @@ template <int TM>
 static void fwd_launch(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
                        hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), block(FWD_WAVES * WAVE);
+    const int sl = fwd_slices(P.nbx * P.nby * P.nbz, P.nq), qps = (P.nq + sl - 1) / sl;
+    dim3 grid(P.nbx * P.nby * P.nbz, sl), block(FWD_WAVES * WAVE);
     if (img_dtype == 0)
-        hipLaunchKernelGGL((srt_fwd_kernel<0, TM>), grid, block, 0, s, P, img, part, klo);
+        hipLaunchKernelGGL((srt_fwd_kernel<0, TM>), grid, block, 0, s, P, img, part, klo, qps);
     else
-        hipLaunchKernelGGL((srt_fwd_kernel<1, TM>), grid, block, 0, s, P, img, part, klo);
+        hipLaunchKernelGGL((srt_fwd_kernel<1, TM>), grid, block, 0, s, P, img, part, klo, qps);
 }
 
 static int table_mode(const Problem &P)
@@ -939,19 +946,25 @@ hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, floa
 template <bool CALIB>
 static void adj_launch(const Problem &P, const float *gp, double *acc, float *r, hipStream_t s)
 {
-    dim3 grid(P.nbx * P.nby * P.nbz), b12(12 * WAVE), b16(16 * WAVE);
+    const int nb = P.nbx * P.nby * P.nbz, nwin = adj_windows(P.nq);
+    const int sl = adj_slices(nb, P.nq), wps = (nwin + sl - 1) / sl;
+    dim3 grid(nb, sl), b12(12 * WAVE), b16(16 * WAVE);
     switch (table_mode(P)) {
     case TM_SEG:
         if (CALIB)
-            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, true, 12>), grid, b12, 0, s, P, gp, acc, r);
+            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, true, 12>), grid, b12, 0, s, P, gp, acc, r,
+                               wps);
         else
-            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, false, 16>), grid, b16, 0, s, P, gp, acc, r);
+            hipLaunchKernelGGL((srt_adj_kernel<TM_SEG, false, 16>), grid, b16, 0, s, P, gp, acc, r,
+                               wps);
         break;
     case TM_ARC:
-        hipLaunchKernelGGL((srt_adj_kernel<TM_ARC, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r);
+        hipLaunchKernelGGL((srt_adj_kernel<TM_ARC, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r,
+                           wps);
         break;
     default:
-        hipLaunchKernelGGL((srt_adj_kernel<TM_BOUNDS, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r);
+        hipLaunchKernelGGL((srt_adj_kernel<TM_BOUNDS, CALIB, 12>), grid, b12, 0, s, P, gp, acc, r,
+                           wps);
         break;
     }
 }

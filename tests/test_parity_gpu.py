@@ -347,3 +347,50 @@ def test_backproject_single_transducer(q, small1_plan):
             ref.backproject(geom.as_dict(), y[q:q + 1], rows=np.array([q], dtype=np.int32)))
     _say(f"[gpu] H^T data on transducer {q}: rel {e:.3e}")
     assert e < 1e-5
+
+
+def _brick_slices(nbricks, items, min_items):
+    """The library's slice count for a brick's work (G: transducers, G^T:
+    windows of 48 transducers), restated to check that a case uses slices."""
+    best, best_eff = 1, 0.0
+    for sl in range(1, 5):
+        if sl > 1 and items // sl < min_items:
+            break
+        g = nbricks * sl
+        eff = g / (((g + 255) // 256) * 256)
+        if eff > best_eff + 0.005:
+            best, best_eff = sl, eff
+    per = (items + best - 1) // best
+    return (items + per - 1) // per
+
+
+@pytest.mark.parametrize("table", list(TABLES))
+def test_transducer_slices(table, Plan):
+    """8 bricks and 384 transducers: G takes each brick's transducers in 4
+    workgroups and G^T its 8 windows in 2, each with its own FP64 brick sums
+    added in slice order.  Parity with the oracle, and G^T bit-identical
+    across the table paths."""
+    geom0 = synth.config_small(1)[0]
+    det = synth.fibonacci_sphere(384, 25.0)
+    geom = synth.Geometry(geom0.nx, geom0.ny, geom0.nz, geom0.dx, geom0.x0, geom0.y0, geom0.z0,
+                          det, geom0.n_t, geom0.dt, geom0.t0, geom0.c0, 1.0)
+    assert _brick_slices(8, 384, 64) == 4 and _brick_slices(8, 8, 4) == 2
+    _say(f"[gpu] transducer slices, tables {table}")
+    gd = geom.as_dict()
+    rng = np.random.default_rng(21)
+    img = rng.uniform(0, 1, size=geom.shape).astype(np.float32).astype(np.float64)
+    y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
+    plan = Plan(geom, 0, **TABLES[table])
+    g = _np(plan.project(_t(img), srt_only=True))
+    e_g = rel(g, ref.srt(gd, img))
+    a = _np(plan.backproject(_t(y), srt_only=True))
+    e_a = rel(a, ref.srt_adj(gd, y))
+    lhs = float(np.dot(g.ravel(), y.ravel()))
+    rhs = float(np.dot(img.ravel(), a.ravel()))
+    scale = float(np.linalg.norm(g) * np.linalg.norm(y))
+    _say(f"  G rel {e_g:.3e}  G^T rel {e_a:.3e}  adjoint (/ norms) {abs(lhs - rhs) / scale:.3e}")
+    assert e_g < 1e-6 and e_a < 1e-5
+    assert abs(lhs - rhs) <= 1e-6 * scale
+    if table == "segments":
+        a_b = _np(Plan(geom, 0, **TABLES["bounds"]).backproject(_t(y), srt_only=True))
+        assert np.array_equal(a, a_b)
