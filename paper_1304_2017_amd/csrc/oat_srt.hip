@@ -603,9 +603,13 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     __shared__ float box[BOX_WORDS];
     __shared__ WaveLds wl[FWD_WAVES];
     __shared__ double gwin[FWD_WAVES][WMAX];
+    __shared__ int q_next;
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
+    // Transducers of this workgroup's slice (blockIdx.y) of the brick's.
+    const int qb = (int)blockIdx.y * q_per_slice, qe = min(P.nq, qb + q_per_slice);
+    if (threadIdx.x == 0) q_next = qb;
 
     // Stage nodes lo .. lo+BOX-1 (zero outside the grid).
     for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
@@ -627,9 +631,13 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
     const int lane = lane_id();
     WaveLds &W = wl[wave];
     double *gw = gwin[wave];
-    // Transducers of this workgroup's slice (blockIdx.y) of the brick's.
-    const int qe = min(P.nq, ((int)blockIdx.y + 1) * q_per_slice);
-    for (int q = (int)blockIdx.y * q_per_slice + wave; q < qe; q += FWD_WAVES) {
+    // Each wave takes the slice's next transducer when it finishes one (an
+    // LDS counter), so the waves end together whatever the units cost.
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(&q_next, 1);
+        q = __builtin_amdgcn_readfirstlane(q);
+        if (q >= qe) break;
         for (int j = lane; j < P.window; j += WAVE) gw[j] = 0.0;
         wave_sync();
         int klo = 0;
@@ -687,8 +695,8 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // range the word decodes exactly: lo = low 32 bits (signed), hi = (word - lo)
 // >> 32 (arithmetic).
 //
-// The transducers are taken in windows of ADJ_WINDOW = 48 (with NW waves,
-// wave w takes transducers window * 48 + w + NW r, r < 48 / NW).  A window's
+// The transducers are taken in windows of ADJ_WINDOW = 48 (the NW waves
+// take a window's transducers one at a time from an LDS counter).  A window's
 // weights are multiplied by S = 0.99 * 2^31 / (R G) and rounded to the nearest
 // integer (v_cvt_rpi_i32_f32), where
 //   R(brick, window) = max over box nodes of sum psi w over the window's
@@ -756,24 +764,24 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
 {
     // The segment-table walk needs only the point level's LDS, which leaves
     // room for 16 waves beside the box.
-    static_assert(ADJ_WINDOW % NW == 0, "window must be whole rounds");
     static_assert(NW <= 12 || TM == TM_SEG, "16 waves fit the LDS only on the segment path");
-    constexpr int ROUNDS = ADJ_WINDOW / NW;
     using WL = typename std::conditional<TM == TM_SEG, SegLds, WaveLds>::type;
     __shared__ unsigned long long box[BOX_WORDS];
     __shared__ WL wl[NW];
     __shared__ unsigned long long wred[NW];
+    __shared__ int q_next;
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
-    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
-    __syncthreads();
-    const int wave = threadIdx.x / WAVE, lane = lane_id();
-    WL &W = wl[wave];
     const int nwin = adj_windows(P.nq);
     // Windows of this workgroup's slice (blockIdx.y); each slice has its own
     // FP64 brick sums.
     const int w0 = (int)blockIdx.y * win_per_slice, w1 = min(nwin, w0 + win_per_slice);
+    for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
+    if (threadIdx.x == 0) q_next = w0 * ADJ_WINDOW;
+    __syncthreads();
+    const int wave = threadIdx.x / WAVE, lane = lane_id();
+    WL &W = wl[wave];
     for (int win = w0; win < w1; ++win) {
         const int q0 = win * ADJ_WINDOW;
         float g1, g2;
@@ -787,9 +795,16 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
             for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
             field_scale((double)P.adj_r[(size_t)b * nwin + win] * (double)m, g1, g2, unscale);
         }
-        for (int r = 0; r < ROUNDS; ++r) {
-            const int q = q0 + r * NW + wave;
-            if (q >= P.nq) break;
+        // Each wave takes the window's next transducer when it finishes one
+        // (an LDS counter): the waves reach the flush together whatever the
+        // units cost.  The LDS sums are exact integers, so the order of the
+        // units does not change them.
+        const int qw = min(P.nq, q0 + ADJ_WINDOW);
+        for (;;) {
+            int q = 0;
+            if (lane == 0) q = atomicAdd(&q_next, 1);
+            q = __builtin_amdgcn_readfirstlane(q);
+            if (q >= qw) break;
             int klo = 0;
             if (CALIB) {
                 auto scatter1 = [&](const Pt &t, float wv) {
@@ -882,6 +897,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
         }
         __syncthreads();
         for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
+        if (threadIdx.x == 0) q_next = (win + 1) * ADJ_WINDOW;
         __syncthreads();
     }
 }
