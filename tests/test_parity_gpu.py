@@ -330,15 +330,19 @@ def test_backproject_with_wide_dynamic_range(Plan):
 
 @pytest.fixture(scope="module")
 def small1_plan(Plan):
-    geom = synth.config_small(1)[0]
+    """config_small's grid with 200 transducers: three windows of 96."""
+    g = synth.config_small(1)[0]
+    geom = synth.Geometry(g.nx, g.ny, g.nz, g.dx, g.x0, g.y0, g.z0,
+                          synth.fibonacci_sphere(200, 25.0), g.n_t, g.dt, g.t0, g.c0, g.gamma)
     return geom, Plan(geom, 0)
 
 
-@pytest.mark.parametrize("q", [0, 11, 12, 47, 48, 63])
+@pytest.mark.parametrize("q", [0, 15, 16, 95, 96, 191, 192, 199])
 def test_backproject_single_transducer(q, small1_plan):
     """Data on one transducer only, at every position class of G^T's
-    transducer windows (first and last of a wave's rounds, last of a window,
-    first of the next): each scale must see that transducer's data."""
+    transducer windows of 96 (first transducer, the ends of the first 16
+    that the waves take, last of a window, first of the next, the partial
+    last window): each window's scale must see that transducer's data."""
     geom, plan = small1_plan
     rng = np.random.default_rng(100 + q)
     y = np.zeros((geom.n_det, geom.n_t))
@@ -351,7 +355,7 @@ def test_backproject_single_transducer(q, small1_plan):
 
 def _brick_slices(nbricks, items, min_items):
     """The library's slice count for a brick's work (G: transducers, G^T:
-    windows of 48 transducers), restated to check that a case uses slices."""
+    windows of 96 transducers), restated to check that a case uses slices."""
     best, best_eff = 1, 0.0
     for sl in range(1, 5):
         if sl > 1 and items // sl < min_items:
@@ -366,15 +370,15 @@ def _brick_slices(nbricks, items, min_items):
 
 @pytest.mark.parametrize("table", list(TABLES))
 def test_transducer_slices(table, Plan):
-    """8 bricks and 384 transducers: G takes each brick's transducers in 4
-    workgroups and G^T its 8 windows in 2, each with its own FP64 brick sums
-    added in slice order.  Parity with the oracle, and G^T bit-identical
-    across the table paths."""
+    """8 bricks and 768 transducers: G takes each brick's transducers in 4
+    workgroups and G^T its 8 windows (of 96) in 2, each with its own FP64
+    brick sums added in slice order.  Parity with the oracle, and G^T
+    bit-identical across the table paths."""
     geom0 = synth.config_small(1)[0]
-    det = synth.fibonacci_sphere(384, 25.0)
+    det = synth.fibonacci_sphere(768, 25.0)
     geom = synth.Geometry(geom0.nx, geom0.ny, geom0.nz, geom0.dx, geom0.x0, geom0.y0, geom0.z0,
                           det, geom0.n_t, geom0.dt, geom0.t0, geom0.c0, 1.0)
-    assert _brick_slices(8, 384, 64) == 4 and _brick_slices(8, 8, 4) == 2
+    assert _brick_slices(8, 768, 64) == 4 and _brick_slices(8, 768 // 96, 4) == 2
     _say(f"[gpu] transducer slices, tables {table}")
     gd = geom.as_dict()
     rng = np.random.default_rng(21)
