@@ -121,3 +121,18 @@ def test_host_fbp_floor_thresholds(tmp_path):
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.startswith("OK"), r.stdout
     assert int(r.stdout.split()[1]) > 1000000
+
+
+def test_flag_and_status_constants_match_the_header():
+    """The binding's flag, dtype and status constants equal the header's."""
+    import re
+    text = open(os.path.join(ROOT, "include", "oat.h")).read()
+    defines = {m.group(1): int(m.group(2)) for m in
+               re.finditer(r"#define\s+(OAT_FLAG_\w+)\s+(\d+)u", text)}
+    assert defines == {"OAT_FLAG_SRT_ONLY": oat.OAT_FLAG_SRT_ONLY,
+                       "OAT_FLAG_DETERMINISTIC": oat.OAT_FLAG_DETERMINISTIC}
+    enums = {m.group(1): int(m.group(2)) for m in
+             re.finditer(r"\b(OAT_(?:OK|ERR_\w+|F32|BF16))\s*=\s*(-?\d+)", text)}
+    for name, value in enums.items():
+        assert getattr(oat, name) == value, name
+    assert {"OAT_OK", "OAT_ERR_ARG", "OAT_ERR_GEOMETRY", "OAT_F32", "OAT_BF16"} <= set(enums)
