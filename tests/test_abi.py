@@ -125,7 +125,6 @@ def test_host_fbp_floor_thresholds(tmp_path):
 
 def test_flag_and_status_constants_match_the_header():
     """The binding's flag, dtype and status constants equal the header's."""
-    import re
     text = open(os.path.join(ROOT, "include", "oat.h")).read()
     defines = {m.group(1): int(m.group(2)) for m in
                re.finditer(r"#define\s+(OAT_FLAG_\w+)\s+(\d+)u", text)}
