@@ -770,17 +770,45 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
     __shared__ WL wl[NW];
     __shared__ unsigned long long wred[NW];
     __shared__ int q_next;
+    __shared__ int qperm[ADJ_WINDOW];
+    __shared__ long long qcost[ADJ_WINDOW];
     const int b = blockIdx.x;
     int lo[3], hi[3], n0[3], n1[3];
     brick_box(P, b, lo, hi, n0, n1);
     const int nwin = adj_windows(P.nq);
+    const int wave = threadIdx.x / WAVE, lane = lane_id();
+    // Order in which the waves take a window's transducers (wave 0 writes
+    // it): with the segment table by decreasing segment count, so the
+    // longest units start first and the waves reach the window's barrier
+    // close together; otherwise in index order.
+    auto order_window = [&](int wn) {
+        const int qa = wn * ADJ_WINDOW, cnt = min(ADJ_WINDOW, P.nq - qa);
+        if constexpr (TM == TM_SEG && !CALIB) {
+            for (int i = lane; i < cnt; i += WAVE) {
+                const size_t u = (size_t)b * P.nq + qa + i;
+                qcost[i] = P.seg_off[u + 1] - P.seg_off[u];
+            }
+            wave_sync();
+            for (int i = lane; i < cnt; i += WAVE) {
+                const long long c = qcost[i];
+                int rank = 0;
+                for (int j = 0; j < cnt; ++j) {
+                    const long long cj = qcost[j];
+                    rank += (cj > c || (cj == c && j < i)) ? 1 : 0;
+                }
+                qperm[rank] = qa + i;
+            }
+        } else {
+            for (int i = lane; i < cnt; i += WAVE) qperm[i] = qa + i;
+        }
+    };
     // Windows of this workgroup's slice (blockIdx.y); each slice has its own
     // FP64 brick sums.
     const int w0 = (int)blockIdx.y * win_per_slice, w1 = min(nwin, w0 + win_per_slice);
     for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
-    if (threadIdx.x == 0) q_next = w0 * ADJ_WINDOW;
+    if (threadIdx.x == 0) q_next = 0;
+    if (wave == 0) order_window(w0);
     __syncthreads();
-    const int wave = threadIdx.x / WAVE, lane = lane_id();
     WL &W = wl[wave];
     for (int win = w0; win < w1; ++win) {
         const int q0 = win * ADJ_WINDOW;
@@ -795,16 +823,17 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
             for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
             field_scale((double)P.adj_r[(size_t)b * nwin + win] * (double)m, g1, g2, unscale);
         }
-        // Each wave takes the window's next transducer when it finishes one
-        // (an LDS counter): the waves reach the flush together whatever the
-        // units cost.  The LDS sums are exact integers, so the order of the
-        // units does not change them.
-        const int qw = min(P.nq, q0 + ADJ_WINDOW);
+        // Each wave takes the window's next transducer (in qperm order) when
+        // it finishes one (an LDS counter): the waves reach the flush
+        // together whatever the units cost.  The LDS sums are exact
+        // integers, so the order of the units does not change them.
+        const int cntw = min(ADJ_WINDOW, P.nq - q0);
         for (;;) {
-            int q = 0;
-            if (lane == 0) q = atomicAdd(&q_next, 1);
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (q >= qw) break;
+            int i = 0;
+            if (lane == 0) i = atomicAdd(&q_next, 1);
+            i = __builtin_amdgcn_readfirstlane(i);
+            if (i >= cntw) break;
+            const int q = qperm[i];
             int klo = 0;
             if (CALIB) {
                 auto scatter1 = [&](const Pt &t, float wv) {
@@ -897,7 +926,8 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
         }
         __syncthreads();
         for (int t = threadIdx.x; t < BOX_WORDS; t += blockDim.x) box[t] = 0ull;
-        if (threadIdx.x == 0) q_next = (win + 1) * ADJ_WINDOW;
+        if (threadIdx.x == 0) q_next = 0;
+        if (wave == 0 && win + 1 < w1) order_window(win + 1);
         __syncthreads();
     }
 }
