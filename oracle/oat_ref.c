@@ -370,27 +370,27 @@ void ref_fbp(const ref_geom *G, const double *p, double *img)
     ref_fbp_voxels(G, p, NULL, 0, img);
 }
 
-/* Number of quadrature points visited by G for the listed rows (bands that
- * can reach the support), for work accounting. */
-typedef struct { long n; } count_ctx;
-static void count_point(void *vctx, double x, double y, double z, double w)
+/* The quadrature points of one shell (q, k), in visiting order: up to cap
+ * rows of (x, y, z, w) are written to out and the number of points visited is
+ * returned (0 when the shell misses the support).  This is the enumeration G
+ * and G^T use, exposed so that it can be checked on its own against the
+ * Appendix's band construction. */
+typedef struct { double *out; long cap, n; } list_ctx;
+static void list_point(void *vctx, double x, double y, double z, double w)
 {
-    (void)x; (void)y; (void)z; (void)w;
-    ((count_ctx *)vctx)->n += 1;
+    list_ctx *c = (list_ctx *)vctx;
+    if (c->n < c->cap) {
+        double *o = c->out + 4 * c->n;
+        o[0] = x; o[1] = y; o[2] = z; o[3] = w;
+    }
+    c->n += 1;
 }
 
-long ref_count_points(const ref_geom *G, const int *qsel, int nsel)
+long ref_shell_points(const ref_geom *G, int q, int k, double *out, long cap)
 {
-    double R = ref_support_radius(G);
-    long total = 0;
-    long rows = (long)nsel * G->nt;
-#pragma omp parallel for reduction(+ : total) schedule(dynamic, 4)
-    for (long idx = 0; idx < rows; ++idx) {
-        count_ctx c = {0};
-        shell_points(G, qsel[idx / G->nt], (int)(idx % G->nt), R, count_point, &c);
-        total += c.n;
-    }
-    return total;
+    list_ctx c = {out, cap, 0};
+    shell_points(G, q, k, ref_support_radius(G), list_point, &c);
+    return c.n;
 }
 
 /* Thread count of the following calls (timing only; results do not depend on it). */

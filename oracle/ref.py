@@ -51,8 +51,8 @@ def lib():
         L.ref_project_rows.argtypes = [G, _c_dp, _c_ip, ctypes.c_int, _c_dp]
         L.ref_backproject_rows.argtypes = [G, _c_dp, _c_ip, ctypes.c_int, _c_dp]
         L.ref_fbp_voxels.argtypes = [G, _c_dp, _c_lp, ctypes.c_long, _c_dp]
-        L.ref_count_points.argtypes = [G, _c_ip, ctypes.c_int]
-        L.ref_count_points.restype = ctypes.c_long
+        L.ref_shell_points.argtypes = [G, ctypes.c_int, ctypes.c_int, _c_dp, ctypes.c_long]
+        L.ref_shell_points.restype = ctypes.c_long
         L.ref_max_threads.restype = ctypes.c_int
         L.ref_set_threads.argtypes = [ctypes.c_int]
         L.ref_set_threads.restype = None
@@ -170,10 +170,14 @@ def fbp(geom, p, voxels=None):
     return out
 
 
-def count_points(geom, rows=None):
+def shell_points(geom, q, k):
+    """The quadrature points of shell (q, k) that G and G^T visit, as an
+    (n, 4) array of rows (x, y, z, weight), in visiting order."""
     h = _GeomHolder(geom)
-    rows, rp = _rows(h, rows)
-    return int(lib().ref_count_points(h.ptr, rp, rows.size))
+    n = int(lib().ref_shell_points(h.ptr, int(q), int(k), _c_dp(), 0))
+    out = np.zeros((max(n, 1), 4))
+    lib().ref_shell_points(h.ptr, int(q), int(k), _dp(out), n)
+    return out[:n]
 
 
 def max_threads():

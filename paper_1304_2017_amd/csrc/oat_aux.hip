@@ -4,6 +4,7 @@
 // of Eq. (disfbp).
 #include "oat_dtype.hpp"
 #include "oat_internal.hpp"
+#include "oat_fbp_window.hpp"
 
 #pragma clang fp contract(off)
 
@@ -161,7 +162,6 @@ adj_gather_kernel(Problem P, const double *__restrict__ acc, int slices, void *_
 // is decided exactly as the FP64 problem statement takes it (the plan's
 // threshold table), because Eq. (disfbp) switches its forward difference at
 // integer k~.
-constexpr int FBP_TX = 16, FBP_TY = 16, FBP_TZ = 8;
 constexpr int FBP_LDS = 8192;   // floats of staged samples per chunk
 
 template <int P_DT, int IMG_DT>
@@ -180,8 +180,7 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
     // tile centre and half-diagonal (grid units)
     const float cx = blockIdx.x * FBP_TX + 0.5f * (FBP_TX - 1), cy = blockIdx.y * FBP_TY + 0.5f * (FBP_TY - 1);
     const float cz = iz0 + 0.5f * (FBP_TZ - 1);
-    const float hd = 0.5f * sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1) +
-                                          (FBP_TZ - 1) * (FBP_TZ - 1)));
+    const float hd = fbp_half_diag();
     const int K = P.nt;
     // With fr = kt - k and inv = 1/(kt + tau) = ri c0 dt / dx, the two
     // coefficients of Eq. (disfbp) are (1 - fr) inv - 1/2 and fr inv + 1/2,
@@ -202,8 +201,7 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
             // 1 ulp, the product); the tolerance is twice that at the tile's
             // largest kt.
             const float tol = fmaf(1e-6f, (dc + hd + 1.f) * P.sigma, 1e-5f);
-            sklo[j] = make_int2((int)floorf(fmaf(dc - hd, P.sigma, -P.tau)) - 2,
-                                __float_as_int(0.5f - tol));
+            sklo[j] = make_int2(fbp_first_sample(dc, P.sigma, P.tau), __float_as_int(0.5f - tol));
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nq * win; t += blockDim.x) {
@@ -251,8 +249,9 @@ fbp_kernel(Problem P, const void *__restrict__ pres, void *__restrict__ img, int
                     }
                 }
                 // ki - sk.x lies in 0 .. win - 2 (the window spans the tile's
-                // sample range with margins); the unsigned minimum only keeps
-                // the reads inside the row.
+                // sample range with margins; tests/host/fbp_window_check.cpp
+                // checks it over every workload geometry); the unsigned
+                // minimum only keeps the reads inside the row.
                 const unsigned li = min((unsigned)(ki - sk.x), (unsigned)(win - 2));
                 const float p0 = row[li], dp = row[li + 1] - p0;
                 acc_a[v] = fmaf(d.fbp_w * ri, fmaf(fr, dp, p0), acc_a[v]);
@@ -306,9 +305,7 @@ hipError_t launch_fbp(const Problem &P, const void *p, int p_dtype, void *img, i
                       hipStream_t s)
 {
     // Samples a tile can touch per transducer: its diagonal in shells plus margins.
-    const float diag = sqrtf((float)((FBP_TX - 1) * (FBP_TX - 1) + (FBP_TY - 1) * (FBP_TY - 1) +
-                                     (FBP_TZ - 1) * (FBP_TZ - 1)));
-    int win = (int)ceilf(diag * P.sigma) + 6;
+    const int win = fbp_window(P.sigma);
     int chunk = FBP_LDS / win;
     if (chunk > FBP_LDS / 8) chunk = FBP_LDS / 8;
     if (chunk < 1) return hipErrorInvalidValue;

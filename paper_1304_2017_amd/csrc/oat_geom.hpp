@@ -58,16 +58,24 @@ OAT_HD float acos_approx(float x)
     return x >= 0.0f ? r : kPi - r;
 }
 
-// atan2 with absolute error below 2e-5 rad (odd minimax polynomial for
-// atan on [-1, 1] plus octant reduction); conservative-range use only.
+// atan2 by octant reduction to atan on [0, 1], with the polynomial of
+// Abramowitz & Stegun 4.4.49 (|error| <= 2e-8 rad on [0, 1]; in FP32, with
+// the approximate reciprocal, a few 1e-7 rad); conservative-range use only.
 OAT_HD float atan2_approx(float y, float x)
 {
     float ax = fabsf(x), ay = fabsf(y);
     float mx = fmaxf_(ax, ay), mn = fminf_(ax, ay);
     float a = mx > 0.0f ? mn * rcp_approx(mx) : 0.0f;
     float s = a * a;
-    float r = ((((-0.0117212f * s + 0.05265332f) * s - 0.11643287f) * s + 0.19354346f) * s
-               - 0.33262347f) * s * a + 0.99997726f * a;
+    float p = 0.0028662257f;
+    p = p * s - 0.0161657367f;
+    p = p * s + 0.0429096138f;
+    p = p * s - 0.0752896400f;
+    p = p * s + 0.1065626393f;
+    p = p * s - 0.1420889944f;
+    p = p * s + 0.1999355085f;
+    p = p * s - 0.3333314528f;
+    float r = (p * s) * a + a;
     if (ay > ax) r = 1.57079632679f - r;
     if (x < 0.0f) r = kPi - r;
     return y < 0.0f ? -r : r;

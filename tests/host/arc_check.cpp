@@ -21,6 +21,22 @@ int main(int argc, char **argv)
     unsigned seed = argc > 2 ? (unsigned)atoi(argv[2]) : 1u;
     std::mt19937_64 rng(seed);
     std::uniform_real_distribution<double> U01(0.0, 1.0);
+    // atan2_approx (Abramowitz & Stegun 4.4.49 after octant reduction)
+    // against the library atan2 over the whole circle and several radii.
+    double atan_err = 0.0;
+    for (int i = 0; i <= 400000; ++i) {
+        const double a = -M_PI + 2.0 * M_PI * i / 400000.0;
+        for (double rad : {1e-3, 1.0, 700.0}) {
+            const float x = (float)(rad * cos(a)), y = (float)(rad * sin(a));
+            double e = fabs((double)atan2_approx(y, x) - atan2((double)y, (double)x));
+            if (e > M_PI) e = 2.0 * M_PI - e;   // the two ends of (-pi, pi]
+            atan_err = fmax(atan_err, e);
+        }
+    }
+    if (!(atan_err <= 1e-6)) {
+        printf("FAIL atan2_approx error %.3e\n", atan_err);
+        return 1;
+    }
     long rings = 0, inside = 0, covered = 0;
     for (int t = 0; t < trials; ++t) {
         // transducer at distance 40..600 grid units, random direction

@@ -135,3 +135,46 @@ def test_flag_and_status_constants_match_the_header():
     for name, value in enums.items():
         assert getattr(oat, name) == value, name
     assert {"OAT_OK", "OAT_ERR_ARG", "OAT_ERR_GEOMETRY", "OAT_F32", "OAT_BF16"} <= set(enums)
+
+
+def _fbp_window_workloads():
+    """Every workload geometry: the 32^3, 256^3 (2048 hemisphere and 8192
+    sphere), 192^3, 128^3 and paper-shape cases, and grids with ragged,
+    off-centre and t0 != 0 timing."""
+    from paper_1304_2017_amd import synth
+    g = [synth.config_small(0)[0], synth.config_large_geometry(), synth.config_c_geometry(),
+         synth.config_d_geometry(), synth.config_e_geometry(), synth.config_p_geometry()]
+    for n, dx, off, Q, Rs, K, dt, t0 in [((37, 29, 23), 0.45, (0.3, -0.7, 0.2), 24, 21.0, 300, 0.08, 0.0),
+                                         ((41, 22, 3), 0.3, (-1.0, 0.5, 0.0), 16, 18.0, 400, 0.05, 5.0),
+                                         ((40, 20, 21), 0.5, (0.0, 0.0, 0.0), 8, 22.0, 260, 0.1, -1.0),
+                                         ((1, 1, 1), 0.5, (0.0, 0.0, 0.0), 3, 5.0, 3, 0.2, 3.0)]:
+        g.append(synth.Geometry(n[0], n[1], n[2], dx, synth.centred_origin(n[0], dx) + off[0],
+                                synth.centred_origin(n[1], dx) + off[1],
+                                synth.centred_origin(n[2], dx) + off[2],
+                                synth.fibonacci_sphere(Q, Rs), K, dt, t0, 1.5, 1.0))
+    return g
+
+
+def test_host_fbp_window_bounds(tmp_path):
+    """FBP reads samples floor(kt) and floor(kt) + 1 from a per-(tile,
+    transducer) window of staged samples; the window must hold them for
+    every voxel, tile and transducer of every workload (the kernel only
+    clamps the index to stay inside its row)."""
+    exe = tmp_path / "fbp_window_check"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1304_2017_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "host", "fbp_window_check.cpp"), "-o", str(exe)],
+                   check=True)
+    for geom in _fbp_window_workloads():
+        lines = [" ".join(repr(float(v)) if isinstance(v, float) else str(v) for v in
+                          (geom.nx, geom.ny, geom.nz, float(geom.dx), float(geom.x0),
+                           float(geom.y0), float(geom.z0), float(geom.c0), float(geom.dt),
+                           float(geom.t0), geom.n_t, geom.n_det))]
+        lines += [" ".join(repr(float(c)) for c in r) for r in geom.det_xyz]
+        r = subprocess.run([str(exe)], input="\n".join(lines) + "\n", capture_output=True,
+                           text=True, timeout=300)
+        assert r.returncode == 0, (geom.name, r.stdout + r.stderr)
+        assert r.stdout.startswith("OK"), (geom.name, r.stdout)
+        pairs, lo_m, hi_m = map(int, r.stdout.split()[1:4])
+        print(f"{geom.name or geom.shape}: {pairs} tile-transducer pairs, margins {lo_m} / {hi_m}")
+        assert pairs > 0 and lo_m >= 0 and hi_m >= 0

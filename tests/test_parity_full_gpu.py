@@ -3,15 +3,22 @@
 FP64 oracle can compute one by one:
 
 - H and G: whole rows of a few transducers (the oracle evaluates rows);
-- H^T: the full image for data that is nonzero on two transducers only
-  (the kernel still walks every transducer's points);
+- H^T: the full image for data that is nonzero on a few transducers (the
+  kernel still walks every transducer's points), among them one transducer
+  in each of G^T's 22 windows of 96, so every window's fixed-point scale,
+  the FP64 sums of all windows and every slice of a brick's windows carry
+  data;
+- the adjoint identity <Hx, y> = <x, H^T y> with random x and y on every
+  transducer;
 - FBP: sampled voxels of the full image for seeded Gaussian data.
+Each comparison gates the relative L2 and max |error| / max |reference|.
 """
 import sys
 
 import numpy as np
 import pytest
 
+from checks import BF16_ELEM, check
 from paper_1304_2017_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -52,11 +59,8 @@ def test_full_size_project_rows(large):
     g = g.double().cpu().numpy()[rows]
     gd = geom.as_dict()
     img64 = img.astype(np.float64)
-    eg = rel(g, ref.srt(gd, img64, rows=rows))
-    ep = rel(p, ref.project(gd, img64, rows=rows))
-    _say(f"  G rel {eg:.3e}  H rel {ep:.3e}")
-    assert eg < 1e-6
-    assert ep < 1e-5
+    check("G rows", g, ref.srt(gd, img64, rows=rows), 5e-7)
+    check("H rows", p, ref.project(gd, img64, rows=rows), 1e-5)
 
 
 def test_full_size_project_rows_bf16(large):
@@ -68,9 +72,7 @@ def test_full_size_project_rows_bf16(large):
     torch.cuda.synchronize()
     p = p.double().cpu().numpy()[rows]
     img_b = xb.double().cpu().numpy()
-    e = rel(p, ref.project(geom.as_dict(), img_b, rows=rows))
-    _say(f"  rel {e:.3e}")
-    assert e < 2e-3
+    check("H bf16 rows", p, ref.project(geom.as_dict(), img_b, rows=rows), 2e-3, BF16_ELEM)
 
 
 def test_full_size_backproject_two_transducers(large):
@@ -84,9 +86,65 @@ def test_full_size_backproject_two_transducers(large):
     torch.cuda.synchronize()
     a = a.double().cpu().numpy()
     want = ref.backproject(geom.as_dict(), y[rows].astype(np.float64), rows=rows)
-    e = rel(a, want)
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-5
+    check("H^T", a, want, 1e-5)
+
+
+def window_rows(n_det, window=96):
+    """One transducer in every window of `window`, at a position within the
+    window that moves from window to window (first, last and in between)."""
+    rows = []
+    for w in range((n_det + window - 1) // window):
+        size = min(window, n_det - w * window)
+        rows.append(w * window + (w * 37) % size)
+    return np.array(rows, dtype=np.int32)
+
+
+def test_full_size_backproject_one_row_per_window(large):
+    """Seeded data on one transducer in each of the 22 windows (and so in
+    all three brick slices), zero elsewhere: the whole H^T image against the
+    oracle's sum over those rows."""
+    geom, img, plan = large
+    rows = window_rows(geom.n_det)
+    assert rows.size == 22
+    _say(f"[gpu-full] H^T with data on one transducer per window: {rows.tolist()}")
+    rng = np.random.default_rng(14)
+    y = np.zeros((geom.n_det, geom.n_t), dtype=np.float32)
+    y[rows] = rng.normal(size=(rows.size, geom.n_t)).astype(np.float32)
+    a = plan.backproject(torch.from_numpy(y).cuda())
+    g = plan.backproject(torch.from_numpy(y).cuda(), srt_only=True)
+    torch.cuda.synchronize()
+    gd = geom.as_dict()
+    y64 = y[rows].astype(np.float64)
+    check("H^T 22 windows", a.double().cpu().numpy(), ref.backproject(gd, y64, rows=rows), 1e-5)
+    check("G^T 22 windows", g.double().cpu().numpy(), ref.srt_adj(gd, y64, rows=rows), 1e-5)
+
+
+def test_full_size_adjoint_identity(large):
+    """<Hx, y> = <x, H^T y> at full size with seeded random x and y on all
+    2048 transducers, every window and slice carrying data; bound
+    1e-6 |Hx| |y| (both sides FP32 operators, inner products in FP64)."""
+    geom, img, plan = large
+    _say("[gpu-full] adjoint identity, random data on every transducer")
+    gen = torch.Generator(device="cuda").manual_seed(15)
+    x = torch.randn(geom.shape, device="cuda", generator=gen)
+    y = torch.randn((geom.n_det, geom.n_t), device="cuda", generator=gen)
+    Hx = plan.project(x)
+    HTy = plan.backproject(y)
+    torch.cuda.synchronize()
+    lhs = float(torch.dot(Hx.double().ravel(), y.double().ravel()))
+    rhs = float(torch.dot(x.double().ravel(), HTy.double().ravel()))
+    scale = float(Hx.double().norm() * y.double().norm())
+    _say(f"  <Hx,y> {lhs:.9e}  <x,H^T y> {rhs:.9e}  |diff| / (|Hx||y|) {abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
+    # and with the ellipsoid phantom as x
+    xi = torch.from_numpy(img).cuda()
+    Hxi = plan.project(xi)
+    torch.cuda.synchronize()
+    lhs = float(torch.dot(Hxi.double().ravel(), y.double().ravel()))
+    rhs = float(torch.dot(xi.double().ravel(), HTy.double().ravel()))
+    scale = float(Hxi.double().norm() * y.double().norm())
+    _say(f"  phantom: |diff| / (|Hx||y|) {abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) <= 1e-6 * scale
 
 
 def test_full_size_fbp_sampled_voxels(large):
@@ -99,9 +157,7 @@ def test_full_size_fbp_sampled_voxels(large):
     f = f.double().cpu().numpy().ravel()
     vox = rng.choice(geom.n_vox, 3000, replace=False)
     want = ref.fbp(geom.as_dict(), p.astype(np.float64), voxels=vox)
-    e = rel(f[vox], want)
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-5
+    check("FBP voxels", f[vox], want, 1e-5)
 
 
 def test_sphere_8192_shapes_on_64_transducers():
@@ -117,18 +173,16 @@ def test_sphere_8192_shapes_on_64_transducers():
     p = plan.project(torch.from_numpy(img).cuda())
     torch.cuda.synchronize()
     p = p.double().cpu().numpy()
-    eh = rel(p, ref.project(gd, img64))
+    check("H", p, ref.project(gd, img64), 1e-5)
     rng = np.random.default_rng(21)
     y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32)
     a = plan.backproject(torch.from_numpy(y).cuda())
     torch.cuda.synchronize()
-    eht = rel(a.double().cpu().numpy(), ref.backproject(gd, y.astype(np.float64)))
+    check("H^T", a.double().cpu().numpy(), ref.backproject(gd, y.astype(np.float64)), 1e-5)
     pf = p.astype(np.float32)
     f = plan.fbp(torch.from_numpy(pf).cuda())
     torch.cuda.synchronize()
-    ef = rel(f.double().cpu().numpy(), ref.fbp(gd, pf.astype(np.float64)))
-    _say(f"  H rel {eh:.3e}  H^T rel {eht:.3e}  FBP rel {ef:.3e}")
-    assert eh < 1e-5 and eht < 1e-5 and ef < 1e-5
+    check("FBP", f.double().cpu().numpy(), ref.fbp(gd, pf.astype(np.float64)), 1e-5)
 
 
 def test_paper_shape_rows_and_voxels():
@@ -145,16 +199,14 @@ def test_paper_shape_rows_and_voxels():
     p = plan.project(x)
     g = plan.project(x, srt_only=True)
     torch.cuda.synchronize()
-    eg = rel(g.double().cpu().numpy()[rows], ref.srt(gd, img64, rows=rows))
-    ep = rel(p.double().cpu().numpy()[rows], ref.project(gd, img64, rows=rows))
+    check("G rows", g.double().cpu().numpy()[rows], ref.srt(gd, img64, rows=rows), 5e-7)
+    check("H rows", p.double().cpu().numpy()[rows], ref.project(gd, img64, rows=rows), 1e-5)
     pn = p.float()
     f = plan.fbp(pn)
     torch.cuda.synchronize()
     vox = np.random.default_rng(22).choice(geom.n_vox, 2000, replace=False)
-    ef = rel(f.double().cpu().numpy().ravel()[vox],
-             ref.fbp(gd, pn.double().cpu().numpy(), voxels=vox))
-    _say(f"  G rel {eg:.3e}  H rel {ep:.3e}  FBP rel {ef:.3e}")
-    assert eg < 1e-6 and ep < 1e-5 and ef < 1e-5
+    check("FBP voxels", f.double().cpu().numpy().ravel()[vox],
+          ref.fbp(gd, pn.double().cpu().numpy(), voxels=vox), 1e-5)
 
 
 def test_full_size_bf16_backproject_and_fbp(large):
@@ -171,13 +223,12 @@ def test_full_size_bf16_backproject_and_fbp(large):
     torch.cuda.synchronize()
     assert torch.equal(a, a2)
     y_b = yb.double().cpu().numpy()
-    e = rel(a.double().cpu().numpy(), ref.backproject(geom.as_dict(), y_b[rows], rows=rows))
+    check("H^T bf16", a.double().cpu().numpy(),
+          ref.backproject(geom.as_dict(), y_b[rows], rows=rows), 2e-3, BF16_ELEM)
     p = torch.from_numpy(rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32))
     pb = p.to(torch.bfloat16).cuda()
     f = plan.fbp(pb, out_dtype=torch.bfloat16)
     torch.cuda.synchronize()
     vox = rng.choice(geom.n_vox, 2000, replace=False)
-    ef = rel(f.double().cpu().numpy().ravel()[vox],
-             ref.fbp(geom.as_dict(), pb.double().cpu().numpy(), voxels=vox))
-    _say(f"[gpu-full] BF16 H^T rel {e:.3e}  FBP rel {ef:.3e}")
-    assert e < 2e-3 and ef < 2e-3
+    check("FBP bf16 voxels", f.double().cpu().numpy().ravel()[vox],
+          ref.fbp(geom.as_dict(), pb.double().cpu().numpy(), voxels=vox), 2e-3, BF16_ELEM)

@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (relative L2 over the whole output): FP32 storage 1e-5 for H,
-H^T and FBP; G alone 1e-6 (D amplifies G's error); BF16 storage 2e-3, with
-the oracle fed the same BF16-rounded inputs.
+Tolerances, each gated both as a relative L2 over the whole output and
+element by element (max |error| / max |reference|, see checks.py): FP32
+storage 1e-5 for H, H^T and FBP; G alone 5e-7 (D amplifies G's error about
+12x at the 256^3 workload); BF16 output storage 2e-3 in L2 and half a BF16
+ulp element-wise, with the oracle fed the same BF16-rounded inputs.
 """
 import math
 import sys
@@ -10,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+from checks import BF16_ELEM, check
 from paper_1304_2017_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -72,18 +75,14 @@ def test_srt_only_matches_oracle(small):
     geom, _, img, plan, seed = small
     _say(f"[gpu] G 32^3 seed {seed}")
     g = _np(plan.project(_t(img), srt_only=True))
-    e = rel(g, ref.srt(geom.as_dict(), img))
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-6
+    check("G", g, ref.srt(geom.as_dict(), img), 5e-7)
 
 
 def test_project_matches_oracle(small):
     geom, _, img, plan, seed = small
     _say(f"[gpu] H 32^3 seed {seed}")
     p = _np(plan.project(_t(img)))
-    e = rel(p, ref.project(geom.as_dict(), img))
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-5
+    check("H", p, ref.project(geom.as_dict(), img), 1e-5)
 
 
 def test_backproject_matches_oracle(small):
@@ -92,13 +91,9 @@ def test_backproject_matches_oracle(small):
     rng = np.random.default_rng(100 + seed)
     y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
     a = _np(plan.backproject(_t(y)))
-    e = rel(a, ref.backproject(geom.as_dict(), y))
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-5
+    check("H^T", a, ref.backproject(geom.as_dict(), y), 1e-5)
     b = _np(plan.backproject(_t(y), srt_only=True))
-    e2 = rel(b, ref.srt_adj(geom.as_dict(), y))
-    _say(f"  G^T rel {e2:.3e}")
-    assert e2 < 1e-5
+    check("G^T", b, ref.srt_adj(geom.as_dict(), y), 1e-5)
 
 
 def test_fbp_matches_oracle(small):
@@ -106,9 +101,7 @@ def test_fbp_matches_oracle(small):
     _say(f"[gpu] FBP 32^3 seed {seed}")
     p = synth.nwave_balls(geom, balls).astype(np.float32).astype(np.float64)
     f = _np(plan.fbp(_t(p)))
-    e = rel(f, ref.fbp(geom.as_dict(), p))
-    _say(f"  rel {e:.3e}")
-    assert e < 1e-5
+    check("FBP", f, ref.fbp(geom.as_dict(), p), 1e-5)
 
 
 def test_fbp_floor_at_exact_sample_times(Plan):
@@ -155,7 +148,7 @@ def test_adjoint_identity_on_gpu(small):
     rhs = float(torch.dot(x.double().ravel(), HTy.double().ravel()))
     scale = float(Hx.double().norm() * y.double().norm())
     _say(f"  |<Hx,y>-<x,H^T y>| / (|Hx||y|) = {abs(lhs - rhs) / scale:.3e}")
-    assert abs(lhs - rhs) <= 1e-5 * scale
+    assert abs(lhs - rhs) <= 1e-6 * scale
 
 
 def test_bf16_storage(small_bf16):
@@ -164,17 +157,17 @@ def test_bf16_storage(small_bf16):
     gd = geom.as_dict()
     img_b = _bf16_round(img)
     p = _np(plan.project(_t(img, torch.bfloat16), out_dtype=torch.bfloat16))
-    assert rel(p, ref.project(gd, img_b)) < 2e-3
+    check("H bf16", p, ref.project(gd, img_b), 2e-3, BF16_ELEM)
     rng = np.random.default_rng(300 + seed)
     y_b = _bf16_round(rng.normal(size=(geom.n_det, geom.n_t)))
     a = _np(plan.backproject(_t(y_b, torch.bfloat16), out_dtype=torch.bfloat16))
-    assert rel(a, ref.backproject(gd, y_b)) < 2e-3
+    check("H^T bf16", a, ref.backproject(gd, y_b), 2e-3, BF16_ELEM)
     pn = _bf16_round(synth.nwave_balls(geom, balls))
     f = _np(plan.fbp(_t(pn, torch.bfloat16), out_dtype=torch.bfloat16))
-    assert rel(f, ref.fbp(gd, pn)) < 2e-3
+    check("FBP bf16", f, ref.fbp(gd, pn), 2e-3, BF16_ELEM)
     # mixed: BF16 image in, FP32 data out
     p2 = _np(plan.project(_t(img, torch.bfloat16), out_dtype=torch.float32))
-    assert rel(p2, ref.project(gd, img_b)) < 1e-5
+    check("H bf16 in, f32 out", p2, ref.project(gd, img_b), 1e-5)
 
 
 # ---------------------------------------------------------------------------
@@ -216,14 +209,14 @@ def test_ragged_grids(case, table, Plan):
     assert (st["arc_table_bytes"] > 0) == (table != "bounds")
     assert (st["segment_table_bytes"] > 0) == (table == "segments")
     g = _np(plan.project(_t(img), srt_only=True))
-    assert rel(g, ref.srt(gd, img)) < 1e-6
+    check("G", g, ref.srt(gd, img), 5e-7)
     p = _np(plan.project(_t(img)))
-    assert rel(p, ref.project(gd, img)) < 1e-5
+    check("H", p, ref.project(gd, img), 1e-5)
     y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
     a = _np(plan.backproject(_t(y)))
-    assert rel(a, ref.backproject(gd, y)) < 1e-5
+    check("H^T", a, ref.backproject(gd, y), 1e-5)
     f = _np(plan.fbp(_t(y)))
-    assert rel(f, ref.fbp(gd, y)) < 1e-5
+    check("FBP", f, ref.fbp(gd, y), 1e-5)
 
 
 def test_zero_inputs_and_overwrite(Plan):
@@ -301,8 +294,8 @@ def test_table_paths_agree(seed, Plan):
     gs, gt, gn = (_np(p.project(x, srt_only=True)) for p in (ps, pt, pn))
     e1, e2 = rel(gs, gn), rel(gt, gn)
     _say(f"  G segments vs bounds rel {e1:.3e}, arcs vs bounds rel {e2:.3e}")
-    assert e1 < 1e-6 and e2 < 1e-6
-    assert rel(gn, ref.srt(geom.as_dict(), img)) < 1e-6
+    assert e1 < 5e-7 and e2 < 5e-7
+    check("G bounds path", gn, ref.srt(geom.as_dict(), img), 5e-7)
     rng = np.random.default_rng(400 + seed)
     y = _t(rng.normal(size=(geom.n_det, geom.n_t)))
     a_s, a_t, a_n = (_np(p.backproject(y, srt_only=True)) for p in (ps, pt, pn))
@@ -321,11 +314,10 @@ def test_backproject_with_wide_dynamic_range(Plan):
     y = rng.normal(size=(geom.n_det, geom.n_t))
     y[5] *= 1e4
     y = y.astype(np.float32).astype(np.float64)
-    e = rel(_np(plan.backproject(_t(y))), ref.backproject(gd, y))
+    _say("[gpu] H^T with one loud transducer, and with 1e-30 data")
+    check("H^T loud", _np(plan.backproject(_t(y))), ref.backproject(gd, y), 1e-5)
     tiny = (rng.normal(size=(geom.n_det, geom.n_t)) * 1e-30).astype(np.float32).astype(np.float64)
-    e2 = rel(_np(plan.backproject(_t(tiny))), ref.backproject(gd, tiny))
-    _say(f"[gpu] H^T loud transducer rel {e:.3e}; 1e-30 data rel {e2:.3e}")
-    assert e < 1e-5 and e2 < 1e-5
+    check("H^T 1e-30", _np(plan.backproject(_t(tiny))), ref.backproject(gd, tiny), 1e-5)
 
 
 @pytest.fixture(scope="module")
@@ -347,10 +339,9 @@ def test_backproject_single_transducer(q, small1_plan):
     rng = np.random.default_rng(100 + q)
     y = np.zeros((geom.n_det, geom.n_t))
     y[q] = rng.normal(size=geom.n_t).astype(np.float32)
-    e = rel(_np(plan.backproject(_t(y))),
-            ref.backproject(geom.as_dict(), y[q:q + 1], rows=np.array([q], dtype=np.int32)))
-    _say(f"[gpu] H^T data on transducer {q}: rel {e:.3e}")
-    assert e < 1e-5
+    _say(f"[gpu] H^T data on transducer {q}")
+    check("H^T", _np(plan.backproject(_t(y))),
+          ref.backproject(geom.as_dict(), y[q:q + 1], rows=np.array([q], dtype=np.int32)), 1e-5)
 
 
 def _brick_slices(nbricks, items, min_items):
@@ -386,14 +377,13 @@ def test_transducer_slices(table, Plan):
     y = rng.normal(size=(geom.n_det, geom.n_t)).astype(np.float32).astype(np.float64)
     plan = Plan(geom, 0, **TABLES[table])
     g = _np(plan.project(_t(img), srt_only=True))
-    e_g = rel(g, ref.srt(gd, img))
+    check("G", g, ref.srt(gd, img), 5e-7)
     a = _np(plan.backproject(_t(y), srt_only=True))
-    e_a = rel(a, ref.srt_adj(gd, y))
+    check("G^T", a, ref.srt_adj(gd, y), 1e-5)
     lhs = float(np.dot(g.ravel(), y.ravel()))
     rhs = float(np.dot(img.ravel(), a.ravel()))
     scale = float(np.linalg.norm(g) * np.linalg.norm(y))
-    _say(f"  G rel {e_g:.3e}  G^T rel {e_a:.3e}  adjoint (/ norms) {abs(lhs - rhs) / scale:.3e}")
-    assert e_g < 1e-6 and e_a < 1e-5
+    _say(f"  adjoint (/ norms) {abs(lhs - rhs) / scale:.3e}")
     assert abs(lhs - rhs) <= 1e-6 * scale
     if table == "segments":
         a_b = _np(Plan(geom, 0, **TABLES["bounds"]).backproject(_t(y), srt_only=True))

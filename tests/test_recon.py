@@ -116,7 +116,8 @@ def test_pls_cg_matches_oracle_recursion(mu):
     got = res.image.double().cpu().numpy()
     e = float(np.linalg.norm(got - a) / np.linalg.norm(a))
     _say(f"  iterate rel {e:.3e}; residuals {['%.4f' % v for v in res.residuals]}")
-    assert e < 1e-3
+    # about 10x the measured FP32 error of five iterations
+    assert e < 2e-6
     # CG minimises the objective monotonically along its Krylov space
     obj = res.objective
     assert all(obj[i + 1] <= obj[i] * (1 + 1e-6) for i in range(len(obj) - 1))
@@ -265,6 +266,8 @@ def test_pls_tv_matches_oracle_recursion(storage):
     got = res.image.double().cpu().numpy()
     e = float(np.linalg.norm(got - a) / np.linalg.norm(a))
     _say(f"  iterate rel {e:.3e}; residuals {['%.4f' % v for v in res.residuals]}")
-    assert e < (1e-3 if storage == "f32" else 3e-2)
+    # about 10x the measured errors (1.5e-7 FP32; 6e-4 with BF16 storage of
+    # the operator inputs and outputs)
+    assert e < (2e-6 if storage == "f32" else 6e-3)
     obj = res.objective
     assert all(obj[i + 1] <= obj[i] * (1 + 1e-4) for i in range(len(obj) - 1))
