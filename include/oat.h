@@ -232,6 +232,23 @@ int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *
 int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, double df,
                         void *img, oat_dtype img_dtype, uint32_t flags, void *stream);
 
+/* oat_sph_backproject for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, operation and results (bit for bit) as
+ * oat_sph_backproject, which may grow the plan's workspace; this variant
+ * calls no hipMalloc, hipFree or allocating library routine and never waits
+ * for the device.  Images of fewer than 512K voxels split the transducers
+ * into slices whose FP64 partial images go to a fixed 8 MiB scratch array in
+ * device memory, one per GPU (resolved at the first oat_plan_create on that
+ * GPU and held until the process ends); every image this library accepts
+ * needs at most 2 x 523776 x 8 bytes of it, and a larger need is rejected
+ * with OAT_ERR_ARG.  Every slice value is written before it is read, so the
+ * scratch needs no clearing.  All calls on one GPU share that scratch: calls
+ * that overlap in time on one GPU (other streams, other plans, other
+ * threads) race and give wrong results. */
+int oat_sph_backproject_noalloc(oat_plan *plan, const void *u, int n_f, double f_min, double df,
+                                void *img, oat_dtype img_dtype, uint32_t flags, void *stream);
+
 /* Thread-local, NUL-terminated description of the last non-OK status
  * returned on this thread ("" if none).  Valid until the next call. */
 const char *oat_last_error(void);

@@ -182,5 +182,14 @@ int sph_adj_slices(const Problem &P);
 size_t sph_adj_workspace_bytes(const Problem &P);
 hipError_t launch_sph_backproject(const Problem &P, const float2 *u, int n_f, double f_min,
                                   double df, void *img, int img_dt, double *work, hipStream_t s);
+// The adjoint's slice sums never exceed 2 x 523776 doubles: sph_adj_slices
+// splits only images of fewer than 1024 workgroups of 512 voxels, and over
+// every such voxel count N the product slices x N peaks at two slices of
+// 523776 voxels.  So this fixed scratch holds them for every image.
+constexpr size_t SPH_SCRATCH_BYTES = size_t(8) << 20;
+// Device address of the fixed scratch on `device`, which must be current.
+// Resolved by hipGetSymbolAddress on the first call for that device, cached
+// afterwards (thread-safe).
+hipError_t sph_scratch_address(int device, double **out);
 
 }  // namespace oat

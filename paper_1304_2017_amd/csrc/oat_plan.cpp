@@ -489,6 +489,16 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         delete plan;
         return fail_hip(e, "hipSetDevice");
     }
+    {
+        // Resolve this device's fixed scratch (oat_sph_backproject_noalloc)
+        // while the device is current; later plans reuse the cached address.
+        double *scr = nullptr;
+        if ((e = sph_scratch_address(device, &scr)) != hipSuccess) {
+            delete plan;
+            (void)hipSetDevice(prev);
+            return fail_hip(e, "oat_plan_create: hipGetSymbolAddress(scratch)");
+        }
+    }
     auto alloc = [&](void **p, size_t bytes, const char *what) -> hipError_t {
         hipError_t err = hipMalloc(p, bytes < 16 ? 16 : bytes);
         if (err != hipSuccess) g_last_error = std::string("hipMalloc ") + what;
@@ -810,6 +820,29 @@ int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, do
                                           (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_sph_backproject: launch");
+    return OAT_OK;
+}
+
+int oat_sph_backproject_noalloc(oat_plan *plan, const void *u, int n_f, double f_min, double df,
+                                void *img, oat_dtype img_dtype, uint32_t flags, void *stream)
+{
+    int rc = check_sph(plan, u, img, (int)img_dtype, n_f, f_min, df, flags,
+                       "oat_sph_backproject_noalloc");
+    if (rc) return rc;
+    const size_t need = sph_adj_workspace_bytes(plan->P);
+    if (need > SPH_SCRATCH_BYTES)
+        return fail(OAT_ERR_ARG, "oat_sph_backproject_noalloc: the image needs " +
+                                     std::to_string(need) + " bytes of scratch, more than the " +
+                                     std::to_string(SPH_SCRATCH_BYTES) + " available");
+    int prev;
+    if ((rc = with_device(plan, prev))) return rc;
+    double *scr = nullptr;
+    hipError_t e = sph_scratch_address(plan->device, &scr);
+    if (e == hipSuccess)
+        e = launch_sph_backproject(plan->P, (const float2 *)u, n_f, f_min, df, img, (int)img_dtype,
+                                   scr, (hipStream_t)stream);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail_hip(e, "oat_sph_backproject_noalloc: launch");
     return OAT_OK;
 }
 

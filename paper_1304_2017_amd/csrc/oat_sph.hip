@@ -10,6 +10,9 @@
 // the phase's fractional turn followed by short FP32 recurrences along l (a
 // rotation in the forward kernel, Horner's rule in the adjoint); sums are
 // FP64.
+#include <mutex>
+#include <vector>
+
 #include "oat_dtype.hpp"
 #include "oat_geom.hpp"
 #include "oat_internal.hpp"
@@ -289,7 +292,30 @@ sph_adj_sum_kernel(const double *__restrict__ slice_sum, int slices, long long N
     store_val(img, (size_t)n, img_dt, (float)acc);
 }
 
+// Device scratch of oat_sph_backproject_noalloc: the adjoint's FP64 slice
+// partial images.  Each GPU the library runs on holds its own copy until the
+// process ends.  In host code this name is only a stand-in for the symbol:
+// kernels and copies get the address that sph_scratch_address resolved.
+static __device__ __align__(256) double scratch[SPH_SCRATCH_BYTES / sizeof(double)];
+
 }  // namespace
+
+hipError_t sph_scratch_address(int device, double **out)
+{
+    static std::mutex mu;
+    static std::vector<double *> addr;   // per device ordinal; null until resolved
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+    if (!addr[(size_t)device]) {
+        double *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[(size_t)device] = p;
+    }
+    *out = addr[(size_t)device];
+    return hipSuccess;
+}
 
 size_t sph_workspace_bytes(const Problem &P, int n_f)
 {

@@ -31,6 +31,7 @@ OAT_FLAG_DETERMINISTIC = 2
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
             "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",
             "oat_plan_set_eir", "oat_deconvolve", "oat_sph_project", "oat_sph_backproject",
+            "oat_sph_backproject_noalloc",
             # include/oat_cnn.h
             "oat_conv3d_forward", "oat_conv3d_backward_weight_workspace",
             "oat_conv3d_backward_weight", "oat_adam_step", "oat_mse_workspace", "oat_mse")
@@ -101,6 +102,8 @@ def lib():
         L.oat_sph_backproject.argtypes = [vp, vp, ctypes.c_int, d, d, vp, ctypes.c_int,
                                           ctypes.c_uint32, vp]
         L.oat_sph_backproject.restype = ctypes.c_int
+        L.oat_sph_backproject_noalloc.argtypes = L.oat_sph_backproject.argtypes
+        L.oat_sph_backproject_noalloc.restype = ctypes.c_int
         L.oat_last_error.argtypes = []
         L.oat_last_error.restype = ctypes.c_char_p
         L.oat_plan_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
@@ -289,6 +292,21 @@ class Plan:
         _check(lib().oat_sph_backproject(self._h, ctypes.c_void_p(u.data_ptr()), n_f,
                                          float(f_min), float(df), ctypes.c_void_p(out.data_ptr()),
                                          _dtype_code(out), 0, self._stream(stream)))
+        return out
+
+    def sph_backproject_noalloc(self, u, f_min: float, df: float, out, stream=None):
+        """Eq. (sphbwd) into the caller's `out` through the entry point that
+        allocates nothing (fixed per-GPU scratch; overlapping calls on one GPU
+        race)."""
+        import torch
+        if not isinstance(u, torch.Tensor) or u.dtype != torch.complex64 or u.dim() != 2:
+            raise TypeError("sph_backproject_noalloc expects complex64 data [n_det, n_f]")
+        n_f = int(u.shape[1])
+        self._prep(u, (self.geom.n_det, n_f))
+        self._prep(out, self.image_shape)
+        _check(lib().oat_sph_backproject_noalloc(
+            self._h, ctypes.c_void_p(u.data_ptr()), n_f, float(f_min), float(df),
+            ctypes.c_void_p(out.data_ptr()), _dtype_code(out), 0, self._stream(stream)))
         return out
 
     def deconvolve(self, u, f_cut: float, out=None, out_dtype=None, stream=None):

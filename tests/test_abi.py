@@ -92,6 +92,8 @@ def test_null_arguments():
     assert L.oat_project(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
     assert L.oat_backproject(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
     assert L.oat_fbp(None, None, 0, None, 0, 0, None) == oat.OAT_ERR_ARG
+    assert L.oat_sph_backproject_noalloc(None, None, 16, 0.0, 0.1, None, 0, 0,
+                                         None) == oat.OAT_ERR_ARG
     assert "null" in oat.last_error()
     L.oat_plan_destroy(None)
 
