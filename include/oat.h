@@ -117,35 +117,38 @@ typedef struct oat_plan oat_plan;
  * On success *out owns device memory until oat_plan_destroy. */
 int oat_plan_create(const oat_geometry *geom, int device, oat_plan **out);
 
-/* Plan options for oat_plan_create_ex.
- *
- * arc_table_bytes: device memory the plan may spend on its arc table.  The
- * table lists, for every (image brick, transducer) pair, the quadrature rings
- * that hold points of the brick and the exact index range of those points on
- * each ring; with it oat_project and oat_backproject skip their per-ring
- * bound computations and evaluate no points outside the brick.  It is built
- * on the device at plan creation (two passes as costly as one oat_project)
- * and takes about 4 bytes per (brick, transducer, ring) triple: 15 GB for a
- * 256^3 image at 2048 transducers and 1024 samples.  Results are identical
- * with or without it up to FP32 summation order.
- *   -1  automatic: build it if it fits in 40% of the device memory free at
- *       plan creation (the default of oat_plan_create);
- *    0  never build it;
- *  > 0  build it if it fits in this many bytes.
- * Without a table, or when the geometry has rings of more than 65535 points
- * or shells of more than 65535 rings, the kernels bound the arcs themselves.
+/* Plan options for oat_plan_create_ex.  The kernels of oat_project and
+ * oat_backproject enumerate, for every (image brick, transducer) pair, the
+ * quadrature points of Eq. (dis_srt) whose trilinear cell lies in the brick.
+ * A plan can record that enumeration once, in one of two tables; results
+ * are the same on every path up to FP32 summation order in oat_project and
+ * bit for bit in oat_backproject.
  *
  * segment_table_bytes: device memory the plan may spend on its segment
- * table, built from the arc table (so only when that exists).  It lists, for
- * every (image brick, transducer) pair, the ring segments (runs of at most 32
- * consecutive points) that hold the brick's points, 8 bytes each: 40 GB for
- * the 256^3 case above.  With it the kernels stream a pair's segments
- * directly instead of expanding shells into rings and rings into segments
- * (about a quarter less work per point).  Once it is built the plan frees
- * the arc table.  Same values as arc_table_bytes; the automatic budget is 40%
- * of the device memory free after the arc table is built, and must hold both
- * tables while the segment table is filled.  Results are identical with or
- * without it up to FP32 summation order (bit for bit in oat_backproject). */
+ * table: for every pair, the ring segments (runs of at most 32 consecutive
+ * points) that hold the brick's points, 4 bytes each, ordered by point
+ * count; about 20 GB for a 256^3 image at 2048 transducers and 1024
+ * samples, 80 GB at 8192 transducers.  With it the kernels take one segment
+ * per lane and skip every bound computation.  It is built on the device at
+ * plan creation by two passes of the kernels' own bounds walk (each about as
+ * costly as one oat_project without a table), and is not built when a
+ * segment does not fit its 4-byte entry (more than 63 candidate rings per
+ * shell or 256 segments per ring, far beyond the workloads above).
+ *
+ * arc_table_bytes: device memory the plan may spend on its arc table, built
+ * only when the plan has no segment table: for every pair, the rings that
+ * hold points of the brick and the exact index range of those points on
+ * each ring, about 4 bytes per (brick, transducer, ring) triple (15 GB for
+ * the 256^3 case above); the kernels then skip the per-ring bound
+ * computations.  Without either table, or when the geometry has rings of
+ * more than 65535 points or shells of more than 65535 rings, the kernels
+ * bound the arcs themselves.
+ *
+ * Values of both fields:
+ *   -1  automatic: build the table if it fits in 40% of the device memory
+ *       free at that point of plan creation (the default of oat_plan_create);
+ *    0  never build it;
+ *  > 0  build it if it fits in this many bytes. */
 typedef struct {
     int64_t arc_table_bytes;
     int64_t segment_table_bytes;
@@ -258,8 +261,8 @@ const char *oat_last_error(void);
  * stats[1] = number of image bricks, stats[2] = brick edge (cells),
  * stats[3] = shell window per (brick, transducer),
  * stats[4] = bytes of device workspace, stats[5] = bytes of device tables,
- * stats[6] = bytes of the arc table (0: none built; the plan frees it again
- * when it builds the segment table), stats[7] = its ring entries,
+ * stats[6] = bytes of the arc table (0: none built, which is the case
+ * whenever the plan has a segment table), stats[7] = its ring entries,
  * stats[8] = its build time in microseconds,
  * stats[9] = time of the G^T calibration pass in microseconds (the plan runs
  * G^T's walk once with unit data to bound its fixed-point sums),

@@ -82,14 +82,36 @@ struct alignas(16) ShellRec {
 struct alignas(16) RingRec {
     double rc;         // rho cos(theta_i) / dx
     double rs;         // rho sin(theta_i) / dx
-    double inv_nj;     // 1 / nj
     float rsf;         // rs rounded to FP32 (arc bounds)
     int32_t nj;        // points on the ring
     float w;           // band area / nj  (mm^2)
     float delta;       // 2 pi / nj
     int32_t lshift;    // ring segments hold 2^lshift consecutive points
-    int32_t pad;
+    int32_t sref;      // first entry of this ring size in Problem::segref
 };
+
+// Ring segments: segment s of a ring of nj points holds the indices
+// s 2^lshift .. min((s+1) 2^lshift, nj) - 1; its reference index is the
+// middle one (the lower of the two for an even count).
+__host__ __device__ inline int seg_ref_index(int s, int lshift, int nj)
+{
+    const int sb = s << lshift;
+    const int se = sb + (1 << lshift) < nj ? sb + (1 << lshift) : nj;
+    return sb + ((se - sb - 1) >> 1);
+}
+
+// Compact segment-table entry (4 bytes; see Problem::seg).
+constexpr int SEG_SHELL_BITS = 8, SEG_RING_BITS = 6, SEG_INDEX_BITS = 8;
+constexpr int SEG_OFF_BITS = 5, SEG_CNT_BITS = 5;
+static_assert(SEG_SHELL_BITS + SEG_RING_BITS + SEG_INDEX_BITS + SEG_OFF_BITS + SEG_CNT_BITS == 32,
+              "one 32-bit word per segment");
+__host__ __device__ inline unsigned seg_pack(int shell, int ring, int index, int off, int cnt)
+{
+    return (unsigned)shell | ((unsigned)ring << SEG_SHELL_BITS) |
+           ((unsigned)index << (SEG_SHELL_BITS + SEG_RING_BITS)) |
+           ((unsigned)off << (SEG_SHELL_BITS + SEG_RING_BITS + SEG_INDEX_BITS)) |
+           ((unsigned)(cnt - 1) << (32 - SEG_CNT_BITS));
+}
 
 // Everything a kernel needs about the problem (passed by value).
 struct Problem {
@@ -128,14 +150,27 @@ struct Problem {
     unsigned *tab_run;
     unsigned *tab_arc;
     int *tab_cnt;
+    // segref[sref(nj) + s] = (cos, sin) in FP64 of the reference azimuth
+    // 2 pi seg_ref_index(s) / nj of segment s of any ring of nj points.
+    const double2 *segref;
+    int n_rings, n_segref;  // entries of ring and segref (index clamps)
     // Segment table (null when the plan has none): the segments of unit u
-    // are entries seg_off[u] .. seg_off[u+1]-1, two words each: the ring's
-    // global index, and jb | npts << 16 | (k - klo(u)) << 22 (first point
-    // index, points, shell offset), in the order of the arc-table walk.
-    // seg_cnt[u] = segments of unit u (written by the count pass).
+    // that hold points owned by the brick are entries seg_off[u] ..
+    // seg_off[u+1]-1, one 32-bit word each (seg_pack): the shell offset
+    // k - klo(u), the ring index relative to the first candidate ring of
+    // that shell (shell_rings), the segment index, the first owned point's
+    // offset in the segment and the count of points from it to the last
+    // owned one.  A unit's entries are ordered by decreasing count (walk
+    // order within a count), so a window of 64 has nearly equal counts.
+    // Written by two passes of the bounds walk: seg_cnt[u] and
+    // seg_hist[u * 32 + count - 1] (count pass), then the entries (fill
+    // pass, from seg_off and seg_hist); seg_flag is set when a segment does
+    // not fit the entry's fields (the plan then keeps no table).
     const long long *seg_off;
     unsigned *seg;
     int *seg_cnt;
+    int *seg_hist;
+    int *seg_flag;
 };
 
 // Sets the thread-local text returned by oat_last_error (defined with the
@@ -146,8 +181,9 @@ void set_last_error(const char *msg);
 hipError_t launch_srt_fwd(const Problem &P, const void *img, int img_dtype, float *part,
                           int *klo, hipStream_t s);
 // Table passes: mode 0 writes tab_run and tab_cnt (tab_run zeroed
-// beforehand), 1 writes tab_arc (tab_off set); with the arc table in place,
-// 2 writes seg_cnt and 3 writes seg (seg_off set).
+// beforehand), 1 writes tab_arc (tab_off set); 2 writes seg_cnt and
+// seg_hist and 3 writes seg (seg_off and seg_hist set), both over the
+// bounds walk (no arc table needed).
 hipError_t launch_arc_build(const Problem &P, int mode, hipStream_t s);
 hipError_t launch_srt_reduce(const Problem &P, const float *part, const int *klo,
                              void *out, int out_dtype, int apply_d, hipStream_t s);

@@ -69,6 +69,7 @@ struct oat_plan {
     float *d_rowmax = nullptr;   // [Q] max reachable |D^T y| per transducer
     float *d_adjr = nullptr;     // [bricks][windows] G^T calibration
     double *d_fbp_thr = nullptr; // [K + 2] FBP floor thresholds (Problem::fbp_thr)
+    double2 *d_segref = nullptr; // segment reference azimuths (Problem::segref)
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
@@ -182,13 +183,17 @@ int build_arc_table(oat_plan *plan, int64_t budget)
     return OAT_OK;
 }
 
-// Segment table from the arc table: a count pass (segments per unit), the
-// host prefix sum, a fill pass that writes each unit's segments in walk
-// order.  Skipped (OAT_OK, no table) when it does not fit the budget; on
-// success the arc table is freed.
+// Segment table, built over the bounds walk (no arc table needed): a count
+// pass (segments per unit and per point count, and a flag for segments that
+// do not fit the compact entry), the host prefix sum, a fill pass that
+// writes each unit's entries ordered by decreasing count.  Skipped (OAT_OK,
+// no table) when it does not fit the budget (< 0: 40% of the device memory
+// free now) or when a segment does not fit its entry; a failing launch fails
+// the plan.
 int build_seg_table(oat_plan *plan, int64_t budget)
 {
     Problem &P = plan->P;
+    if (plan->max_nj > 65535 || plan->max_rings > 65535) return OAT_OK;
     if (budget < 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) return OAT_OK;
@@ -197,32 +202,44 @@ int build_seg_table(oat_plan *plan, int64_t budget)
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t units = (int64_t)P.nbx * P.nby * P.nbz * P.nq;
     const size_t cnt_b = sizeof(int) * (size_t)units;
+    const size_t hist_b = sizeof(int) * 32 * (size_t)units;
     const size_t off_b = sizeof(long long) * (size_t)(units + 1);
-    if ((int64_t)(cnt_b + off_b) > budget) return OAT_OK;
-    int *cnt = nullptr;
+    if ((int64_t)(cnt_b + hist_b + off_b) > budget) return OAT_OK;
+    int *cnt = nullptr, *hist = nullptr, *flag = nullptr;
     long long *off = nullptr;
     unsigned *seg = nullptr;
     auto release = [&]() {
-        if (cnt) (void)hipFree(cnt);
-        if (off) (void)hipFree(off);
-        if (seg) (void)hipFree(seg);
-        cnt = nullptr;
+        for (void *b : {(void *)cnt, (void *)hist, (void *)flag, (void *)off, (void *)seg})
+            if (b) (void)hipFree(b);
+        cnt = hist = flag = nullptr;
         off = nullptr;
         seg = nullptr;
     };
-    if (hipMalloc((void **)&cnt, cnt_b) != hipSuccess) {
+    if (hipMalloc((void **)&cnt, cnt_b) != hipSuccess ||
+        hipMalloc((void **)&hist, hist_b) != hipSuccess ||
+        hipMalloc((void **)&flag, sizeof(int)) != hipSuccess) {
+        release();
         (void)hipGetLastError();
         return OAT_OK;
     }
     Problem Pc = P;
     Pc.seg_cnt = cnt;
-    hipError_t e = launch_arc_build(Pc, 2, nullptr);
+    Pc.seg_hist = hist;
+    Pc.seg_flag = flag;
+    hipError_t e = hipMemset(flag, 0, sizeof(int));
+    if (e == hipSuccess) e = launch_arc_build(Pc, 2, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     std::vector<int> hcnt(units);
+    int hflag = 0;
     if (e == hipSuccess) e = hipMemcpy(hcnt.data(), cnt, cnt_b, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
         release();
         return fail_hip(e, "oat_plan_create: segment table count pass");
+    }
+    if (hflag != 0) {   // a segment does not fit the compact entry
+        release();
+        return OAT_OK;
     }
     std::vector<long long> hoff(units + 1);
     long long total = 0;
@@ -233,8 +250,8 @@ int build_seg_table(oat_plan *plan, int64_t budget)
     hoff[units] = total;
     (void)hipFree(cnt);
     cnt = nullptr;
-    const size_t seg_b = 2 * sizeof(unsigned) * (size_t)(total > 0 ? total : 1);
-    if ((int64_t)(seg_b + off_b) > budget || hipMalloc((void **)&off, off_b) != hipSuccess ||
+    const size_t seg_b = sizeof(unsigned) * (size_t)(total > 0 ? total : 1);
+    if ((int64_t)(seg_b + hist_b + off_b) > budget || hipMalloc((void **)&off, off_b) != hipSuccess ||
         hipMalloc((void **)&seg, seg_b) != hipSuccess) {
         release();
         (void)hipGetLastError();
@@ -250,21 +267,16 @@ int build_seg_table(oat_plan *plan, int64_t budget)
         release();
         return fail_hip(e, "oat_plan_create: segment table fill pass");
     }
-    // The kernels now read the segment table; the arc table is not needed.
-    (void)hipFree(plan->d_tab_run);
-    (void)hipFree(plan->d_tab_off);
-    (void)hipFree(plan->d_tab_arc);
-    plan->d_tab_run = nullptr;
-    plan->d_tab_off = nullptr;
-    plan->d_tab_arc = nullptr;
-    P.tab_run = nullptr;
-    P.tab_off = nullptr;
-    P.tab_arc = nullptr;
+    (void)hipFree(hist);
+    (void)hipFree(flag);
+    hist = flag = nullptr;
     plan->d_seg_off = off;
     plan->d_seg = seg;
     P.seg_off = off;
     P.seg = seg;
     P.seg_cnt = nullptr;
+    P.seg_hist = nullptr;
+    P.seg_flag = nullptr;
     plan->seg_bytes = (int64_t)(seg_b + off_b);
     plan->seg_entries = total;
     plan->seg_build_us = (int64_t)std::chrono::duration_cast<std::chrono::microseconds>(
@@ -290,7 +302,8 @@ void oat_plan_destroy(oat_plan *plan)
                     plan->d_klo, plan->d_gp, plan->d_acc, plan->d_rowmax, plan->d_adjr,
                     plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
                     plan->d_seg, plan->d_eir_h, plan->d_eir_spec, plan->d_eir_tw,
-                    plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part, plan->d_fbp_thr};
+                    plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part, plan->d_fbp_thr,
+                    plan->d_segref};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -414,19 +427,50 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
             RingRec rr;
             rr.rc = rho * std::cos(th) / dx;
             rr.rs = rho * std::sin(th) / dx;
-            rr.inv_nj = 1.0 / (double)nj;
             rr.rsf = (float)rr.rs;
             rr.nj = (int32_t)nj;
             rr.w = (float)(area / (double)nj);
             rr.delta = (float)(2.0 * M_PI / (double)nj);
             rr.lshift = seg_shift((int)nj);
-            rr.pad = 0;
+            rr.sref = 0;   // set below, once every ring size is known
             if (nj > max_nj) max_nj = (int)nj;
             if (rr.w > w_max) w_max = rr.w;
             ring.push_back(rr);
         }
     }
-    if (ring.empty()) ring.push_back(RingRec{0.0, 0.0, 1.0, 0.f, 1, 0.f, 0.f, 0, 0});
+    if (ring.empty()) ring.push_back(RingRec{0.0, 0.0, 0.f, 1, 0.f, 0.f, 0, 0});
+    if (max_nj < 1) max_nj = 1;
+    // Segment reference azimuths in FP64 per ring size: every segment of
+    // every ring of nj points starts from (cos, sin) of 2 pi jref / nj, so
+    // the kernels evaluate no FP64 sine.  The reduction to [0, 1/8] turn is
+    // exact in integers; the octant's sine and cosine come from long double.
+    std::vector<int32_t> sref_of(max_nj + 1, 0);
+    std::vector<double2> segref;
+    for (int nj = 1; nj <= max_nj; ++nj) {
+        sref_of[nj] = (int32_t)segref.size();
+        const int ls = seg_shift(nj), nseg = (nj + (1 << ls) - 1) >> ls;
+        for (int sg = 0; sg < nseg; ++sg) {
+            const int64_t j = seg_ref_index(sg, ls, nj);
+            // 2 pi j / nj = (pi/4) (m + r) with m = floor(8 j / nj) and r in [0, 1)
+            const int64_t m = (8 * j) / nj, rn = 8 * j - m * nj;   // r = rn / nj
+            const long double qa = (long double)M_PI / 4.0L;
+            // angle within the octant, measured from the octant's even edge
+            const bool odd = (m & 1) != 0;
+            const long double a = qa * (long double)(odd ? nj - rn : rn) / (long double)nj;
+            long double c = std::cos(a), sn = std::sin(a);
+            // octant m spans [m pi/4, (m+1) pi/4]; odd octants measure from
+            // the upper edge, so reflect about the diagonal first
+            long double cc = odd ? sn : c, ss = odd ? c : sn;
+            // rotate by the quarter turns m / 2
+            for (int t = 0; t < (int)(m / 2); ++t) {
+                const long double tc = -ss;
+                ss = cc;
+                cc = tc;
+            }
+            segref.push_back(make_double2((double)cc, (double)ss));
+        }
+    }
+    for (RingRec &rr : ring) rr.sref = sref_of[rr.nj];
 
     oat_plan *plan = new (std::nothrow) oat_plan();
     if (!plan) return fail(OAT_ERR_NOMEM, "host allocation failed");
@@ -515,6 +559,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     size_t adjr_b = sizeof(float) * (size_t)nbricks * adj_windows(Q);
     const std::vector<double> fbp_thr = fbp_floor_thresholds(g->c0, g->t0, g->dt, K);
     size_t thr_b = sizeof(double) * fbp_thr.size();
+    size_t segref_b = sizeof(double2) * segref.size();
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
@@ -524,7 +569,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = alloc((void **)&plan->d_acc, acc_b, "brick node sums")) != hipSuccess ||
         (e = alloc((void **)&plan->d_rowmax, rowmax_b, "gp row max")) != hipSuccess ||
         (e = alloc((void **)&plan->d_adjr, adjr_b, "G^T calibration")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_fbp_thr, thr_b, "FBP floor thresholds")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_fbp_thr, thr_b, "FBP floor thresholds")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_segref, segref_b, "segment references")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -534,6 +580,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = hipMemcpy(plan->d_shell, shell.data(), sh_b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(plan->d_ring, ring.data(), ring_b, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(plan->d_fbp_thr, fbp_thr.data(), thr_b, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(plan->d_segref, segref.data(), segref_b, hipMemcpyHostToDevice)) !=
             hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMemcpy");
         oat_plan_destroy(plan);
@@ -545,6 +593,9 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.ring = plan->d_ring;
     P.gp_rowmax = plan->d_rowmax;
     P.fbp_thr = plan->d_fbp_thr;
+    P.segref = plan->d_segref;
+    P.n_rings = (int)ring.size();
+    P.n_segref = (int)segref.size();
     P.adj_r = nullptr;
     P.tab_off = nullptr;
     P.tab_run = nullptr;
@@ -553,12 +604,17 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.seg_off = nullptr;
     P.seg = nullptr;
     P.seg_cnt = nullptr;
+    P.seg_hist = nullptr;
+    P.seg_flag = nullptr;
     plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + acc_b + rowmax_b);
-    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b + thr_b);
-    if (table_budget != 0) {
-        int code = build_arc_table(plan, table_budget);
-        if (code == OAT_OK && seg_budget != 0 && plan->d_tab_arc)
-            code = build_seg_table(plan, seg_budget);
+    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b + thr_b + segref_b);
+    {
+        // The segment table if it fits, else the arc table if that fits,
+        // else neither (the kernels then bound the arcs themselves).
+        int code = OAT_OK;
+        if (seg_budget != 0) code = build_seg_table(plan, seg_budget);
+        if (code == OAT_OK && !plan->d_seg && table_budget != 0)
+            code = build_arc_table(plan, table_budget);
         if (code != OAT_OK) {
             oat_plan_destroy(plan);
             (void)hipSetDevice(prev);

@@ -220,49 +220,94 @@ enum TableMode {
 struct BuildLds {
     int rmin[64], rmax[64];
     int smin[64], smax[64];
+    int hist[32];    // segment passes: the unit's segments per point count
 };
 
+// Reference point of a ring segment.  cs = (cos, sin) in FP64 of the
+// segment's reference azimuth (Problem::segref).  The point, formed in FP64,
+// is split into an integer cell relative to the box (clamped; clamped
+// offsets only occur for points far outside the box) and an FP32 fraction
+// Pl; (xa, xb) = rs (cos, sin) are its in-plane coordinates.
+__device__ __forceinline__ void seg_ref(const double uq[3], const double e3[3],
+                                        const double e1d[3], const double e2d[3],
+                                        const int lo[3], double rc, double rs, double2 cs,
+                                        float Pl[3], int dc[3], float &xa, float &xb)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double pa = fma(rc, e3[a], uq[a]) + rs * fma(cs.x, e1d[a], cs.y * e2d[a]);
+        const double ph = floor(pa);
+        Pl[a] = (float)(pa - ph);
+        dc[a] = min(max((int)ph - lo[a], -512), 511);
+    }
+    xa = (float)(rs * cs.x);
+    xb = (float)(rs * cs.y);
+}
+
+// Point j of a segment, dj = j - jref, relative to the segment's reference
+// point: ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
+// b = xb (cos d - 1) + xa sin d, d = dj 2 pi / nj (dd = 2 pi / nj).  The
+// fraction stays within a few tens of cells, so positions carry ~1e-6 cell
+// of FP32 error, and every brick evaluates the same FP32 operations, so each
+// point belongs to exactly one brick.  own: its cell lies in the brick.
+__device__ __forceinline__ Pt seg_point(const float Pl[3], const int dc[3], float qa, float qb,
+                                        float dd, int dj, const float e1[3], const float e2[3],
+                                        const int lo[3], const int hi[3])
+{
+    float cm1, sn;
+    small_rot((float)dj * dd, cm1, sn);
+    const float al = fmaf(qa, cm1, -(qb * sn));
+    const float be = fmaf(qb, cm1, qa * sn);
+    const float ux = fmaf(be, e2[0], fmaf(al, e1[0], Pl[0]));
+    const float uy = fmaf(be, e2[1], fmaf(al, e1[1], Pl[1]));
+    const float uz = fmaf(be, e2[2], fmaf(al, e1[2], Pl[2]));
+    Pt t;
+    t.cx = cvt_floor(ux) + dc[0];
+    t.cy = cvt_floor(uy) + dc[1];
+    t.cz = cvt_floor(uz) + dc[2];
+    t.fx = __builtin_amdgcn_fractf(ux);
+    t.fy = __builtin_amdgcn_fractf(uy);
+    t.fz = __builtin_amdgcn_fractf(uz);
+    t.own = (unsigned)t.cx < (unsigned)(hi[0] - lo[0]) &&
+            (unsigned)t.cy < (unsigned)(hi[1] - lo[1]) &&
+            (unsigned)t.cz < (unsigned)(hi[2] - lo[2]);
+    return t;
+}
+
 // One window of up to 64 segments, one per lane (v2 = the lane holds one):
-// ring (rc, rs, 1/nj, nj, delta, segment shift ls), shell k2, its weight w2
-// (w g' 2^s in G^T), points jb .. jb+npts-1 of segment jb >> ls.  Stages the
-// segments' data and walks their points two per lane (level 3).  ub and rl
-// are the arc-table passes' offset of jb in the ring's arc and the ring's
-// level-1 lane.
+// ring (rc, rs, reference table offset sref, delta, nj, segment shift ls),
+// shell k2, its weight w2 (w g' 2^s in G^T), points jb .. jb+npts-1 of
+// segment jb >> ls.  Stages the segments' data and walks their points two
+// per lane (level 3).  ub and rl are the arc-table passes' offset of jb in
+// the ring's arc and the ring's level-1 lane.  The segment-table passes
+// (unit, rrel = ring index relative to the shell's first candidate ring,
+// scount = the unit's segments so far) record each segment's owned index
+// range and count or write its compact entry.
 template <int MODE, class Fn>
 __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, BuildLds *B,
                                                const int lo[3], const int hi[3],
                                                const double uq[3], const double e3[3],
                                                const double e1d[3], const double e2d[3],
                                                const float e1[3], const float e2[3], bool v2,
-                                               double rc2, double rs2, double in2, float w2,
+                                               double rc2, double rs2, int sref2, float w2,
                                                float dl2, int nj2, int ls2, int k2, int jb,
-                                               int npts, int ub, int rl, int klo, Fn &&fn)
+                                               int npts, int ub, int rl, int klo, size_t unit,
+                                               int rrel, long long &scount, Fn &&fn)
 {
+    constexpr bool SEGB = MODE == WALK_SEGCOUNT || MODE == WALK_SEGFILL;
     const int lane = lane_id();
     Level L3{W.bits3, W.prod3, 0, 0};
-    const int sb = (jb >> ls2) << ls2, se = min(sb + (1 << ls2), nj2);
-    const int jref = sb + ((se - sb - 1) >> 1);
-    // Reference point of the segment in FP64, split into an integer cell
-    // (relative to the box, packed 10 bits per axis) and an FP32 fraction,
-    // and its in-plane coordinates (xa, xb) = rs (cos, sin) of the reference
-    // azimuth: point j is ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
-    // b = xb (cos d - 1) + xa sin d, d = (j - jref) 2 pi / nj.
-    double cr, sr;
-    sincos_turns_d((double)jref * in2, cr, sr);
-    float Pl[3];
+    const int sg = jb >> ls2;
+    const int jref = seg_ref_index(sg, ls2, nj2);
+    float Pl[3], xa, xb;
     int dc[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double pa = fma(rc2, e3[a], uq[a]) + rs2 * fma(cr, e1d[a], sr * e2d[a]);
-        const double ph = floor(pa);
-        Pl[a] = (float)(pa - ph);
-        // clamped offsets only occur for points far outside the box
-        dc[a] = min(max((int)ph - lo[a], -512), 511);
-    }
-    const float xa = (float)(rs2 * cr), xb = (float)(rs2 * sr);
+    seg_ref(uq, e3, e1d, e2d, lo, rc2, rs2, v2 ? P.segref[sref2 + sg] : make_double2(1.0, 0.0),
+            Pl, dc, xa, xb);
     const int np = v2 ? npts : 0;
     // jb - jref in [-16, 16], npts <= 32, shell index < 4096 (n_t <= 4096)
     const int meta = (jb - jref + 64) | (np << 7) | (k2 << 13);
+    // The segment-table passes key their owned ranges by the segment's lane.
+    const int tag = SEGB ? (lane | (jb << 8)) : (rl | (ub << 8));
     // The segment's data goes to the wave's LDS stage, where the lanes of its
     // points read it (a broadcast read; cheaper than one bpermute per value
     // on this part).  The cell offsets are stored unpacked: the point level
@@ -271,7 +316,11 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
     W.stage[lane][0] = make_float4(Pl[0], Pl[1], Pl[2], __int_as_float(meta));
     W.stage[lane][1] = make_float4(xa, xb, dl2, w2);
     W.stage[lane][2] = make_float4(__int_as_float(dc[0]), __int_as_float(dc[1]),
-                                   __int_as_float(dc[2]), __int_as_float(rl | (ub << 8)));
+                                   __int_as_float(dc[2]), __int_as_float(tag));
+    if (SEGB) {
+        B->rmin[lane] = 0x7fffffff;
+        B->rmax[lane] = -1;
+    }
     // Level 3: each lane takes two consecutive points of a segment
     // (level_begin orders the stage writes before the reads).
     level_begin<5>(L3, (np + 1) >> 1);
@@ -279,10 +328,10 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
         int s3, pr;
         const bool v3 = level_item(L3, F3, s3, pr);
         const float4 r0 = W.stage[s3][0], r1 = W.stage[s3][1], r2 = W.stage[s3][2];
-        const float p0 = r0.x, p1 = r0.y, p2 = r0.z;
+        const float p3[3] = {r0.x, r0.y, r0.z};
         const int mt = __float_as_int(r0.w);
         const float qa = r1.x, qb = r1.y, dd = r1.z, wv = r1.w;
-        const int d0 = __float_as_int(r2.x), d1 = __float_as_int(r2.y), d2 = __float_as_int(r2.z);
+        const int d3[3] = {__float_as_int(r2.x), __float_as_int(r2.y), __float_as_int(r2.z)};
         int rlp = 0, ur = 0;
         if (MODE != WALK_POINTS) {
             const int ru = __float_as_int(r2.w);
@@ -294,25 +343,8 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
         Pt pt[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            float cm1, sn;
-            small_rot((float)(djA + h) * dd, cm1, sn);
-            const float al = fmaf(qa, cm1, -(qb * sn));
-            const float be = fmaf(qb, cm1, qa * sn);
-            // Fractional coordinates about the reference cell: the same FP32
-            // operations in every brick, so ownership is exact.
-            const float ux = fmaf(be, e2[0], fmaf(al, e1[0], p0));
-            const float uy = fmaf(be, e2[1], fmaf(al, e1[1], p1));
-            const float uz = fmaf(be, e2[2], fmaf(al, e1[2], p2));
-            Pt &t = pt[h];
-            t.cx = cvt_floor(ux) + d0;
-            t.cy = cvt_floor(uy) + d1;
-            t.cz = cvt_floor(uz) + d2;
-            t.fx = __builtin_amdgcn_fractf(ux);
-            t.fy = __builtin_amdgcn_fractf(uy);
-            t.fz = __builtin_amdgcn_fractf(uz);
-            t.own = v3 && 2 * pr + h < npp && (unsigned)t.cx < (unsigned)(hi[0] - lo[0]) &&
-                    (unsigned)t.cy < (unsigned)(hi[1] - lo[1]) &&
-                    (unsigned)t.cz < (unsigned)(hi[2] - lo[2]);
+            pt[h] = seg_point(p3, d3, qa, qb, dd, djA + h, e1, e2, lo, hi);
+            pt[h].own = pt[h].own && v3 && 2 * pr + h < npp;
         }
         if (MODE == WALK_POINTS) {
             fn(pt[0], pt[1], wv, kk, klo);
@@ -325,22 +357,109 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
                 }
         }
     }
+    if constexpr (SEGB) {
+        // The segment's owned points span jmin .. jmax (a superset of them
+        // when the brick cuts the segment twice; the kernels test each).
+        wave_sync();
+        const int jmin = B->rmin[lane], jmax = B->rmax[lane];
+        const bool has = v2 && jmax >= 0;
+        const int koff = k2 - klo, cnt = jmax - jmin + 1;
+        const int off = jmin - (sg << ls2);
+        if (has && (rrel < 0 || rrel >= (1 << SEG_RING_BITS) || koff < 0 ||
+                    koff >= (1 << SEG_SHELL_BITS) || sg >= (1 << SEG_INDEX_BITS) || off < 0 ||
+                    cnt > 32))
+            atomicOr(P.seg_flag, 1);
+        const uint64_t bal = __ballot(has);
+        if (MODE == WALK_SEGCOUNT) {
+            if (has) atomicAdd(&B->hist[cnt - 1], 1);
+        } else {
+            // Entries of equal count keep walk order: per count present in
+            // this window, the lanes holding it take consecutive places
+            // after the count's earlier entries (B->hist holds each count's
+            // next place, counts in decreasing order).
+            uint64_t pend = bal;
+            while (pend) {
+                const int first = __ffsll((long long)pend) - 1;
+                const int c = __shfl(cnt, first);
+                const uint64_t m = __ballot(has && cnt == c);
+                const int base = B->hist[c - 1];
+                if (has && cnt == c) {
+                    const long long pos = P.seg_off[unit] + base + __popcll(m & mask_below());
+                    // the count pass saw the same segments; the guard only
+                    // keeps a mismatch inside the unit's range
+                    if (pos < P.seg_off[unit + 1])
+                        P.seg[pos] = seg_pack(koff, rrel, sg, off, cnt);
+                }
+                wave_sync();
+                if (lane == first) B->hist[c - 1] = base + __popcll(m);
+                wave_sync();
+                pend &= ~m;
+            }
+        }
+        scount += __popcll(bal);
+        wave_sync();
+    }
+}
+
+// Shells klo .. khi of the transducer at uq (grid units) that can reach the
+// cell box [lo, hi) (at most the plan's window of them; klo > khi: none).
+__device__ __forceinline__ void unit_shells(const Problem &P, const double uq[3], const int lo[3],
+                                            const int hi[3], int &klo, int &khi)
+{
+    float dmin2 = 0.f, dmax2 = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        float u = (float)uq[a];
+        float dl = (float)lo[a] - u, dh = u - (float)hi[a];
+        float dm = fmaxf(fmaxf(dl, dh), 0.f);
+        dmin2 += dm * dm;
+        float e = fmaxf(fabsf(u - (float)lo[a]), fabsf(u - (float)hi[a]));
+        dmax2 += e * e;
+    }
+    float dmin = sqrtf(dmin2) - 0.1f, dmax = sqrtf(dmax2) + 0.1f;
+    klo = max(0, (int)ceilf((dmin - P.rho0) / P.rho_step));
+    khi = min(P.nt - 1, (int)floorf((dmax - P.rho0) / P.rho_step));
+    khi = min(khi, klo + P.window - 1);
+}
+
+// Candidate rings i0 .. i0+cnt-1 of shell sh that can reach the ball that
+// holds the box (D = distance of its centre from the transducer, thb = the
+// centre's polar angle in the transducer frame, h2 = squared radius); a
+// superset of the rings with points in the box.  cnt = 0: none.
+__device__ __forceinline__ void shell_rings(const ShellRec &sh, float D, float thb, float h2,
+                                            int &i0, int &cnt)
+{
+    i0 = 0;
+    cnt = 0;
+    if (sh.n_rings <= 0) return;
+    const float rho = sh.rho;
+    const float om = (h2 - (rho - D) * (rho - D)) * rcp_approx(2.f * rho * D);   // 1 - cos(delta)
+    if (!(om > 0.f)) return;
+    const float delta = om >= 2.f ? kPi : acos_approx(1.f - om);
+    const float tlo = (thb - delta) * rho - 0.5f;
+    const float thi = (thb + delta) * rho - 0.5f;
+    const int a = max(0, (int)floorf(tlo) - 2);
+    const int b = min(sh.n_rings - 1, (int)ceilf(thi) + 2);
+    if (b >= a) {
+        i0 = a;
+        cnt = b - a + 1;
+    }
 }
 
 // Walk all points of transducer q owned by the brick (unit = brick * nq + q).
-// The rings and arcs come from the ball/slab bounds (TM_BOUNDS), the plan's
-// arc table (TM_ARC: tight arcs of exactly the rings that hold owned points)
-// or its segment table (TM_SEG: those arcs' segments, listed per unit in the
-// order of the arc-table walk); all three give the same owned points.  In
-// WALK_POINTS mode fn is called per window of 64 lanes with the lane's two
-// consecutive points of one segment (Pt each), their weight, their shell
-// index and the unit's first shell.
+// The rings and arcs come from the ball/slab bounds (TM_BOUNDS) or the
+// plan's arc table (TM_ARC: tight arcs of exactly the rings that hold owned
+// points); both give the same owned points (and so does walk_seg, the
+// segment-table walk).  In WALK_POINTS mode fn is called per window of 64
+// lanes with the lane's two consecutive points of one segment (Pt each),
+// their weight, their shell index and the unit's first shell.  The
+// segment-table passes (bounds walk) count or write the unit's segments.
 template <bool ADJ, int TM, int MODE, class WL, class Fn>
 __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, const int lo[3],
                                           const int hi[3], WL &W, BuildLds *B,
                                           const float *gp, float gscale, float gscale2,
                                           int &klo_out, Fn &&fn)
 {
+    static_assert(TM != TM_SEG, "the segment table is walked by walk_seg");
     constexpr bool TAB = TM == TM_ARC;
     constexpr bool READ_RUNS = TAB || MODE == WALK_FILL;
     constexpr bool SEGB = MODE == WALK_SEGCOUNT || MODE == WALK_SEGFILL;
@@ -352,44 +471,22 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
     const float e1[3] = {d.e1[0], d.e1[1], d.e1[2]};
     const float e2[3] = {d.e2[0], d.e2[1], d.e2[2]};
 
-    // Shells that can reach the box.
-    float dmin2 = 0.f, dmax2 = 0.f;
-    for (int a = 0; a < 3; ++a) {
-        float u = (float)uq[a];
-        float dl = (float)lo[a] - u, dh = u - (float)hi[a];
-        float dm = fmaxf(fmaxf(dl, dh), 0.f);
-        dmin2 += dm * dm;
-        float e = fmaxf(fabsf(u - (float)lo[a]), fabsf(u - (float)hi[a]));
-        dmax2 += e * e;
-    }
-    float dmin = sqrtf(dmin2) - 0.1f, dmax = sqrtf(dmax2) + 0.1f;
-    int klo = max(0, (int)ceilf((dmin - P.rho0) / P.rho_step));
-    int khi = min(P.nt - 1, (int)floorf((dmax - P.rho0) / P.rho_step));
-    khi = min(khi, klo + P.window - 1);
+    int klo, khi;
+    unit_shells(P, uq, lo, hi, klo, khi);
     klo_out = klo;
     const int lane = lane_id();
 
-    if constexpr (TM == TM_SEG) {
-        // 64 segment entries per window: (ring, jb | npts << 16 | (k - klo) << 22).
-        const long long s0 = P.seg_off[unit], s1 = P.seg_off[unit + 1];
-        const uint2 *seg = reinterpret_cast<const uint2 *>(P.seg);
-        // The next window's entries are loaded while this window runs.
-        uint2 nxt = s0 + lane < s1 ? seg[s0 + lane] : make_uint2(0u, 0u);
-        for (long long c = s0; c < s1; c += WAVE) {
-            const bool v2 = c + lane < s1;
-            const uint2 ent = nxt;
-            const RingRec rr = P.ring[ent.x];
-            const long long en = c + WAVE + lane;
-            nxt = en < s1 ? seg[en] : make_uint2(0u, 0u);
-            const int jb = (int)(ent.y & 0xffffu), npts = (int)((ent.y >> 16) & 63u);
-            const int k2 = klo + (int)(ent.y >> 22);
-            float w2 = rr.w;
-            if (ADJ && v2) w2 = w2 * ((gp[(size_t)q * P.nt + k2] * gscale) * gscale2);
-            segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rr.rc, rr.rs,
-                                 rr.inv_nj, w2, rr.delta, rr.nj, rr.lshift, k2, jb, npts, 0, 0,
-                                 klo, fn);
-        }
-    } else {
+    if (SEGB) {
+        // Per point count: the count pass tallies the unit's segments; the
+        // fill pass starts each count's entries after those of all larger
+        // counts.
+        int h = 0;
+        if (MODE == WALK_SEGFILL && lane < 32) h = P.seg_hist[unit * 32 + (31 - lane)];
+        int tot;
+        const int before = excl_scan_wave<24>(lane < 32 ? h : 0, tot);
+        if (lane < 32) B->hist[31 - lane] = MODE == WALK_SEGFILL ? before : 0;
+        wave_sync();
+    }
     ArcUnit U;
     if (!TAB) arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
     const float D = TAB ? 0.f : sqrtf(U.rhov2 + U.V3 * U.V3);
@@ -426,23 +523,9 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 rbase = P.shell[k].ring_base;
             }
         } else if (k <= khi) {
-            ShellRec sh = P.shell[k];
-            if (sh.n_rings > 0) {
-                float rho = sh.rho;
-                float om = (h2 - (rho - D) * (rho - D)) * rcp_approx(2.f * rho * D);   // 1 - cos(delta)
-                if (om > 0.f) {
-                    float delta = om >= 2.f ? kPi : acos_approx(1.f - om);
-                    float tlo = (thb - delta) * rho - 0.5f;
-                    float thi = (thb + delta) * rho - 0.5f;
-                    int i0 = max(0, (int)floorf(tlo) - 2);
-                    int i1 = min(sh.n_rings - 1, (int)ceilf(thi) + 2);
-                    if (i1 >= i0) {
-                        cnt_all = i1 - i0 + 1;
-                        ilo_all = i0;
-                        rbase = sh.ring_base;
-                    }
-                }
-            }
+            const ShellRec sh = P.shell[k];
+            shell_rings(sh, D, thb, h2, ilo_all, cnt_all);
+            rbase = sh.ring_base;
         }
         if (MODE == WALK_COUNT) {
             B->smin[lane] = 0x7fffffff;
@@ -461,18 +544,20 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
             int kr = bperm_i(s1, k);
             int ir = bperm_i(s1, ilo) + loc1;
             int rb = bperm_i(s1, rbase);
+            // segment passes: ring index relative to the shell's first candidate
+            const int rrel1 = SEGB ? ir - bperm_i(s1, ilo_all) : 0;
             const int run_i0 = READ_RUNS ? bperm_i(s1, r_i0) : 0;
             const int run_n = READ_RUNS ? bperm_i(s1, r_n) : 0;
             const int run_ex = READ_RUNS ? bperm_i(s1, r_ex) : 0;
             // Ring (kr, ir): arc of indices that holds every owned point.
-            double rcd = 0.0, rsd = 0.0, invd = 1.0;
+            double rcd = 0.0, rsd = 0.0;
             float w = 0.f, dlt = 0.f;
-            int nj = 1, jlo = 0, jcnt = 0, ls = 0, n1 = 0, items_all = 0;
+            int nj = 1, jlo = 0, jcnt = 0, ls = 0, n1 = 0, items_all = 0, srf = 0;
             if (v1) {
                 const RingRec rr = P.ring[rb + ir];
                 rcd = rr.rc;
                 rsd = rr.rs;
-                invd = rr.inv_nj;
+                srf = rr.sref;
                 nj = rr.nj;
                 w = rr.w;
                 dlt = rr.delta;
@@ -505,7 +590,6 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 B->rmax[lane] = -1;
                 wave_sync();
             }
-            const int rg = rb + ir;
             for (int pass2 = 0; __ballot(items_all - pass2 * CAP2 > 0) != 0ull; ++pass2) {
             const int nitems = min(max(items_all - pass2 * CAP2, 0), CAP2);
             level_begin<5>(L2, nitems);
@@ -522,31 +606,14 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
                 const int jb = wrap ? sb : max(sb, jlo2);
                 const int je = min(se, wrap ? jlo2 + jc2 - nj2 : jlo2 + jc2);
                 const int npts = v2 ? max(je - jb, 0) : 0;
-                if (SEGB) {
-                    // Segment table passes: count, or write the unit's
-                    // entries in this order.
-                    const bool has = npts > 0;
-                    const uint64_t bal = __ballot(has);
-                    if (MODE == WALK_SEGFILL) {
-                        const int rg2 = bperm_i(s2, rg);
-                        const long long pos =
-                            P.seg_off[unit] + scount + __popcll(bal & mask_below());
-                        // the count pass saw the same segments; the guard
-                        // only keeps a mismatch inside the unit's range
-                        if (has && pos < P.seg_off[unit + 1]) {
-                            reinterpret_cast<uint2 *>(P.seg)[pos] = make_uint2(
-                                (unsigned)rg2, (unsigned)jb | ((unsigned)npts << 16) |
-                                                   ((unsigned)(k2 - klo) << 22));
-                        }
-                    }
-                    scount += __popcll(bal);
-                    continue;
-                }
-                const double rc2 = bperm_d(s2, rcd), rs2 = bperm_d(s2, rsd), in2 = bperm_d(s2, invd);
+                const double rc2 = bperm_d(s2, rcd), rs2 = bperm_d(s2, rsd);
+                const int sr2 = bperm_i(s2, srf);
                 const float w2 = bperm_f(s2, w), dl2 = bperm_f(s2, dlt);
+                const int rrel2 = SEGB ? bperm_i(s2, rrel1) : 0;
                 const int ub = wrap ? jb + nj2 - jlo2 : jb - jlo2;   // offset of jb in the arc
-                segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rc2, rs2, in2,
-                                     w2, dl2, nj2, ls2, k2, jb, npts, ub, s2, klo, fn);
+                segment_points<MODE>(P, W, B, lo, hi, uq, e3, e1d, e2d, e1, e2, v2, rc2, rs2, sr2,
+                                     w2, dl2, nj2, ls2, k2, jb, npts, ub, s2, klo, unit, rrel2,
+                                     scount, fn);
             }
             }  // pass2
             if (MODE == WALK_COUNT || MODE == WALK_FILL) {
@@ -584,8 +651,108 @@ __device__ __forceinline__ void walk_unit(const Problem &P, int q, size_t unit, 
         const float tot = wave_sum_dpp((float)ucount);
         if (lane == 0) P.tab_cnt[unit] = (int)tot;
     }
-    if (MODE == WALK_SEGCOUNT && lane == 0) P.seg_cnt[unit] = (int)scount;
-    }  // TM != TM_SEG
+    if (MODE == WALK_SEGCOUNT) {
+        if (lane == 0) P.seg_cnt[unit] = (int)scount;
+        if (lane < 32) P.seg_hist[unit * 32 + lane] = B->hist[lane];
+    }
+}
+
+// Per-wave LDS of the segment-table walk: the global index of each shell's
+// first candidate ring for the current unit.
+struct SegWave {
+    int gbase[WMAX];
+};
+
+// Maximum over the 64 lanes (all active), returned to every lane.
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    v = max(v, dpp_i<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+    v = max(v, dpp_i<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+    v = max(v, dpp_i<0x141, 0xF>(v));   // row_half_mirror
+    v = max(v, dpp_i<0x140, 0xF>(v));   // row_mirror: every lane holds its row maximum
+    v = max(v, __builtin_amdgcn_readlane(v, 16));
+    v = max(v, __builtin_amdgcn_readlane(v, 32));
+    v = max(v, __builtin_amdgcn_readlane(v, 48));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Walk the points of transducer q owned by the brick from the plan's segment
+// table: one segment per lane, 64 at a time, each lane taking its segment's
+// points one after the other (a window's segments have nearly equal counts:
+// the table orders a unit's segments by decreasing count).  The positions
+// are those of walk_unit's point level (seg_ref, seg_point), so the owned
+// point set is the same.  pfn(t, w) is called for every point of a segment
+// with its weight (w g' in G^T), then sfn(np, so, w) once per window with
+// the lane's segment count (0: none), shell offset and weight.
+template <bool ADJ, class PFn, class SFn>
+__device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, const int lo[3],
+                                         const int hi[3], SegWave &W, const float *gp,
+                                         float gscale, float gscale2, int &klo_out, PFn &&pfn,
+                                         SFn &&sfn)
+{
+    const DetRec &d = P.det[q];
+    const double uq[3] = {d.uq[0], d.uq[1], d.uq[2]};
+    const double e3[3] = {d.e3[0], d.e3[1], d.e3[2]};
+    const double e1d[3] = {d.e1d[0], d.e1d[1], d.e1d[2]};
+    const double e2d[3] = {d.e2d[0], d.e2d[1], d.e2d[2]};
+    const float e1[3] = {d.e1[0], d.e1[1], d.e1[2]};
+    const float e2[3] = {d.e2[0], d.e2[1], d.e2[2]};
+    int klo, khi;
+    unit_shells(P, uq, lo, hi, klo, khi);
+    klo_out = klo;
+    const int lane = lane_id();
+    const long long s0 = P.seg_off[unit], s1 = P.seg_off[unit + 1];
+    if (s0 >= s1) return;
+    // Each shell's first candidate ring, as the bounds walk found it when
+    // the table was built (the same FP32 operations).
+    {
+        ArcUnit U;
+        arc_unit_setup(U, lo, hi, uq, e1, e2, e3, 0.02f);
+        const float D = sqrtf(U.rhov2 + U.V3 * U.V3);
+        const float thb = acos_approx(U.V3 * rcp_approx(D));
+        for (int so = lane; so <= khi - klo; so += WAVE) {
+            const ShellRec sh = P.shell[klo + so];
+            int i0, cnt;
+            shell_rings(sh, D, thb, U.h2, i0, cnt);
+            W.gbase[so] = sh.ring_base + i0;
+        }
+        wave_sync();
+    }
+    // The next window's entries are loaded while this window runs.
+    unsigned nxt = s0 + lane < s1 ? P.seg[s0 + lane] : 0u;
+    for (long long c = s0; c < s1; c += WAVE) {
+        const bool v = c + lane < s1;
+        const unsigned ent = nxt;
+        const long long en = c + WAVE + lane;
+        nxt = en < s1 ? P.seg[en] : 0u;
+        const int so = (int)(ent & ((1u << SEG_SHELL_BITS) - 1u));
+        const int rrel = (int)((ent >> SEG_SHELL_BITS) & ((1u << SEG_RING_BITS) - 1u));
+        const int sg = (int)((ent >> (SEG_SHELL_BITS + SEG_RING_BITS)) &
+                             ((1u << SEG_INDEX_BITS) - 1u));
+        const int off = (int)((ent >> (32 - SEG_CNT_BITS - SEG_OFF_BITS)) &
+                              ((1u << SEG_OFF_BITS) - 1u));
+        const int np = v ? (int)(ent >> (32 - SEG_CNT_BITS)) + 1 : 0;
+        // (the clamps only keep a table that disagrees with the walk inside
+        // the tables; they never bind for a table built by this plan)
+        const RingRec rr = P.ring[v ? min(max(W.gbase[so] + rrel, 0), P.n_rings - 1) : 0];
+        const int jref = seg_ref_index(sg, rr.lshift, rr.nj);
+        const int dj0 = (sg << rr.lshift) + off - jref;   // first point, relative to jref
+        float Pl[3], xa, xb;
+        int dc[3];
+        seg_ref(uq, e3, e1d, e2d, lo, rr.rc, rr.rs,
+                v ? P.segref[min(rr.sref + sg, P.n_segref - 1)] : make_double2(1.0, 0.0), Pl,
+                dc, xa, xb);
+        float w = rr.w;
+        if (ADJ && v) w = w * ((gp[(size_t)q * P.nt + klo + so] * gscale) * gscale2);
+        const int nmax = wave_max_i(np);
+        for (int t = 0; t < nmax; ++t) {
+            if (t < np) {
+                const Pt pt = seg_point(Pl, dc, xa, xb, rr.delta, dj0 + t, e1, e2, lo, hi);
+                if (pt.own) pfn(pt, w);
+            }
+        }
+        sfn(np, so, w);
+    }
 }
 
 }  // namespace
@@ -600,8 +767,9 @@ __global__ void __launch_bounds__(FWD_WAVES *WAVE) __attribute__((amdgpu_waves_p
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
                int *__restrict__ klo_out, int q_per_slice)
 {
+    using WL = typename std::conditional<TM == TM_SEG, SegWave, WaveLds>::type;
     __shared__ float box[BOX_WORDS];
-    __shared__ WaveLds wl[FWD_WAVES];
+    __shared__ WL wl[FWD_WAVES];
     __shared__ double gwin[FWD_WAVES][WMAX];
     __shared__ int q_next;
     const int b = blockIdx.x;
@@ -629,7 +797,7 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 
     const int wave = threadIdx.x / WAVE;
     const int lane = lane_id();
-    WaveLds &W = wl[wave];
+    WL &W = wl[wave];
     double *gw = gwin[wave];
     // Each wave takes the slice's next transducer when it finishes one (an
     // LDS counter), so the waves end together whatever the units cost.
@@ -670,9 +838,21 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                 racc = fmaf(sum, wv, racc);
             }
         };
-        walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, nullptr,
-                                           1.f, 1.f, klo, gather);
-        if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
+        if constexpr (TM == TM_SEG) {
+            // One segment (one shell) per lane: its unweighted sum, then
+            // the weighted sum added to the shell's FP64 window entry.
+            auto point = [&](const Pt &t, float) { racc += interp(t); };
+            auto segment = [&](int np, int so, float wv) {
+                if (np > 0) atomicAdd(gw + so, (double)racc * (double)wv);
+                racc = 0.f;
+            };
+            walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, 1.f, 1.f, klo, point,
+                            segment);
+        } else {
+            walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr,
+                                               nullptr, 1.f, 1.f, klo, gather);
+            if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
+        }
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
         for (int j = lane; j < P.window; j += WAVE) dst[j] = (float)gw[j];
@@ -765,7 +945,7 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
     // The segment-table walk needs only the point level's LDS, which leaves
     // room for 16 waves beside the box.
     static_assert(NW <= 12 || TM == TM_SEG, "16 waves fit the LDS only on the segment path");
-    using WL = typename std::conditional<TM == TM_SEG, SegLds, WaveLds>::type;
+    using WL = typename std::conditional<TM == TM_SEG, SegWave, WaveLds>::type;
     __shared__ unsigned long long box[BOX_WORDS];
     __shared__ WL wl[NW];
     __shared__ unsigned long long wred[NW];
@@ -855,12 +1035,19 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     add(pz + BOX_SY, gx * w11);
                     add(pz + BOX_SY + 1, t.fx * w11);
                 };
-                auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
-                    if (a.own) scatter1(a, (wv * g1) * g2);
-                    if (c.own) scatter1(c, (wv * g1) * g2);
-                };
-                walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
-                                                   nullptr, nullptr, 1.f, 1.f, klo, scatter);
+                if constexpr (TM == TM_SEG) {
+                    auto point = [&](const Pt &t, float wv) { scatter1(t, (wv * g1) * g2); };
+                    auto segment = [](int, int, float) {};
+                    walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, 1.f, 1.f,
+                                    klo, point, segment);
+                } else {
+                    auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
+                        if (a.own) scatter1(a, (wv * g1) * g2);
+                        if (c.own) scatter1(c, (wv * g1) * g2);
+                    };
+                    walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                                                       nullptr, nullptr, 1.f, 1.f, klo, scatter);
+                }
             } else {
                 auto scatter1 = [&](const Pt &t, float wv) {
                     unsigned long long *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
@@ -881,12 +1068,19 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                     add2(pz, w10);
                     add2(pz + BOX_SY, w11);
                 };
-                auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
-                    if (a.own) scatter1(a, wv);
-                    if (c.own) scatter1(c, wv);
-                };
-                walk_unit<true, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
-                                                  nullptr, gp, g1, g2, klo, scatter);
+                if constexpr (TM == TM_SEG) {
+                    auto point = [&](const Pt &t, float wv) { scatter1(t, wv); };
+                    auto segment = [](int, int, float) {};
+                    walk_seg<true>(P, q, (size_t)b * P.nq + q, lo, hi, W, gp, g1, g2, klo, point,
+                                   segment);
+                } else {
+                    auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
+                        if (a.own) scatter1(a, wv);
+                        if (c.own) scatter1(c, wv);
+                    };
+                    walk_unit<true, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W,
+                                                      nullptr, gp, g1, g2, klo, scatter);
+                }
             }
         }
         __syncthreads();
@@ -951,9 +1145,8 @@ arc_build_kernel(Problem P)
     auto none = [](const Pt &, const Pt &, float, int, int) {};
     for (int q = wave; q < P.nq; q += WAVES) {
         int klo = 0;
-        walk_unit<false, (MODE >= WALK_SEGCOUNT ? TM_ARC : TM_BOUNDS), MODE>(
-            P, q, (size_t)b * P.nq + q, lo, hi, wl[wave], &bl[wave],
-                                      nullptr, 1.f, 1.f, klo, none);
+        walk_unit<false, TM_BOUNDS, MODE>(P, q, (size_t)b * P.nq + q, lo, hi, wl[wave],
+                                          &bl[wave], nullptr, 1.f, 1.f, klo, none);
     }
 }
 

@@ -150,7 +150,8 @@ class Plan:
     def __init__(self, geom: Geometry, device: int = 0, arc_table="auto", segment_table="auto"):
         """arc_table, segment_table: "auto" (build it if it fits in 40% of
         free device memory), False / 0 (never), or a byte budget
-        (oat_plan_options).  The segment table needs the arc table."""
+        (oat_plan_options).  The plan tries the segment table first and
+        builds the arc table only when it has none."""
         self.geom = geom
         self.device = int(device)
         self._eir = None

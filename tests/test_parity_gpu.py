@@ -189,6 +189,13 @@ TABLES = {"segments": dict(arc_table="auto", segment_table="auto"),
           "bounds": dict(arc_table=False, segment_table=False)}
 
 
+def _check_tables(st, table):
+    """The plan holds exactly the table of its path (the segment table is
+    built from the bounds walk, so a plan that has it builds no arc table)."""
+    assert (st["segment_table_bytes"] > 0) == (table == "segments")
+    assert (st["arc_table_bytes"] > 0) == (table == "arcs")
+
+
 @pytest.mark.parametrize("table", list(TABLES))
 @pytest.mark.parametrize("case", range(len(RAGGED)))
 def test_ragged_grids(case, table, Plan):
@@ -205,9 +212,7 @@ def test_ragged_grids(case, table, Plan):
     img = rng.uniform(0, 1, size=geom.shape)
     img = img.astype(np.float32).astype(np.float64)
     plan = Plan(geom, 0, **TABLES[table])
-    st = plan.stats()
-    assert (st["arc_table_bytes"] > 0) == (table != "bounds")
-    assert (st["segment_table_bytes"] > 0) == (table == "segments")
+    _check_tables(plan.stats(), table)
     g = _np(plan.project(_t(img), srt_only=True))
     check("G", g, ref.srt(gd, img), 5e-7)
     p = _np(plan.project(_t(img)))
@@ -280,16 +285,21 @@ def test_table_paths_agree(seed, Plan):
     and the same calibrated scales), and all match the oracle."""
     geom, _, img = synth.config_small(seed)
     _say(f"[gpu] segment table vs arc table vs arc bounds seed {seed}")
-    ps = Plan(geom, 0)
-    pt = Plan(geom, 0, segment_table=False)
-    pn = Plan(geom, 0, arc_table=False)
+    ps = Plan(geom, 0, **TABLES["segments"])
+    pt = Plan(geom, 0, **TABLES["arcs"])
+    pn = Plan(geom, 0, **TABLES["bounds"])
     ss, st, sn = ps.stats(), pt.stats(), pn.stats()
-    assert ss["segment_table_bytes"] > 0 and ss["segment_table_entries"] > 0
-    assert st["arc_table_bytes"] > 0 and st["arc_table_entries"] > 0
-    assert st["segment_table_bytes"] == 0
-    assert sn["arc_table_bytes"] == 0 and sn["segment_table_bytes"] == 0
-    assert Plan(geom, 0, arc_table=1).stats()["arc_table_bytes"] == 0   # budget too small
-    assert Plan(geom, 0, segment_table=1).stats()["segment_table_bytes"] == 0
+    _check_tables(ss, "segments")
+    _check_tables(st, "arcs")
+    _check_tables(sn, "bounds")
+    assert ss["segment_table_entries"] > 0 and st["arc_table_entries"] > 0
+    # budgets too small for the table: the next path
+    assert Plan(geom, 0, arc_table=1, segment_table=False).stats()["arc_table_bytes"] == 0
+    s1 = Plan(geom, 0, segment_table=1).stats()
+    assert s1["segment_table_bytes"] == 0 and s1["arc_table_bytes"] > 0
+    # the segment table needs no arc table
+    s2 = Plan(geom, 0, arc_table=False).stats()
+    assert s2["segment_table_bytes"] > 0 and s2["arc_table_bytes"] == 0
     x = _t(img)
     gs, gt, gn = (_np(p.project(x, srt_only=True)) for p in (ps, pt, pn))
     e1, e2 = rel(gs, gn), rel(gt, gn)
