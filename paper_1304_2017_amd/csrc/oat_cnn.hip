@@ -138,6 +138,176 @@ __global__ void __launch_bounds__(NT) conv_bwd_w_kernel(const void *__restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 16 -> 16 channel layers on the matrix cores (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation).  The convolution is an implicit GEMM per 8^3 tile:
+//   forward  Y[voxel][co] = sum_k X[voxel][k] W[k][co],  k = (tap, ci),
+//            27 taps (+ one zero tap) x 16 channels = 14 steps of K = 32;
+//   weights  dW_tap[co][ci] = sum_v dY[co][v] X[ci][v + tap], K = the tile's
+//            512 voxels = 16 steps of 32 (4 rows of 8 along x) per tap.
+// MFMA operand layout (16x16x32): lane l holds row (A) or column (B) l % 16
+// and the 8 consecutive k values 8 (l / 16) .. 8 (l / 16) + 7; the 16x16
+// result holds column l % 16 and rows 4 (l / 16) .. 4 (l / 16) + 3.
+// Weights are rounded to BF16 (round to nearest even) like the activations.
+// ---------------------------------------------------------------------------
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float floatx4;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+
+constexpr int MF_THREADS = 256;   // 4 waves
+constexpr int MF_KSTEPS = 14;     // 28 taps in pairs
+
+__device__ __forceinline__ unsigned bf16_bits(float v)
+{
+    unsigned u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);     // round to nearest even
+    return u >> 16;
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// Offset (voxels of the 10^3 halo tile) of tap t = 9 dz + 3 dy + dx.
+__host__ __device__ constexpr int tap_off(int t) { return ((t / 9) * TI + (t / 3) % 3) * TI + t % 3; }
+
+// Forward (and data backward) of a 16 -> 16 layer on BF16 activations.  A
+// workgroup owns an 8^3 output tile; each wave 128 of its voxels (8 row
+// blocks of 16), all 16 output channels.
+__global__ void __launch_bounds__(MF_THREADS)
+conv16_mfma_kernel(const unsigned short *__restrict__ x, int D, int H, int W,
+                   const float *__restrict__ wt, const float *__restrict__ bias,
+                   void *__restrict__ y, int ydt, int relu, const void *__restrict__ mask)
+{
+    // halo tile, channel-last: [z][y][x][ci], 32 bytes per voxel
+    __shared__ __attribute__((aligned(16))) unsigned short xs[TI3 * 16];
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
+    const size_t plane = (size_t)H * W, vol = plane * D;
+    for (int i = threadIdx.x; i < 16 * TI3; i += MF_THREADS) {
+        const int ci = i / TI3, r = i - ci * TI3;
+        const int zz = r / (TI * TI), yy = (r / TI) % TI, xx = r % TI;
+        const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+        unsigned short v = 0;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = x[ci * vol + gz * plane + (size_t)gy * W + gx];
+        xs[r * 16 + ci] = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    // B fragments: column co = col, k = 8 g .. 8 g + 7 of each step, i.e.
+    // tap 2 s + (g >> 1), channels (g & 1) 8 .. + 7.
+    bf16x8 bw[MF_KSTEPS];
+#pragma unroll
+    for (int s = 0; s < MF_KSTEPS; ++s) {
+        const int tap = 2 * s + (g >> 1), ci0 = (g & 1) * 8;
+        u32x4 pk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float lo = tap < 27 ? wt[(col * 16 + ci0 + 2 * e) * 27 + tap] : 0.f;
+            const float hi = tap < 27 ? wt[(col * 16 + ci0 + 2 * e + 1) * 27 + tap] : 0.f;
+            pk[e] = bf16_bits(lo) | (bf16_bits(hi) << 16);
+        }
+        bw[s] = as_bf16x8(pk);
+    }
+    __syncthreads();
+    const float bcol = bias ? bias[col] : 0.f;
+    for (int m = 0; m < 8; ++m) {
+        // A row: voxel v of the tile; k = tap 2 s + (g >> 1), channels (g & 1) 8 ..
+        const int v = wave * 128 + m * 16 + col;
+        const int lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
+        const unsigned short *base = xs + ((lz * TI + ly) * TI + lx) * 16 + (g & 1) * 8;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < MF_KSTEPS; ++s) {
+            const int t0 = 2 * s, t1 = 2 * s + 1;
+            const int tap = (g >> 1) ? t1 : t0;
+            u32x4 av = {0u, 0u, 0u, 0u};
+            if (tap < 27) av = *reinterpret_cast<const u32x4 *>(base + ((g >> 1) ? tap_off(t1 < 27 ? t1 : 0) : tap_off(t0)) * 16);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), bw[s], acc, 0, 0, 0);
+        }
+        // result: column co = col, rows (voxels) m 16 + 4 g + r
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int vv = wave * 128 + m * 16 + 4 * g + r;
+            const int gx = x0 + (vv & 7), gy = y0 + ((vv >> 3) & 7), gz = z0 + (vv >> 6);
+            if (gx >= W || gy >= H || gz >= D) continue;
+            const size_t off = col * vol + gz * plane + (size_t)gy * W + gx;
+            float o = acc[r] + bcol;
+            if (relu) o = fmaxf(o, 0.f);
+            if (mask && !(ldv(mask, off, ydt) > 0.f)) o = 0.f;
+            stv(y, off, ydt, o);
+        }
+    }
+}
+
+// Per-tile partial weight and bias gradients of a 16 -> 16 layer on BF16
+// activations (same part[tile][j] layout as conv_bwd_w_kernel).  Wave w
+// takes taps w, w + 4, ...; dy and three x copies shifted by dx = 0, 1, 2
+// (so every 8-voxel row starts on 16 bytes) are staged in LDS.
+__global__ void __launch_bounds__(MF_THREADS)
+conv16_wgrad_mfma_kernel(const unsigned short *__restrict__ x, const unsigned short *__restrict__ dy,
+                         int D, int H, int W, float *__restrict__ part)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short xs3[3][16][TI * TI][TT];  // [dx][ci][z y][x]
+    __shared__ __attribute__((aligned(16))) unsigned short gs[16][TT3];             // [co][v]
+    __shared__ float bsum[16][16];
+    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
+    const size_t plane = (size_t)H * W, vol = plane * D;
+    for (int i = threadIdx.x; i < 3 * 16 * TI * TI * TT; i += MF_THREADS) {
+        const int xx = i % TT, r = i / TT;
+        const int zy = r % (TI * TI), r2 = r / (TI * TI);
+        const int ci = r2 % 16, dx = r2 / 16;
+        const int gz = z0 - 1 + zy / TI, gy = y0 - 1 + zy % TI, gx = x0 - 1 + xx + dx;
+        unsigned short v = 0;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = x[ci * vol + gz * plane + (size_t)gy * W + gx];
+        xs3[dx][ci][zy][xx] = v;
+    }
+    for (int i = threadIdx.x; i < 16 * TT3; i += MF_THREADS) {
+        const int co = i / TT3, v = i - co * TT3;
+        const int gz = z0 + v / (TT * TT), gy = y0 + (v / TT) % TT, gx = x0 + v % TT;
+        unsigned short gv = 0;
+        if (gz < D && gy < H && gx < W) gv = dy[co * vol + gz * plane + (size_t)gy * W + gx];
+        gs[co][v] = gv;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    constexpr int NW = 16 * 16 * 27;
+    const size_t tile = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float *dst = part + tile * (NW + 16);
+    for (int tap = wave; tap < 27; tap += 4) {
+        const int dz = tap / 9, dyy = (tap / 3) % 3, dx = tap % 3;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            // k = voxels of row R = 4 kk + g (8 along x) of the tile
+            const int R = 4 * kk + g, lz = R >> 3, ly = R & 7;
+            // A: row co = col, dy[co][R 8 .. R 8 + 7]
+            const u32x4 av = *reinterpret_cast<const u32x4 *>(&gs[col][R * TT]);
+            // B: column ci = col, x[ci][lz + dz][ly + dy][dx .. dx + 7]
+            const u32x4 bv =
+                *reinterpret_cast<const u32x4 *>(&xs3[dx][col][(lz + dz) * TI + ly + dyy][0]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc, 0, 0, 0);
+        }
+        // rows co = 4 g + r, column ci = col
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[((4 * g + r) * 16 + col) * 27 + tap] = acc[r];
+    }
+    // bias: 16 partial sums of 32 voxels per channel, added in a fixed order
+    {
+        const int co = threadIdx.x >> 4, pp = threadIdx.x & 15;
+        float sacc = 0.f;
+        for (int v = pp * 32; v < pp * 32 + 32; ++v)
+            sacc += __uint_as_float((unsigned)gs[co][v] << 16);
+        bsum[co][pp] = sacc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float sb = 0.f;
+        for (int pp = 0; pp < 16; ++pp) sb += bsum[threadIdx.x][pp];
+        dst[NW + threadIdx.x] = sb;
+    }
+}
+
 // Sum the per-tile partials in tile order (deterministic).
 __global__ void sum_tiles_kernel(const float *__restrict__ part, int ntiles, int nj, int nw,
                                  float *__restrict__ dw, float *__restrict__ db)
@@ -235,7 +405,11 @@ int oat_conv3d_forward(const void *x, oat_dtype xdt, int c_in, int d, int h, int
 #define FWD(CI, CO)                                                                                 \
     hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), g, b, 0, s, x, (int)xdt, d, h, w, weight, bias, y, \
                        (int)ydt, relu, mask)
-    if (c_in == 1 && c_out == 16) FWD(1, 16);
+    if (c_in == 16 && c_out == 16 && xdt == OAT_BF16)
+        hipLaunchKernelGGL(conv16_mfma_kernel, g, dim3(MF_THREADS), 0, s,
+                           (const unsigned short *)x, d, h, w, weight, bias, y, (int)ydt, relu,
+                           mask);
+    else if (c_in == 1 && c_out == 16) FWD(1, 16);
     else if (c_in == 16 && c_out == 16) FWD(16, 16);
     else if (c_in == 16 && c_out == 1) FWD(16, 1);
     else FWD(1, 1);
@@ -267,7 +441,10 @@ int oat_conv3d_backward_weight(const void *x, oat_dtype xdt, const void *dy, oat
 #define BWD(CI, CO)                                                                                \
     hipLaunchKernelGGL((conv_bwd_w_kernel<CI, CO>), g, b, 0, s, x, (int)xdt, dy, (int)dydt, d, h, w, \
                        part)
-    if (c_in == 1 && c_out == 16) BWD(1, 16);
+    if (c_in == 16 && c_out == 16 && xdt == OAT_BF16 && dydt == OAT_BF16)
+        hipLaunchKernelGGL(conv16_wgrad_mfma_kernel, g, dim3(MF_THREADS), 0, s,
+                           (const unsigned short *)x, (const unsigned short *)dy, d, h, w, part);
+    else if (c_in == 1 && c_out == 16) BWD(1, 16);
     else if (c_in == 16 && c_out == 16) BWD(16, 16);
     else if (c_in == 16 && c_out == 1) BWD(16, 1);
     else BWD(1, 1);

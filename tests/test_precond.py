@@ -114,6 +114,43 @@ def test_conv3d_weight_grad_matches_autograd(ci, co):
 
 
 @gpu
+@pytest.mark.parametrize("shape", [(13, 11, 9), (19, 17, 21), (8, 8, 8)])
+def test_bf16_16ch_layers_on_matrix_cores(shape):
+    """BF16 16 -> 16 layers run on the matrix cores (BF16 operands, weights
+    rounded to BF16, FP32 accumulation).  Against FP64 on the same rounded
+    weights and inputs only FP32 accumulation remains (FP32 output) or the
+    output's BF16 rounding (BF16 output); the weight gradient of BF16 x and
+    dy is exact products summed in FP32."""
+    g = torch.Generator().manual_seed(sum(shape))
+    x = torch.randn((16,) + shape, generator=g).to(torch.bfloat16)
+    w = torch.randn((16, 16, 27), generator=g) * 0.2
+    b = torch.randn((16,), generator=g)
+    wb = w.to(torch.bfloat16).float()
+    ref = _ref_conv(x.float(), wb, b)
+    y32 = precond.conv3d(x.cuda(), w.cuda(), b.cuda(), out_dtype=torch.float32)
+    y16 = precond.conv3d(x.cuda(), w.cuda(), b.cuda())
+    m = torch.randn((16,) + shape, generator=g).to(torch.bfloat16)
+    ym = precond.conv3d(x.cuda(), w.cuda(), b.cuda(), relu=True, mask=m.cuda())
+    e32, e16 = _rel(y32, ref), _rel(y16, ref)
+    em = _rel(ym, ref.clamp(min=0) * (m.double() > 0))
+    # element-wise: every output within its BF16 half-ulp (plus FP32 sums)
+    d16 = (y16.double().cpu() - ref).abs() / ref.abs().clamp(min=1e-3)
+    dy = torch.randn((16,) + shape, generator=g).to(torch.bfloat16)
+    dw, db = precond.conv3d_weight_grad(x.cuda(), dy.cuda())
+    wr = torch.zeros((16, 16, 3, 3, 3), dtype=torch.float64, requires_grad=True)
+    br = torch.zeros((16,), dtype=torch.float64, requires_grad=True)
+    (F.conv3d(x.double()[None], wr, br, padding=1)[0] * dy.double()).sum().backward()
+    ew, eb = _rel(dw, wr.grad.reshape(16, 16, 27)), _rel(db, br.grad)
+    _say(f"[gpu] MFMA 16->16 {shape}: fwd FP32-out rel {e32:.3e}, BF16-out rel {e16:.3e} "
+         f"(max {float(d16.max()):.2e}), relu+mask {em:.3e}; dW rel {ew:.3e}, db rel {eb:.3e}")
+    assert e32 < 1e-5 and e16 < 2.5e-3 and em < 2.5e-3
+    assert float(d16.max()) < 2 ** -8 + 1e-4
+    assert ew < 1e-5 and eb < 1e-5
+    dw2, db2 = precond.conv3d_weight_grad(x.cuda(), dy.cuda())
+    assert torch.equal(dw, dw2) and torch.equal(db, db2)
+
+
+@gpu
 def test_adam_and_mse_match_their_formulas():
     g = torch.Generator().manual_seed(3)
     p = torch.randn(1000, generator=g)
