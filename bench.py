@@ -243,7 +243,10 @@ def learned_run(n_phantoms, epochs, iters):
     torch.cuda.empty_cache()
 
     geom, _, img = synth.config_e(0)
-    plan = big_plan(geom)
+    plan = Plan(geom, 0)
+    st = plan.stats()
+    log(f"[learned] plan: segment table {st['segment_table_bytes'] / 1e9:.1f} GB, "
+        f"arc table {st['arc_table_bytes'] / 1e9:.1f} GB")
     clean = plan.project(torch.from_numpy(img).cuda())
     torch.cuda.synchronize()
     gen = torch.Generator(device="cuda").manual_seed(0)
@@ -252,24 +255,46 @@ def learned_run(n_phantoms, epochs, iters):
     mu = 1e-3 * float(u.double().pow(2).sum()) / (geom.n_vox * eps)
     recon.pls_tv(plan, u, mu=mu, eps=eps, iters=1)          # warm-up
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     plain = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters)
     torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    r_star = plain.residuals[-1]
-    log(f"[learned] plain {iters} iterations {t_plain:.1f} s, r* = {r_star:.5f}")
-    t0 = time.perf_counter()
+    # targets: the plain residual after 5, 10, 20 and `iters` iterations
+    marks = sorted({k for k in (5, 10, 20, iters) if k <= iters})
+    targets = {k: plain.residuals[k] for k in marks}
+    r_star = targets[iters]
+    log(f"[learned] plain {iters} iterations {plain.times[-1]:.1f} s, r* = {r_star:.5f}")
     learned = precond.pls_tv_learned(plan, u, model, mu=mu, eps=eps, iters=iters, target=r_star)
     torch.cuda.synchronize()
-    t_learned = time.perf_counter() - t0
-    k_plain = next(i for i, r in enumerate(plain.residuals) if r <= r_star)
-    k_learned = next((i for i, r in enumerate(learned.residuals) if r <= r_star), None)
+
+    def first(res, r):
+        k = next((i for i, v in enumerate(res.residuals) if v <= r), None)
+        return (k, res.times[k] if k is not None else None)
+
+    per_target = []
+    for k, r in targets.items():
+        kp, tp = first(plain, r)
+        kl, tl_ = first(learned, r)
+        per_target.append(dict(plain_iterations_for_target=k, target=r, plain_iterations=kp,
+                               plain_s=tp, learned_iterations=kl, learned_s=tl_,
+                               speedup=(tp / tl_) if (tp and tl_) else None))
+    # the recursive residual checked by one fresh H on each final image
+    unorm = float(u.double().norm())
+
+    def fresh(a):
+        return float((u - plan.project(a.float().contiguous())).double().norm()) / unorm
+
     print(json.dumps(dict(
         workload=geom.name, data="H a_true + 1% noise, 60 seeded ellipsoids", mu=mu, eps=eps,
-        r_star=r_star, plain=dict(iterations=k_plain, seconds=t_plain,
-                                  residuals=[round(v, 6) for v in plain.residuals]),
-        learned=dict(iterations=k_learned, seconds=t_learned, reached=k_learned is not None,
-                     residuals=[round(v, 6) for v in learned.residuals]),
+        plan=dict(segment_table_bytes=st["segment_table_bytes"],
+                  arc_table_bytes=st["arc_table_bytes"]),
+        r_star=r_star, targets=per_target,
+        plain=dict(iterations=len(plain.residuals) - 1, seconds=plain.times[-1],
+                   fresh_residual=fresh(plain.image),
+                   residuals=[round(v, 6) for v in plain.residuals],
+                   times=[round(v, 4) for v in plain.times]),
+        learned=dict(iterations=len(learned.residuals) - 1, seconds=learned.times[-1],
+                     reached=learned.residuals[-1] <= r_star, fresh_residual=fresh(learned.image),
+                     residuals=[round(v, 6) for v in learned.residuals],
+                     times=[round(v, 4) for v in learned.times]),
         training=dict(workload=gd.name, phantoms=n_phantoms, pairs=n, epochs=epochs,
                       phantom_s=t_phantoms, pairs_s=t_pairs, train_s=t_train,
                       loss_first_epoch=loss_first, loss_last_epoch=loss_last))), flush=True)

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import time
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -204,6 +205,7 @@ def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps:
                    iters: int = 20, storage=torch.float32, target: Optional[float] = None):
     """PLS-TV with the learned direction.  Stops after `iters` iterations or
     once ||u - H a|| / ||u|| <= target.  Returns a recon.PLSResult."""
+    t0 = time.perf_counter()
     u = u.float().contiguous()
     unorm = max(recon._dot(u, u) ** 0.5, 1e-300)
 
@@ -223,6 +225,7 @@ def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps:
     res = recon.PLSResult(a)
     res.residuals.append(1.0)
     res.objective.append(unorm ** 2 + mu * tv)
+    res.times.append(time.perf_counter() - t0)
     zs = recon._dot(zf, s)
     for _ in range(iters):
         if recon._dot(g, d) >= 0.0:
@@ -247,6 +250,7 @@ def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps:
         rn = recon._dot(r, r)
         res.residuals.append(rn ** 0.5 / unorm)
         res.objective.append(rn + mu * tv)
+        res.times.append(time.perf_counter() - t0)   # after FP64 dots: the device is synced
         if target is not None and res.residuals[-1] <= target:
             break
     res.image = a

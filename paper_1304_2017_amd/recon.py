@@ -24,6 +24,7 @@ CG recursion is accumulated in FP64.
 """
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass, field
 from typing import List
 
@@ -96,6 +97,7 @@ class PLSResult:
     image: torch.Tensor
     residuals: List[float] = field(default_factory=list)    # ||u - H a_i|| / ||u||
     objective: List[float] = field(default_factory=list)    # ||u - H a_i||^2 + mu R(a_i)
+    times: List[float] = field(default_factory=list)        # wall seconds to a_i (device synced)
 
 
 def pls_cg(plan, u: torch.Tensor, mu: float = 0.0, iters: int = 20,
@@ -215,6 +217,7 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
     """Nonlinear CG for min ||u - H a||^2 + mu TV_eps(a) from a = 0.
     `storage` is the dtype of the operator inputs and outputs (FP32 or BF16);
     iterates and residuals are kept in FP32 and every inner product in FP64."""
+    t0 = time.perf_counter()
     u = u.float().contiguous()
     unorm = max(_dot(u, u) ** 0.5, 1e-300)
     res = PLSResult(None)
@@ -223,6 +226,7 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
         if track:
             res.residuals.append(rn ** 0.5 / unorm)
             res.objective.append(rn + mu * tv)
+            res.times.append(time.perf_counter() - t0)   # rn is an FP64 dot: the device is synced
     return res
 
 
