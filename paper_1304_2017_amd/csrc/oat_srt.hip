@@ -245,22 +245,36 @@ __device__ __forceinline__ void seg_ref(const double uq[3], const double e3[3],
 }
 
 // Point j of a segment, dj = j - jref, relative to the segment's reference
-// point: ref + a e1 + b e2 with a = xa (cos d - 1) - xb sin d,
-// b = xb (cos d - 1) + xa sin d, d = dj 2 pi / nj (dd = 2 pi / nj).  The
-// fraction stays within a few tens of cells, so positions carry ~1e-6 cell
-// of FP32 error, and every brick evaluates the same FP32 operations, so each
-// point belongs to exactly one brick.  own: its cell lies in the brick.
-__device__ __forceinline__ Pt seg_point(const float Pl[3], const int dc[3], float qa, float qb,
-                                        float dd, int dj, const float e1[3], const float e2[3],
-                                        const int lo[3], const int hi[3])
+// point: ref + (cos d - 1) A + sin d B (seg_axes), d = dj 2 pi / nj
+// (dd = 2 pi / nj).  The fraction stays within a few tens of cells, so
+// positions carry a few 1e-6 cell of FP32 error, and every brick evaluates
+// the same FP32 operations, so each point belongs to exactly one brick.
+// own: its cell lies in the brick.
+// In-plane axes of a segment: point j sits at ref + (cos d - 1) A + sin d B
+// with A = xa e1 + xb e2 and B = xa e2 - xb e1.
+struct SegAxes {
+    float A[3], B[3];
+};
+__device__ __forceinline__ SegAxes seg_axes(float xa, float xb, const float e1[3],
+                                            const float e2[3])
+{
+    SegAxes s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s.A[a] = fmaf(xb, e2[a], xa * e1[a]);
+        s.B[a] = fmaf(-xb, e1[a], xa * e2[a]);
+    }
+    return s;
+}
+
+__device__ __forceinline__ Pt seg_point(const float Pl[3], const int dc[3], const SegAxes &ax,
+                                        float dd, int dj, const int lo[3], const int hi[3])
 {
     float cm1, sn;
     small_rot((float)dj * dd, cm1, sn);
-    const float al = fmaf(qa, cm1, -(qb * sn));
-    const float be = fmaf(qb, cm1, qa * sn);
-    const float ux = fmaf(be, e2[0], fmaf(al, e1[0], Pl[0]));
-    const float uy = fmaf(be, e2[1], fmaf(al, e1[1], Pl[1]));
-    const float uz = fmaf(be, e2[2], fmaf(al, e1[2], Pl[2]));
+    const float ux = fmaf(sn, ax.B[0], fmaf(cm1, ax.A[0], Pl[0]));
+    const float uy = fmaf(sn, ax.B[1], fmaf(cm1, ax.A[1], Pl[1]));
+    const float uz = fmaf(sn, ax.B[2], fmaf(cm1, ax.A[2], Pl[2]));
     Pt t;
     t.cx = cvt_floor(ux) + dc[0];
     t.cy = cvt_floor(uy) + dc[1];
@@ -341,9 +355,10 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
         const int npp = (mt >> 7) & 63, kk = mt >> 13;
         const int djA = (mt & 127) - 64 + 2 * pr;
         Pt pt[2];
+        const SegAxes ax = seg_axes(qa, qb, e1, e2);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            pt[h] = seg_point(p3, d3, qa, qb, dd, djA + h, e1, e2, lo, hi);
+            pt[h] = seg_point(p3, d3, ax, dd, djA + h, lo, hi);
             pt[h].own = pt[h].own && v3 && 2 * pr + h < npp;
         }
         if (MODE == WALK_POINTS) {
@@ -686,7 +701,7 @@ __device__ __forceinline__ int wave_max_i(int v)
 // the lane's segment count (0: none), shell offset and weight.
 template <bool ADJ, class PFn, class SFn>
 __device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, const int lo[3],
-                                         const int hi[3], SegWave &W, const float *gp,
+                                         const int hi[3], int *gbase, const float *gp,
                                          float gscale, float gscale2, int &klo_out, PFn &&pfn,
                                          SFn &&sfn)
 {
@@ -714,7 +729,7 @@ __device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, c
             const ShellRec sh = P.shell[klo + so];
             int i0, cnt;
             shell_rings(sh, D, thb, U.h2, i0, cnt);
-            W.gbase[so] = sh.ring_base + i0;
+            gbase[so] = sh.ring_base + i0;
         }
         wave_sync();
     }
@@ -734,7 +749,7 @@ __device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, c
         const int np = v ? (int)(ent >> (32 - SEG_CNT_BITS)) + 1 : 0;
         // (the clamps only keep a table that disagrees with the walk inside
         // the tables; they never bind for a table built by this plan)
-        const RingRec rr = P.ring[v ? min(max(W.gbase[so] + rrel, 0), P.n_rings - 1) : 0];
+        const RingRec rr = P.ring[v ? min(max(gbase[so] + rrel, 0), P.n_rings - 1) : 0];
         const int jref = seg_ref_index(sg, rr.lshift, rr.nj);
         const int dj0 = (sg << rr.lshift) + off - jref;   // first point, relative to jref
         float Pl[3], xa, xb;
@@ -744,10 +759,11 @@ __device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, c
                 dc, xa, xb);
         float w = rr.w;
         if (ADJ && v) w = w * ((gp[(size_t)q * P.nt + klo + so] * gscale) * gscale2);
+        const SegAxes ax = seg_axes(xa, xb, e1, e2);
         const int nmax = wave_max_i(np);
         for (int t = 0; t < nmax; ++t) {
             if (t < np) {
-                const Pt pt = seg_point(Pl, dc, xa, xb, rr.delta, dj0 + t, e1, e2, lo, hi);
+                const Pt pt = seg_point(Pl, dc, ax, rr.delta, dj0 + t, lo, hi);
                 if (pt.own) pfn(pt, w);
             }
         }
@@ -767,7 +783,8 @@ __global__ void __launch_bounds__(FWD_WAVES *WAVE) __attribute__((amdgpu_waves_p
 srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
                int *__restrict__ klo_out, int q_per_slice)
 {
-    using WL = typename std::conditional<TM == TM_SEG, SegWave, WaveLds>::type;
+    static_assert(TM != TM_SEG, "the segment table has srt_fwd_seg_kernel");
+    using WL = WaveLds;
     __shared__ float box[BOX_WORDS];
     __shared__ WL wl[FWD_WAVES];
     __shared__ double gwin[FWD_WAVES][WMAX];
@@ -838,24 +855,90 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
                 racc = fmaf(sum, wv, racc);
             }
         };
-        if constexpr (TM == TM_SEG) {
-            // One segment (one shell) per lane: its unweighted sum, then
-            // the weighted sum added to the shell's FP64 window entry.
-            auto point = [&](const Pt &t, float) { racc += interp(t); };
-            auto segment = [&](int np, int so, float wv) {
-                if (np > 0) atomicAdd(gw + so, (double)racc * (double)wv);
-                racc = 0.f;
-            };
-            walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, 1.f, 1.f, klo, point,
-                            segment);
-        } else {
-            walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr,
-                                               nullptr, 1.f, 1.f, klo, gather);
-            if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
-        }
+        walk_unit<false, TM, WALK_POINTS>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr,
+                                           nullptr, 1.f, 1.f, klo, gather);
+        if (rk >= 0) atomicAdd(gw + (rk - rbase), (double)racc);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * P.window;
         for (int j = lane; j < P.window; j += WAVE) dst[j] = (float)gw[j];
+        if (lane == 0) klo_out[(size_t)b * P.nq + q] = klo;
+        wave_sync();
+    }
+}
+
+// G on the segment table: one segment per lane (walk_seg), FWD_SEG_WAVES
+// waves per workgroup and two workgroups per CU (at most 64 VGPRs, the LDS
+// of two boxes).  Per wave, dynamic LDS holds the unit's first candidate
+// ring per shell (window ints) and its FP64 shell sums (window doubles).
+constexpr int FWD_SEG_WAVES = 16;
+
+template <int IMG_DT>
+__global__ void __launch_bounds__(FWD_SEG_WAVES *WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part,
+                   int *__restrict__ klo_out, int q_per_slice)
+{
+    constexpr int NW = FWD_SEG_WAVES;
+    __shared__ float box[BOX_WORDS];
+    __shared__ int q_next;
+    extern __shared__ double dyn_lds[];
+    const int win = P.window;
+    const int b = blockIdx.x;
+    int lo[3], hi[3], n0[3], n1[3];
+    brick_box(P, b, lo, hi, n0, n1);
+    const int qb = (int)blockIdx.y * q_per_slice, qe = min(P.nq, qb + q_per_slice);
+    if (threadIdx.x == 0) q_next = qb;
+    auto node = [&](int x, int y, int z) {
+        const int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
+        float v = 0.f;
+        if (gx >= 0 && gx < P.nx && gy >= 0 && gy < P.ny && gz >= 0 && gz < P.nz) {
+            const size_t n = ((size_t)gz * P.ny + gy) * P.nx + gx;
+            if (IMG_DT == 0)
+                v = ((const float *)img)[n];
+            else
+                v = __uint_as_float(((unsigned)((const unsigned short *)img)[n]) << 16);
+        }
+        return v;
+    };
+    for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
+        const int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
+        box[z * BOX_SZ + y * BOX_SY + x] = node(x, y, z);
+    }
+    const int wave = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    double *gw = dyn_lds + (size_t)wave * win;
+    int *gbase = reinterpret_cast<int *>(dyn_lds + (size_t)NW * win) + wave * win;
+    __syncthreads();
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(&q_next, 1);
+        q = __builtin_amdgcn_readfirstlane(q);
+        if (q >= qe) break;
+        for (int j = lane; j < win; j += WAVE) gw[j] = 0.0;
+        wave_sync();
+        int klo = 0;
+        float racc = 0.f;
+        auto point = [&](const Pt &t, float) {
+            const float *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
+                              __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+            const float *pz = pb + BOX_SZ;
+            const float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
+            const float v100 = pz[0], v101 = pz[1], v110 = pz[BOX_SY], v111 = pz[BOX_SY + 1];
+            const float c00 = fmaf(t.fx, v001 - v000, v000), c01 = fmaf(t.fx, v011 - v010, v010);
+            const float c10 = fmaf(t.fx, v101 - v100, v100), c11 = fmaf(t.fx, v111 - v110, v110);
+            const float c0 = fmaf(t.fy, c01 - c00, c00), c1 = fmaf(t.fy, c11 - c10, c10);
+            racc += fmaf(t.fz, c1 - c0, c0);
+        };
+        // one segment (one shell) per lane: the weighted sum of its points
+        // goes to the shell's FP64 entry
+        auto segment = [&](int np, int so, float wv) {
+            if (np > 0) atomicAdd(gw + so, (double)racc * (double)wv);
+            racc = 0.f;
+        };
+        walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, gbase, nullptr, 1.f, 1.f, klo, point,
+                        segment);
+        wave_sync();
+        float *dst = part + ((size_t)b * P.nq + q) * win;
+        for (int j = lane; j < win; j += WAVE) dst[j] = (float)gw[j];
         if (lane == 0) klo_out[(size_t)b * P.nq + q] = klo;
         wave_sync();
     }
@@ -1038,8 +1121,8 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                 if constexpr (TM == TM_SEG) {
                     auto point = [&](const Pt &t, float wv) { scatter1(t, (wv * g1) * g2); };
                     auto segment = [](int, int, float) {};
-                    walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, W, nullptr, 1.f, 1.f,
-                                    klo, point, segment);
+                    walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, W.gbase, nullptr, 1.f,
+                                    1.f, klo, point, segment);
                 } else {
                     auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
                         if (a.own) scatter1(a, (wv * g1) * g2);
@@ -1071,8 +1154,8 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                 if constexpr (TM == TM_SEG) {
                     auto point = [&](const Pt &t, float wv) { scatter1(t, wv); };
                     auto segment = [](int, int, float) {};
-                    walk_seg<true>(P, q, (size_t)b * P.nq + q, lo, hi, W, gp, g1, g2, klo, point,
-                                   segment);
+                    walk_seg<true>(P, q, (size_t)b * P.nq + q, lo, hi, W.gbase, gp, g1, g2, klo,
+                                   point, segment);
                 } else {
                     auto scatter = [&](const Pt &a, const Pt &c, float wv, int, int) {
                         if (a.own) scatter1(a, wv);
@@ -1155,11 +1238,20 @@ static void fwd_launch(const Problem &P, const void *img, int img_dtype, float *
                        hipStream_t s)
 {
     const int sl = fwd_slices(P.nbx * P.nby * P.nbz, P.nq), qps = (P.nq + sl - 1) / sl;
-    dim3 grid(P.nbx * P.nby * P.nbz, sl), block(FWD_WAVES * WAVE);
-    if (img_dtype == 0)
-        hipLaunchKernelGGL((srt_fwd_kernel<0, TM>), grid, block, 0, s, P, img, part, klo, qps);
-    else
-        hipLaunchKernelGGL((srt_fwd_kernel<1, TM>), grid, block, 0, s, P, img, part, klo, qps);
+    if constexpr (TM == TM_SEG) {
+        dim3 grid(P.nbx * P.nby * P.nbz, sl), block(FWD_SEG_WAVES * WAVE);
+        const size_t dyn = (size_t)FWD_SEG_WAVES * P.window * (sizeof(double) + sizeof(int));
+        if (img_dtype == 0)
+            hipLaunchKernelGGL(srt_fwd_seg_kernel<0>, grid, block, dyn, s, P, img, part, klo, qps);
+        else
+            hipLaunchKernelGGL(srt_fwd_seg_kernel<1>, grid, block, dyn, s, P, img, part, klo, qps);
+    } else {
+        dim3 grid(P.nbx * P.nby * P.nbz, sl), block(FWD_WAVES * WAVE);
+        if (img_dtype == 0)
+            hipLaunchKernelGGL((srt_fwd_kernel<0, TM>), grid, block, 0, s, P, img, part, klo, qps);
+        else
+            hipLaunchKernelGGL((srt_fwd_kernel<1, TM>), grid, block, 0, s, P, img, part, klo, qps);
+    }
 }
 
 static int table_mode(const Problem &P)
