@@ -499,8 +499,10 @@ def main():
     value = 2.0 * N * Q / ((t_h + t_ht) * 1e-3)
     pts = quad_points(geom)
     # Dominant kernel: the G or G^T brick kernel (the operator call also holds
-    # one small data-side kernel, under 1% of its time).
-    dom_name, dom_ms = ("srt_adj_kernel", t_ht) if t_ht >= t_h else ("srt_fwd_kernel", t_h)
+    # one small data-side kernel, under 1% of its time).  G on the segment
+    # table is srt_fwd_seg_kernel.
+    g_name = "srt_fwd_seg_kernel" if st["segment_table_bytes"] > 0 else "srt_fwd_kernel"
+    dom_name, dom_ms = ("srt_adj_kernel", t_ht) if t_ht >= t_h else (g_name, t_h)
     achieved = OPS_PER_POINT * pts / (dom_ms * 1e-3)
     traffic = measured_traffic(dom_name)
     roof = dict(bound="alu", kernel=dom_name, achieved=achieved, peak=VALU_PEAK,
