@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 # wave64 VALU instruction per cycle: the FBP kernel measures 1.24.)
 VALU_PEAK = 157.3e12 / 2
 HBM_PEAK = 8.0e12   # bytes/s
+BF16_PEAK = 2.5e15  # dense BF16 matrix-core FLOP/s
 # Algorithmic FP32 VALU operations of one quadrature point of G or G^T
 # (position 6 FMA, cos/sin of the azimuth 2 transcendental = 8 issue slots,
 # floor 3, fraction 3, cell address 3, trilinear 7 lerps = 14, weighted add 2).
@@ -342,6 +343,47 @@ def sph_run(reps):
         reps=reps)), flush=True)
 
 
+def cnn_run(reps):
+    """The learned preconditioner's BF16 16 -> 16 convolution on the matrix
+    cores (forward, which also serves the data backward, and the weight
+    gradient) at 128^3 and 256^3, against the 2.5 PFLOP/s dense BF16 peak,
+    beside the FP32-activation VALU kernel and one whole network forward
+    (1 -> 16 -> 16 -> 1 layers) in BF16.  Prints one JSON line."""
+    import torch
+    from paper_1304_2017_amd import precond
+    out = []
+    g = torch.Generator(device="cuda").manual_seed(0)
+    model = precond.Preconditioner(seed=0)
+    for n in (128, 256):
+        x = torch.randn((16, n, n, n), device="cuda", generator=g).to(torch.bfloat16)
+        dy = torch.randn((16, n, n, n), device="cuda", generator=g).to(torch.bfloat16)
+        w = torch.randn((16, 16, 27), device="cuda", generator=g) * 0.1
+        b = torch.zeros((16,), device="cuda")
+        flop = 2.0 * n ** 3 * 16 * 16 * 27
+        t_f = time_op(lambda: precond.conv3d(x, w, b, relu=True), reps)
+        t_w = time_op(lambda: precond.conv3d_weight_grad(x, dy), reps)
+        x32 = x.float()
+        t_v = time_op(lambda: precond.conv3d(x32, w, b, relu=True), max(1, reps // 2))
+        v = torch.randn((n, n, n), device="cuda", generator=g)
+        t_m = time_op(lambda: model.forward(v), reps)
+        # activation traffic of one bf16 16 -> 16 layer: 16 channels in, 16 out
+        io_bytes = 2.0 * 2 * 16 * n ** 3
+        out.append(dict(
+            shape=f"{n}^3", flop_per_layer=flop,
+            fwd_ms=t_f * 1e3, fwd_tflops=flop / t_f / 1e12, fwd_frac_bf16_peak=flop / t_f / BF16_PEAK,
+            fwd_hbm_frac=io_bytes / t_f / HBM_PEAK,
+            wgrad_ms=t_w * 1e3, wgrad_tflops=flop / t_w / 1e12,
+            wgrad_frac_bf16_peak=flop / t_w / BF16_PEAK,
+            fp32_valu_fwd_ms=t_v * 1e3, fp32_valu_tflops=flop / t_v / 1e12,
+            network_forward_ms=t_m * 1e3))
+        log(f"[cnn] {n}^3: fwd {t_f * 1e3:.3f} ms ({flop / t_f / 1e12:.1f} TFLOP/s), wgrad "
+            f"{t_w * 1e3:.3f} ms, FP32 VALU fwd {t_v * 1e3:.2f} ms, network {t_m * 1e3:.2f} ms")
+        del x, dy, x32, v
+        torch.cuda.empty_cache()
+    print(json.dumps(dict(kernel="conv16_mfma_kernel / conv16_wgrad_mfma_kernel",
+                          peak_bf16_tflops=BF16_PEAK / 1e12, results=out)), flush=True)
+
+
 def matrix(reps):
     """H, H^T and FBP at the 256^3 workloads (2048 hemisphere and 8192 sphere
     transducers) and the paper's 210x210x440 / 64x90 shape, FP32 and BF16
@@ -400,6 +442,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=5, help="training epochs (--learned)")
     ap.add_argument("--sph", action="store_true",
                     help="time the spherical-voxel model H_sph and H_sph^T at 64^3 / 2048 / 256")
+    ap.add_argument("--cnn", action="store_true",
+                    help="time the BF16 16->16 convolutions on the matrix cores at 128^3 and 256^3")
     ap.add_argument("--eir", action="store_true",
                     help="time H, H^T with a 64-tap EIR and the deconvolution + FBP at 256^3")
     args = ap.parse_args()
@@ -423,6 +467,9 @@ def main():
         return
     if args.eir:
         eir_run(max(args.steps, 3))
+        return
+    if args.cnn:
+        cnn_run(max(args.steps, 3))
         return
     if args.sph:
         sph_run(max(args.steps, 3))
