@@ -41,6 +41,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube.txt")
+
+
 def kernel_sources_sha256():
     """Hash of the HIP/C++ sources the kernels are built from."""
     import hashlib
