@@ -170,13 +170,15 @@ def pls_run(cfg, iters):
     from paper_1304_2017_amd import recon, synth
     from paper_1304_2017_amd.oat import Plan
     if cfg == "c":
-        geom, _, u_np = synth.config_c(0)
+        geom, balls, u_np = synth.config_c(0)
         plan = Plan(geom, 0)
         u = torch.from_numpy(u_np.astype(np.float32)).cuda()
+        phantom = torch.from_numpy(synth.voxelise_balls(geom, balls).astype(np.float32)).cuda()
     else:
         geom, _, img = synth.config_e(0)
         plan = Plan(geom, 0)
-        clean = plan.project(torch.from_numpy(img).cuda())
+        phantom = torch.from_numpy(img).cuda()
+        clean = plan.project(phantom)
         torch.cuda.synchronize()
         gen = torch.Generator(device="cuda").manual_seed(0)
         u = clean + 0.01 * float(clean.abs().max()) * torch.randn(clean.shape, device="cuda",
@@ -192,11 +194,67 @@ def pls_run(cfg, iters):
         res = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters, storage=dt, track=True)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        f = plan.fbp(u.to(dt), out_dtype=dt)
         print(json.dumps(dict(workload=geom.name, storage=str(dt).split(".")[-1], iters=iters,
                               mu=mu, eps=eps, seconds=el, s_per_iter=el / iters,
+                              rmse=recon.rmse(res.image, phantom),
+                              fbp_rmse=recon.rmse(f.float(), phantom),
+                              phantom_rms=recon.rmse(torch.zeros_like(phantom), phantom),
                               residuals=[round(v, 6) for v in res.residuals],
                               objective=[float("%.8g" % v) for v in res.objective])), flush=True)
     plan.close()
+
+
+def paper_run(iters):
+    """The paper's simulation study at its shape (Sec. IV.A; Sec. V.B): the
+    210 x 210 x 440 grid at 0.14 mm, 9 Gaussian-blurred spheres, the
+    N-wave of the spheres blurred in time (FWHM 0.5 us) on 32x45, 64x45,
+    64x90 and 128x90 ring views at 65 mm, 1022 samples at 20 MHz from
+    17.5 us.  For each data set and for FP32 and BF16 operator storage: FBP
+    and PLS-Int (linear CG, mu = 0 as in the simulation study, `iters`
+    iterations from 0), their times and the RMSE of Sec. IV.A against the
+    phantom.  Prints one JSON line per data set and storage."""
+    import torch
+    from paper_1304_2017_amd import recon, synth
+    from paper_1304_2017_amd.oat import Plan
+    t0 = time.perf_counter()
+    _, balls, phantom = synth.config_p(0)
+    ph = torch.from_numpy(phantom).cuda()
+    log(f"[paper] phantom in {time.perf_counter() - t0:.1f} s")
+    for nr, nv in ((32, 45), (64, 45), (64, 90), (128, 90)):
+        geom = synth.config_p_rings(nr, nv)
+        u = torch.from_numpy(synth.config_p_data(geom, balls).astype(np.float32)).cuda()
+        t0 = time.perf_counter()
+        # the 128x90 table (~180 GB) needs more than the default 40% of the
+        # free memory: this run dedicates the device to the reconstruction
+        free, _ = torch.cuda.mem_get_info()
+        plan = Plan(geom, 0, segment_table=int(0.75 * free)) if nr * nv > 5760 else Plan(geom, 0)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        st = plan.stats()
+        for dt in (torch.float32, torch.bfloat16):
+            ud = u.to(dt)
+            f = plan.fbp(ud, out_dtype=dt)
+            t_fbp = time_op(lambda: plan.fbp(ud, out_dtype=dt), 3)
+            res = recon.pls_cg(plan, u, mu=0.0, iters=iters, storage=dt)
+            torch.cuda.synchronize()
+            per_it = (res.times[-1] - res.times[0]) / max(len(res.times) - 1, 1)
+            fresh = float((u - plan.project(res.image)).double().norm() / u.double().norm())
+            print(json.dumps(dict(
+                workload=geom.name, views=f"{nr}x{nv}", transducers=geom.n_det,
+                storage="f32" if dt == torch.float32 else "bf16",
+                fbp_ms=t_fbp * 1e3, fbp_rmse=recon.rmse(f.float(), ph),
+                pls_iterations=len(res.residuals) - 1, pls_s_per_iteration=per_it,
+                pls_rmse=recon.rmse(res.image, ph), pls_residual=res.residuals[-1],
+                pls_fresh_residual=fresh, phantom_rms=recon.rmse(torch.zeros_like(ph), ph),
+                plan_s=plan_s, segment_table_bytes=st["segment_table_bytes"],
+                arc_table_bytes=st["arc_table_bytes"])), flush=True)
+            log(f"[paper] {nr}x{nv} {dt}: FBP {t_fbp * 1e3:.1f} ms, PLS-Int {per_it:.3f} s/it, "
+                f"RMSE FBP {recon.rmse(f.float(), ph):.4f} PLS {recon.rmse(res.image, ph):.4f}")
+            del f, res, ud
+        plan.close()
+        del plan, u
+        torch.cuda.empty_cache()
 
 
 def learned_run(n_phantoms, epochs, iters):
@@ -272,11 +330,17 @@ def learned_run(n_phantoms, epochs, iters):
     def fresh(a):
         return float((u - plan.project(a.float().contiguous())).double().norm()) / unorm
 
+    phantom = torch.from_numpy(img).cuda()
+    f_fbp = plan.fbp(u)
+
     print(json.dumps(dict(
         workload=geom.name, data="H a_true + 1% noise, 60 seeded ellipsoids", mu=mu, eps=eps,
         plan=dict(segment_table_bytes=st["segment_table_bytes"],
                   arc_table_bytes=st["arc_table_bytes"]),
         r_star=r_star, targets=per_target,
+        rmse=dict(plain=recon.rmse(plain.image, phantom), learned=recon.rmse(learned.image, phantom),
+                  fbp=recon.rmse(f_fbp, phantom),
+                  phantom_rms=recon.rmse(torch.zeros_like(phantom), phantom)),
         plain=dict(iterations=len(plain.residuals) - 1, seconds=plain.times[-1],
                    fresh_residual=fresh(plain.image),
                    residuals=[round(v, 6) for v in plain.residuals],
@@ -445,6 +509,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=5, help="training epochs (--learned)")
     ap.add_argument("--sph", action="store_true",
                     help="time the spherical-voxel model H_sph and H_sph^T at 64^3 / 2048 / 256")
+    ap.add_argument("--paper", action="store_true",
+                    help="the paper's simulation: FBP and PLS-Int RMSE vs data amount at 210x210x440")
     ap.add_argument("--cnn", action="store_true",
                     help="time the BF16 16->16 convolutions on the matrix cores at 128^3 and 256^3")
     ap.add_argument("--eir", action="store_true",
@@ -473,6 +539,9 @@ def main():
         return
     if args.cnn:
         cnn_run(max(args.steps, 3))
+        return
+    if args.paper:
+        paper_run(args.iters if args.iters != 30 else 20)
         return
     if args.sph:
         sph_run(max(args.steps, 3))

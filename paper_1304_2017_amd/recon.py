@@ -21,12 +21,18 @@
 All operator applications run in the library's kernels on the GPU; the
 vector updates are torch device ops, and every inner product and norm of the
 CG recursion is accumulated in FP64.
+
+Both solvers can write their state every few iterations (`checkpoint`,
+`every`) and continue from such a file (`resume`); the continued run takes
+exactly the steps of an uninterrupted one.  `rmse` is the accuracy measure
+of Sec. IV.A.
 """
 from __future__ import annotations
 
+import os
 import time
 from dataclasses import dataclass, field
-from typing import List
+from typing import List, Optional
 
 import torch
 
@@ -92,6 +98,31 @@ def _dot(a: torch.Tensor, b: torch.Tensor) -> float:
     return float(torch.dot(a.reshape(-1).double(), b.reshape(-1).double()))
 
 
+def rmse(a: torch.Tensor, ref) -> float:
+    """Root mean square error of Sec. IV.A, sqrt((a - ref)^T (a - ref) / N),
+    accumulated in FP64 (ref: tensor or array of the same shape)."""
+    r = torch.as_tensor(ref, device=a.device).double()
+    d = a.double() - r
+    return float(torch.sqrt(torch.dot(d.reshape(-1), d.reshape(-1)) / d.numel()))
+
+
+def save_state(path: str, state: dict) -> None:
+    """Write a solver state (tensors, numbers, lists of numbers) with
+    torch.save, tensors on the CPU; written to a temporary file and renamed,
+    so a reader never sees a partial file."""
+    cpu = {k: (v.detach().cpu() if isinstance(v, torch.Tensor) else v) for k, v in state.items()}
+    tmp = path + ".tmp"
+    torch.save(cpu, tmp)
+    os.replace(tmp, path)
+
+
+def load_state(path: str, device) -> dict:
+    """Read a state written by save_state (weights_only: plain data only),
+    tensors moved to `device`."""
+    st = torch.load(path, map_location="cpu", weights_only=True)
+    return {k: (v.to(device) if isinstance(v, torch.Tensor) else v) for k, v in st.items()}
+
+
 @dataclass
 class PLSResult:
     image: torch.Tensor
@@ -100,22 +131,46 @@ class PLSResult:
     times: List[float] = field(default_factory=list)        # wall seconds to a_i (device synced)
 
 
-def pls_cg(plan, u: torch.Tensor, mu: float = 0.0, iters: int = 20,
-           track: bool = True) -> PLSResult:
-    """Linear CG for (H^T H + mu L^T L) a = H^T u, a_0 = 0 (Sec. IV.A-B)."""
+def pls_cg(plan, u: torch.Tensor, mu: float = 0.0, iters: int = 20, track: bool = True,
+           storage=torch.float32, checkpoint: Optional[str] = None, every: int = 0,
+           resume: Optional[str] = None) -> PLSResult:
+    """Linear CG for (H^T H + mu L^T L) a = H^T u, a_0 = 0 (Sec. IV.A-B).
+    One H and one H^T per iteration: the data residual u - H a is updated
+    with the H p of each step.  `storage` is the dtype of the operator inputs
+    and outputs (FP32 or BF16).  With `checkpoint` and `every` > 0 the state
+    is saved after every `every`-th iteration; `resume` continues from such a
+    file up to `iters` iterations in all."""
+    t0 = time.perf_counter()
+
+    def H(x):
+        return plan.project(x.to(storage).contiguous(), out_dtype=storage).float()
+
+    def HT(y):
+        return plan.backproject(y.to(storage).contiguous(), out_dtype=storage).float()
+
     u = u.float().contiguous()
     unorm = max(_dot(u, u) ** 0.5, 1e-300)
-    a = torch.zeros(plan.image_shape, device=u.device, dtype=torch.float32)
-    r = plan.backproject(u)                         # b - A a_0 with a_0 = 0
-    p = r.clone()
-    rr = _dot(r, r)
-    res = PLSResult(a)
-    if track:
-        res.residuals.append(1.0)
-        res.objective.append(unorm ** 2)
-    for _ in range(iters):
-        Hp = plan.project(p)
-        Ap = plan.backproject(Hp)
+    res = PLSResult(None)
+    if resume:
+        st = load_state(resume, u.device)
+        k0, a, r, p, s, rr = st["k"], st["a"], st["r"], st["p"], st["s"], st["rr"]
+        res.residuals, res.objective = list(st["residuals"]), list(st["objective"])
+        res.times = list(st["times"])
+        t0 -= res.times[-1] if res.times else 0.0
+    else:
+        k0 = 0
+        a = torch.zeros(plan.image_shape, device=u.device, dtype=torch.float32)
+        r = HT(u)                                     # b - A a_0 with a_0 = 0
+        p = r.clone()
+        s = u.clone()                                 # u - H a
+        rr = _dot(r, r)
+        if track:
+            res.residuals.append(1.0)
+            res.objective.append(unorm ** 2)
+            res.times.append(time.perf_counter() - t0)
+    for k in range(k0, iters):
+        Hp = H(p)
+        Ap = HT(Hp)
         if mu:
             Ap = Ap + mu * smoothness_normal(p)
         pAp = _dot(p, Ap)
@@ -123,15 +178,20 @@ def pls_cg(plan, u: torch.Tensor, mu: float = 0.0, iters: int = 20,
             break
         alpha = rr / pAp
         a = a + alpha * p
+        s = s - alpha * Hp
         r = r - alpha * Ap
         rr_new = _dot(r, r)
         p = r + (rr_new / rr) * p
         rr = rr_new
         if track:
-            d = u - plan.project(a)
-            dn = _dot(d, d)
+            dn = _dot(s, s)
             res.residuals.append(dn ** 0.5 / unorm)
             res.objective.append(dn + (mu * float(smoothness_penalty(a)) if mu else 0.0))
+            res.times.append(time.perf_counter() - t0)
+        if checkpoint and every > 0 and (k + 1) % every == 0:
+            save_state(checkpoint, dict(k=k + 1, a=a, r=r, p=p, s=s, rr=rr,
+                                        residuals=res.residuals, objective=res.objective,
+                                        times=res.times))
     res.image = a
     return res
 
@@ -174,23 +234,30 @@ def tv_eps(a: torch.Tensor, eps: float):
     return float(s.double().sum()), grad, w
 
 
-def _pls_tv_steps(plan, u: torch.Tensor, mu: float, eps: float, iters: int, storage):
-    """The PLS-TV recursion; yields (a, g, ||u - H a||^2, TV_eps(a)) for the
-    start a = 0 and after every iteration."""
+def _pls_tv_steps(plan, u: torch.Tensor, mu: float, eps: float, iters: int, storage,
+                  state: Optional[dict] = None):
+    """The PLS-TV recursion; yields (k, a, g, d, r, gg, ||u - H a||^2, TV_eps(a))
+    for the start a = 0 (k = 0) and after every iteration k.  `state` (from a
+    checkpoint: k, a, r, g, d, gg) continues a run after its iteration k."""
     def H(x):
         return plan.project(x.to(storage).contiguous(), out_dtype=storage).float()
 
     def HT(y):
         return plan.backproject(y.to(storage).contiguous(), out_dtype=storage).float()
 
-    a = torch.zeros(plan.image_shape, device=u.device, dtype=torch.float32)
-    r = u.clone()                                    # u - H a
-    tv, tg, w = tv_eps(a, eps)
-    g = -2.0 * HT(r) + mu * tg
-    d = -g
-    yield a, g, _dot(r, r), tv
-    gg = _dot(g, g)
-    for _ in range(iters):
+    if state is None:
+        k0 = 0
+        a = torch.zeros(plan.image_shape, device=u.device, dtype=torch.float32)
+        r = u.clone()                                # u - H a
+        tv, tg, w = tv_eps(a, eps)
+        g = -2.0 * HT(r) + mu * tg
+        d = -g
+        gg = _dot(g, g)
+        yield 0, a, g, d, r, gg, _dot(r, r), tv
+    else:
+        k0, a, r, g, d, gg = state["k"], state["a"], state["r"], state["g"], state["d"], state["gg"]
+        tv, tg, w = tv_eps(a, eps)
+    for k in range(k0, iters):
         Hd = H(d)
         dx, dy, dz = forward_diff(d)
         curv = float((w.double() * (dx * dx + dy * dy + dz * dz).double()).sum())
@@ -209,24 +276,38 @@ def _pls_tv_steps(plan, u: torch.Tensor, mu: float, eps: float, iters: int, stor
         if _dot(g_new, d) >= 0.0:
             d = -g_new
         g, gg = g_new, gg_new
-        yield a, g, _dot(r, r), tv
+        yield k + 1, a, g, d, r, gg, _dot(r, r), tv
 
 
 def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
-           storage=torch.float32, track: bool = True) -> PLSResult:
+           storage=torch.float32, track: bool = True, checkpoint: Optional[str] = None,
+           every: int = 0, resume: Optional[str] = None) -> PLSResult:
     """Nonlinear CG for min ||u - H a||^2 + mu TV_eps(a) from a = 0.
     `storage` is the dtype of the operator inputs and outputs (FP32 or BF16);
-    iterates and residuals are kept in FP32 and every inner product in FP64."""
+    iterates and residuals are kept in FP32 and every inner product in FP64.
+    With `checkpoint` and `every` > 0 the state is saved after every
+    `every`-th iteration; `resume` continues from such a file up to `iters`
+    iterations in all."""
     t0 = time.perf_counter()
     u = u.float().contiguous()
     unorm = max(_dot(u, u) ** 0.5, 1e-300)
     res = PLSResult(None)
-    for a, _, rn, tv in _pls_tv_steps(plan, u, mu, eps, iters, storage):
+    state = None
+    if resume:
+        state = load_state(resume, u.device)
+        res.residuals, res.objective = list(state["residuals"]), list(state["objective"])
+        res.times = list(state["times"])
+        res.image = state["a"]
+        t0 -= res.times[-1] if res.times else 0.0
+    for k, a, g, d, r, gg, rn, tv in _pls_tv_steps(plan, u, mu, eps, iters, storage, state):
         res.image = a
         if track:
             res.residuals.append(rn ** 0.5 / unorm)
             res.objective.append(rn + mu * tv)
             res.times.append(time.perf_counter() - t0)   # rn is an FP64 dot: the device is synced
+        if checkpoint and every > 0 and k > 0 and k % every == 0:
+            save_state(checkpoint, dict(k=k, a=a, r=r, g=g, d=d, gg=gg, residuals=res.residuals,
+                                        objective=res.objective, times=res.times))
     return res
 
 
@@ -235,5 +316,5 @@ def pls_tv_iterates(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 1
     """(a_k, g_k) for k = 0 .. iters-1 of `pls_tv` (iterate and objective
     gradient before step k)."""
     u = u.float().contiguous()
-    for k, (a, g, _, _) in enumerate(_pls_tv_steps(plan, u, mu, eps, iters - 1, storage)):
+    for _, a, g, _, _, _, _, _ in _pls_tv_steps(plan, u, mu, eps, iters - 1, storage):
         yield a, g

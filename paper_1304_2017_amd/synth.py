@@ -234,6 +234,17 @@ def nwave_balls(geom: Geometry, balls) -> np.ndarray:
     return out
 
 
+def blur_time(geom: Geometry, data: np.ndarray, fwhm: float) -> np.ndarray:
+    """Each transducer's samples convolved with a Gaussian of the given FWHM
+    (time units), sampled on the data grid and normalised to unit sum, zero
+    beyond the record (the simulation data of Sec. IV.A: the N-wave of
+    uniform spheres blurred in time like the phantom in space)."""
+    from scipy.ndimage import gaussian_filter1d
+    sigma = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0))) / geom.dt
+    return gaussian_filter1d(np.asarray(data, dtype=np.float64), sigma, axis=1, mode="constant",
+                             truncate=6.0)
+
+
 def gaussian_noise(rng: np.random.Generator, data: np.ndarray, rel: float) -> np.ndarray:
     """Additive white noise with sigma = rel * max|data|."""
     return data + rng.normal(scale=rel * float(np.max(np.abs(data))), size=data.shape)
@@ -355,6 +366,23 @@ def config_p_geometry():
     return Geometry(nx, ny, nz, dx, centred_origin(nx, dx), centred_origin(ny, dx),
                     centred_origin(nz, dx), xyz, 1022, 0.05, 17.5, 1.54, 1.0, area,
                     name="210x210x440 / 64x90 ring views / 1022 samples")
+
+
+def config_p_rings(n_rings: int, n_views: int):
+    """config_p_geometry with n_rings x n_views ring views: rings at
+    theta_n = (n + 1/2) pi / n_rings (full polar range, the paper's
+    theta_min = pi/256 at 128 rings) and n_views views over 2 pi."""
+    g = config_p_geometry()
+    xyz, area = ring_layout(n_rings, n_views, 65.0, math.pi / (2 * n_rings), math.pi / n_rings)
+    return Geometry(g.nx, g.ny, g.nz, g.dx, g.x0, g.y0, g.z0, xyz, g.n_t, g.dt, g.t0, g.c0, g.gamma,
+                    area, name=f"210x210x440 / {n_rings}x{n_views} ring views / 1022 samples")
+
+
+def config_p_data(geom: Geometry, balls) -> np.ndarray:
+    """The paper's simulated pressure for config_p's balls on `geom`: the
+    N-wave of the uniform balls blurred in time by a Gaussian of FWHM
+    0.5 us (0.77 mm at c0 = 1.54 mm/us, the phantom's blur)."""
+    return blur_time(geom, nwave_balls(geom, balls), 0.5)
 
 
 def config_p(seed: int = 0, dtype=np.float32):

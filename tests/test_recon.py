@@ -96,10 +96,24 @@ def test_pls_cg_matches_oracle_recursion(mu):
     res = recon.pls_cg(plan, torch.from_numpy(u).float().cuda(), mu=mu, iters=iters)
     gd = geom.as_dict()
 
+    def LtL(p):
+        # L^T L of the penalty R(a) = sum over axes of (a_n - a_{n - axis})^2,
+        # written out here in numpy
+        out = np.zeros_like(p)
+        for ax in range(3):
+            d = np.diff(p, axis=ax)
+            hi = [slice(None)] * 3
+            lo = [slice(None)] * 3
+            hi[ax] = slice(1, None)
+            lo[ax] = slice(None, -1)
+            out[tuple(hi)] += d
+            out[tuple(lo)] -= d
+        return out
+
     def A(p):
         out = ref.backproject(gd, ref.project(gd, p))
         if mu:
-            out = out + mu * recon.smoothness_normal(torch.from_numpy(p)).numpy()
+            out = out + mu * LtL(p)
         return out
     a = np.zeros(geom.shape)
     r = ref.backproject(gd, u)
@@ -204,6 +218,58 @@ def test_pls_tv_descends_to_the_minimiser():
     assert all(obj[i + 1] <= obj[i] * (1 + 1e-5) for i in range(len(obj) - 1))
     got, _ = F(res.image.double().numpy().ravel())
     assert got - opt.fun <= 1e-4 * opt.fun
+
+
+def test_checkpoint_resume_takes_the_same_steps(tmp_path):
+    """A run continued from a checkpoint takes exactly the steps of an
+    uninterrupted one (image, residuals and objective equal), for linear CG
+    and for PLS-TV; the state file is plain data (weights-only load)."""
+    shape = (4, 5, 6)
+    plan = _DensePlan(shape, 150, 5)
+    g = torch.Generator().manual_seed(7)
+    u = (plan.A @ torch.rand(int(np.prod(shape)), generator=g, dtype=torch.float64)).reshape(150, 1)
+    u = u.float()
+    ck = str(tmp_path / "cg.pt")
+    full = recon.pls_cg(plan, u, mu=0.05, iters=9)
+    part = recon.pls_cg(plan, u, mu=0.05, iters=6, checkpoint=ck, every=3)
+    st = torch.load(ck, weights_only=True)
+    assert st["k"] == 6 and torch.equal(st["a"], part.image)
+    cont = recon.pls_cg(plan, u, mu=0.05, iters=9, resume=ck)
+    assert torch.equal(cont.image, full.image)
+    assert cont.residuals == full.residuals and cont.objective == full.objective
+    ck2 = str(tmp_path / "tv.pt")
+    full = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=12)
+    recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=8, checkpoint=ck2, every=4)
+    assert torch.load(ck2, weights_only=True)["k"] == 8
+    cont = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=12, resume=ck2)
+    assert torch.equal(cont.image, full.image)
+    assert cont.residuals == full.residuals and cont.objective == full.objective
+    assert len(cont.times) == len(full.times) == 13
+
+
+def test_rmse_is_the_papers_definition():
+    a = torch.tensor([[1.0, 2.0], [3.0, 5.0]])
+    b = np.array([[1.0, 0.0], [3.0, 1.0]])
+    assert recon.rmse(a, b) == pytest.approx(((4.0 + 16.0) / 4.0) ** 0.5, rel=1e-15)
+
+
+@pytest.mark.gpu
+def test_fbp_rmse_single_precision_matches_the_oracle():
+    """Sec. V.B: single-precision FBP changes the RMSE against the phantom
+    negligibly.  FP32 FBP of the analytic N-wave of the 32^3 balls against
+    the FP64 oracle's, both measured against the balls' node samples."""
+    from oracle import ref
+    from paper_1304_2017_amd.oat import Plan
+    geom, balls, phantom = synth.config_small(0)
+    plan = Plan(geom, 0)
+    u = synth.nwave_balls(geom, balls).astype(np.float32)
+    f = plan.fbp(torch.from_numpy(u).cuda())
+    torch.cuda.synchronize()
+    f_ref = ref.fbp(geom.as_dict(), u.astype(np.float64))
+    e_gpu = recon.rmse(f.cpu(), phantom)
+    e_ref = float(np.sqrt(np.mean((f_ref - phantom) ** 2)))
+    _say(f"[gpu] FBP RMSE vs phantom: FP32 {e_gpu:.6e}, FP64 oracle {e_ref:.6e}")
+    assert abs(e_gpu - e_ref) <= 1e-4 * e_ref
 
 
 def _np_tv(a, eps):
