@@ -302,12 +302,53 @@ def _nodes(geom):
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)   # [N][3], flat index of [nz][ny][nx]
 
 
-def sph_project(geom, alpha, n_f, f_min, df, rows=None):
-    """Eq. (dis_sph) for point-like transducers (the surface integral over
-    S_q divided by S_q is its value at r_q):
-    u[q, l] = p0(f_l) sum_n alpha_n exp(-j 2 pi f_l d_qn / c0) / (2 pi d_qn),
-    d_qn = |r_q - r_n|.  alpha [nz][ny][nx] real -> u [Q][n_f] complex, or the
-    listed rows only."""
+def sph_face_points(geom, q, aperture):
+    """Quadrature of (1/S_q) times the surface integral over the face S_q in
+    the SIR of Eq. (dis_sph): (points [S][3], weights [S] summing to 1).
+
+    aperture None: point-like transducers, the single point r_q.  Else
+    (width, height, m): the face is the flat width x height rectangle (mm)
+    centred at r_q and normal to r_q, its width along the unit polar vector
+    e1 = (cos t cos p, cos t sin p, -sin t) and its height along
+    e2 = (sin p, -cos p, 0) of r_q = |r_q| (sin t cos p, sin t sin p, cos t),
+    sampled by the m x m Gauss-Legendre product rule (numpy's nodes and
+    weights on [-1, 1], scaled to the face)."""
+    rq = np.asarray(geom["det_xyz"], dtype=np.float64).reshape(-1, 3)[q]
+    if aperture is None:
+        return rq[None, :], np.ones(1)
+    w, h, m = aperture
+    dist = float(np.linalg.norm(rq))
+    t = np.arccos(rq[2] / dist)
+    p = np.arctan2(rq[1], rq[0])
+    e1 = np.array([np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)])
+    e2 = np.array([np.sin(p), -np.cos(p), 0.0])
+    x, wx = np.polynomial.legendre.leggauss(int(m))
+    pts, wts = [], []
+    for i in range(int(m)):
+        for j in range(int(m)):
+            pts.append(rq + 0.5 * w * x[i] * e1 + 0.5 * h * x[j] * e2)
+            wts.append(0.25 * wx[i] * wx[j])
+    return np.array(pts), np.array(wts)
+
+
+def sph_sir(geom, q, r, f, aperture=None):
+    """(1/S_q) h~_q(r, f) of Eq. (dis_sph) for points r [N][3] and frequencies
+    f [L]: the face average of exp(-j 2 pi f |r^s - r| / c0) / (2 pi |r^s - r|)
+    by sph_face_points' rule -> [L][N] complex."""
+    pts, wts = sph_face_points(geom, q, aperture)
+    f = np.asarray(f, dtype=np.float64)
+    out = np.zeros((f.size, r.shape[0]), dtype=np.complex128)
+    for ps, ws in zip(pts, wts):
+        d = np.linalg.norm(r - ps, axis=1)
+        out += ws * np.exp(-2j * np.pi * np.outer(f, d) / geom["c0"]) / (2 * np.pi * d)
+    return out
+
+
+def sph_project(geom, alpha, n_f, f_min, df, rows=None, aperture=None):
+    """Eq. (dis_sph): u[q, l] = p0(f_l) sum_n alpha_n (1/S_q) h~_q(r_n, f_l)
+    (sph_sir; point-like transducers for aperture None: exp(-j 2 pi f_l
+    d_qn / c0) / (2 pi d_qn), d_qn = |r_q - r_n|).  alpha [nz][ny][nx] real
+    -> u [Q][n_f] complex, or the listed rows only."""
     r = _nodes(geom)
     a = np.asarray(alpha, dtype=np.float64).ravel()
     f = sph_freqs(n_f, f_min, df)
@@ -316,17 +357,15 @@ def sph_project(geom, alpha, n_f, f_min, df, rows=None):
     qs = np.arange(rq.shape[0]) if rows is None else np.asarray(rows)
     u = np.zeros((qs.size, n_f), dtype=np.complex128)
     for i, q in enumerate(qs):
-        d = np.linalg.norm(r - rq[q], axis=1)
-        E = np.exp(-2j * np.pi * np.outer(f, d) / geom["c0"])          # [n_f][N]
-        u[i] = p0 * (E @ (a / (2 * np.pi * d)))
+        u[i] = p0 * (sph_sir(geom, q, r, f, aperture) @ a)
     return u
 
 
-def sph_backproject(geom, u, n_f, f_min, df, voxels=None):
-    """Eq. (sphbwd): [H^T u]_n = sum_{q,l} u[q,l] conj(p0(f_l)) conj(h_q(r_n, f_l)),
-    h_q(r_n, f) = exp(-j 2 pi f d_qn / c0) / (2 pi d_qn).  Returns its real
-    part [nz][ny][nx] (the image is real, so this is the adjoint of
-    sph_project over real images), or at the listed flat voxel indices."""
+def sph_backproject(geom, u, n_f, f_min, df, voxels=None, aperture=None):
+    """Eq. (sphbwd): [H^T u]_n = sum_{q,l} u[q,l] conj(p0(f_l)) conj((1/S_q) h~_q(r_n, f_l)).
+    Returns its real part [nz][ny][nx] (the image is real, so this is the
+    adjoint of sph_project over real images), or at the listed flat voxel
+    indices."""
     r = _nodes(geom)
     if voxels is not None:
         r = r[np.asarray(voxels)]
@@ -336,9 +375,7 @@ def sph_backproject(geom, u, n_f, f_min, df, voxels=None):
     u = np.asarray(u, dtype=np.complex128).reshape(rq.shape[0], n_f)
     out = np.zeros(r.shape[0], dtype=np.complex128)
     for q in range(rq.shape[0]):
-        d = np.linalg.norm(r - rq[q], axis=1)
-        Ec = np.exp(2j * np.pi * np.outer(f, d) / geom["c0"])          # conj of h's phase
-        out += ((u[q] * p0c) @ Ec) / (2 * np.pi * d)
+        out += (u[q] * p0c) @ np.conj(sph_sir(geom, q, r, f, aperture))
     if voxels is not None:
         return out.real
     return out.real.reshape(geom["nz"], geom["ny"], geom["nx"])

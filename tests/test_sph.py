@@ -72,6 +72,96 @@ def test_voxel_at_the_centre_of_a_transducer_sphere():
 
 
 # --------------------------------------------------------------------------
+# Finite transducer faces: the SIR as a surface integral over S_q
+# --------------------------------------------------------------------------
+def _face_geom():
+    g = synth.config_small(0)[0].as_dict()
+    return dict(g, nx=3, ny=4, nz=2)
+
+
+def _frame(rq):
+    d = np.linalg.norm(rq)
+    t, p = np.arccos(rq[2] / d), np.arctan2(rq[1], rq[0])
+    e1 = np.array([np.cos(t) * np.cos(p), np.cos(t) * np.sin(p), -np.sin(t)])
+    e2 = np.array([np.sin(p), -np.cos(p), 0.0])
+    return e1, e2, -rq / d
+
+
+def test_sir_tends_to_the_point_transducer():
+    """As the face shrinks, (1/S_q) h~_q tends to the point-like term."""
+    g = _face_geom()
+    r = np.array([[1.0, -2.0, 3.0], [0.0, 0.5, -4.0]])
+    f = np.array([0.3, 2.0, 5.0])
+    pt = ref.sph_sir(g, 7, r, f)
+    small = ref.sph_sir(g, 7, r, f, aperture=(1e-4, 1e-4, 4))
+    assert np.max(np.abs(small - pt)) <= 1e-7 * np.max(np.abs(pt))
+    # and a 2 mm face differs from it at 5 MHz (the finite-aperture effect)
+    big = ref.sph_sir(g, 7, r, f, aperture=(2.0, 2.0, 8))
+    assert np.max(np.abs(big[2] - pt[2])) > 1e-2 * np.max(np.abs(pt[2]))
+
+
+def test_sir_mirror_symmetries_of_the_face():
+    """A rectangle centred on r_q is symmetric under a -> -a and b -> -b:
+    sources mirrored across the planes (e3, e1) and (e3, e2) through r_q give
+    equal responses."""
+    g = _face_geom()
+    q = 11
+    rq = np.asarray(g["det_xyz"])[q]
+    e1, e2, e3 = _frame(rq)
+    base = rq + 20.0 * e3
+    r = np.array([base + 1.3 * e1 + 0.7 * e2, base + 1.3 * e1 - 0.7 * e2,
+                  base - 1.3 * e1 + 0.7 * e2])
+    h = ref.sph_sir(g, q, r, np.array([1.0, 4.5]), aperture=(2.0, 1.5, 6))
+    scale = np.max(np.abs(h))
+    assert np.max(np.abs(h[:, 0] - h[:, 1])) <= 1e-13 * scale
+    assert np.max(np.abs(h[:, 0] - h[:, 2])) <= 1e-13 * scale
+
+
+def test_sir_on_axis_matches_the_radial_integral():
+    """On the face's axis at distance z, with R = sqrt(z^2 + rho^2) and
+    rho drho = R dR, the integral is
+    (1/S) int_0^{2 pi} dphi/(2 pi) [exp(-j k z) - exp(-j k R_max(phi))] / (j k),
+    R_max = sqrt(z^2 + rho_max^2), rho_max(phi) = min(w/(2|cos|), h/(2|sin|)):
+    a 1-D integral done by adaptive quadrature, independent of the
+    oracle's 2-D product rule."""
+    from scipy.integrate import quad
+    g = _face_geom()
+    q = 3
+    rq = np.asarray(g["det_xyz"])[q]
+    _, _, e3 = _frame(rq)
+    w, h, z = 2.0, 1.2, 17.0
+    r = (rq + z * e3)[None, :]
+    c0 = g["c0"]
+    corner = np.arctan2(h, w)
+    for f in (0.5, 3.0, 5.0):
+        k = 2 * np.pi * f / c0
+
+        def integrand(phi, part):
+            c, s_ = abs(np.cos(phi)), abs(np.sin(phi))
+            rho = min(w / (2 * c) if c > 0 else np.inf, h / (2 * s_) if s_ > 0 else np.inf)
+            v = (np.exp(-1j * k * z) - np.exp(-1j * k * np.hypot(z, rho))) / (1j * k) / (2 * np.pi)
+            return v.real if part == 0 else v.imag
+        pts = [corner, np.pi - corner, np.pi + corner, 2 * np.pi - corner]
+        want = sum(quad(integrand, 0, 2 * np.pi, args=(i,), points=pts, epsabs=0,
+                        epsrel=1e-13, limit=200)[0] * (1j if i else 1) for i in (0, 1)) / (w * h)
+        got = ref.sph_sir(g, q, r, [f], aperture=(w, h, 20))[0, 0]
+        assert abs(got - want) <= 1e-10 * abs(want), (f, got, want)
+
+
+def test_sph_adjoint_identity_with_faces():
+    g = _face_geom()
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(2, 4, 3))
+    n_f, f0, df = 6, 0.4, 0.7
+    Q = np.asarray(g["det_xyz"]).shape[0]
+    u = rng.normal(size=(Q, n_f)) + 1j * rng.normal(size=(Q, n_f))
+    ap = (2.0, 2.0, 3)
+    lhs = float(np.real(np.sum(np.conj(u) * ref.sph_project(g, a, n_f, f0, df, aperture=ap))))
+    rhs = float(np.sum(a * ref.sph_backproject(g, u, n_f, f0, df, aperture=ap)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# --------------------------------------------------------------------------
 # The library's H_sph and H_sph^T against the oracle (GPU)
 # --------------------------------------------------------------------------
 gpu = pytest.mark.gpu
