@@ -231,9 +231,30 @@ int oat_sph_project(oat_plan *plan, const void *img, oat_dtype img_dtype, void *
                     double f_min, double df, uint32_t flags, void *stream);
 
 /* Eq. (sphbwd): img[n] = Re sum_{q,l} u~[q][l] conj(p0(f_l)) exp(+j 2 pi f_l d_qn / c0) / (2 pi d_qn),
- * the adjoint of oat_sph_project over real images.  Same arguments. */
+ * the adjoint of oat_sph_project over real images.  Same arguments.  With
+ * finite faces (oat_plan_set_aperture) both calls use (1/S_q) h~_q below in
+ * place of the point-like term. */
 int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, double df,
                         void *img, oat_dtype img_dtype, uint32_t flags, void *stream);
+
+/* Finite transducer faces for the spherical-voxel model (Sec. II.B.2): the
+ * SIR h~_q(r_n, f) of Eq. (dis_sph) is the integral over the face S_q of
+ * exp(-j 2 pi f |r^s - r_n| / c0) / (2 pi |r^s - r_n|), and the model uses
+ * (1/S_q) h~_q.  Every face is a flat width x height rectangle (mm) centred
+ * at r_q and normal to r_q, its width along the unit polar vector of r_q and
+ * its height along minus the unit azimuthal vector (the frame of G); the
+ * face average is the m x m Gauss-Legendre product rule, i.e. a weighted sum
+ * of the point-like terms of m^2 nodes, so a call costs m^2 times a
+ * point-like one.  width = height = 0 restores point-like transducers (m is
+ * then ignored).  Affects oat_sph_project, oat_sph_backproject and
+ * oat_sph_backproject_noalloc only; the interpolation model is
+ * point-like.  Synchronous: waits for the device, so no call on the plan may
+ * be in flight.  OAT_ERR_ARG for negative or non-finite sizes, one size 0
+ * and not the other, or m outside 1 .. OAT_APERTURE_MAX_ORDER;
+ * OAT_ERR_GEOMETRY when a face reaches into the sphere that holds the image
+ * support. */
+#define OAT_APERTURE_MAX_ORDER 8
+int oat_plan_set_aperture(oat_plan *plan, double width, double height, int m);
 
 /* oat_sph_backproject for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving loops and harnesses that forbid

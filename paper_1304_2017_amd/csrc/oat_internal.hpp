@@ -154,6 +154,11 @@ struct Problem {
     // 2 pi seg_ref_index(s) / nj of segment s of any ring of nj points.
     const double2 *segref;
     int n_rings, n_segref;  // entries of ring and segref (index clamps)
+    // Spherical-voxel model: each transducer's face as sph_ns quadrature
+    // nodes [nq][sph_ns], (x, y, z) in mm and the weight in w (the weights
+    // of a transducer sum to 1); point-like transducers: one node r_q, 1.
+    const double4 *sph_pts;
+    int sph_ns;
     // Segment table (null when the plan has none): the segments of unit u
     // that hold points owned by the brick are entries seg_off[u] ..
     // seg_off[u+1]-1, one 32-bit word each (seg_pack): the shell offset

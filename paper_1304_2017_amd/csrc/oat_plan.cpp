@@ -70,6 +70,10 @@ struct oat_plan {
     float *d_adjr = nullptr;     // [bricks][windows] G^T calibration
     double *d_fbp_thr = nullptr; // [K + 2] FBP floor thresholds (Problem::fbp_thr)
     double2 *d_segref = nullptr; // segment reference azimuths (Problem::segref)
+    double4 *d_sph_pts = nullptr; // transducer face nodes (Problem::sph_pts)
+    std::vector<DetRec> det;      // host copy of the transducer records
+    double ap_w = 0.0, ap_h = 0.0;   // face of oat_plan_set_aperture (0: point-like)
+    int ap_m = 0;
     long long *d_tab_off = nullptr;   // arc table (see Problem)
     unsigned *d_tab_run = nullptr;
     unsigned *d_tab_arc = nullptr;
@@ -92,6 +96,58 @@ struct oat_plan {
 };
 
 namespace {
+
+// Gauss-Legendre nodes x and weights w on [-1, 1] (m points): the roots of
+// P_m by Newton's method from cos(pi (i + 3/4) / (m + 1/2)), P_m and P_m'
+// from the three-term recurrence, w = 2 / ((1 - x^2) P_m'(x)^2).
+void gauss_legendre(int m, double *x, double *w)
+{
+    for (int i = 0; i < m; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p0 = 0.0;
+            for (int j = 1; j <= m; ++j) {
+                const double pm = p0;
+                p0 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p0 - (j - 1.0) * pm) / j;
+            }
+            dp = m * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) <= 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Face nodes of every transducer (see Problem::sph_pts): with m = 0 the
+// point r_q with weight 1; else the m x m Gauss-Legendre nodes of the
+// width x height rectangle centred at r_q, its width along the frame's e1
+// (polar direction) and height along e2, weights summing to 1.
+std::vector<double4> face_nodes(const std::vector<DetRec> &det, double width, double height, int m)
+{
+    const int S = m > 0 ? m * m : 1;
+    std::vector<double4> pts(det.size() * (size_t)S);
+    std::vector<double> x(m > 0 ? m : 1), w(m > 0 ? m : 1);
+    if (m > 0) gauss_legendre(m, x.data(), w.data());
+    for (size_t q = 0; q < det.size(); ++q) {
+        const DetRec &d = det[q];
+        if (m == 0) {
+            pts[q] = make_double4(d.r[0], d.r[1], d.r[2], 1.0);
+            continue;
+        }
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double a = 0.5 * width * x[i], b = 0.5 * height * x[j];
+                pts[q * S + i * m + j] =
+                    make_double4(d.r[0] + a * d.e1d[0] + b * d.e2d[0],
+                                 d.r[1] + a * d.e1d[1] + b * d.e2d[1],
+                                 d.r[2] + a * d.e1d[2] + b * d.e2d[2], 0.25 * w[i] * w[j]);
+            }
+    }
+    return pts;
+}
 
 // Arc table of a plan (see Problem): the count pass, an exclusive prefix sum
 // of the per-unit counts on the host, the fill pass.  budget < 0: up to 40%
@@ -303,7 +359,7 @@ void oat_plan_destroy(oat_plan *plan)
                     plan->d_tab_off, plan->d_tab_run, plan->d_tab_arc, plan->d_seg_off,
                     plan->d_seg, plan->d_eir_h, plan->d_eir_spec, plan->d_eir_tw,
                     plan->d_eir_filt, plan->d_eirbuf, plan->d_sph_part, plan->d_fbp_thr,
-                    plan->d_segref};
+                    plan->d_segref, plan->d_sph_pts};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     (void)hipSetDevice(prev);
@@ -560,6 +616,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     const std::vector<double> fbp_thr = fbp_floor_thresholds(g->c0, g->t0, g->dt, K);
     size_t thr_b = sizeof(double) * fbp_thr.size();
     size_t segref_b = sizeof(double2) * segref.size();
+    const std::vector<double4> faces = face_nodes(det, 0.0, 0.0, 0);
+    size_t faces_b = sizeof(double4) * faces.size();
     if ((e = alloc((void **)&plan->d_det, det_b, "det")) != hipSuccess ||
         (e = alloc((void **)&plan->d_shell, sh_b, "shell")) != hipSuccess ||
         (e = alloc((void **)&plan->d_ring, ring_b, "ring")) != hipSuccess ||
@@ -570,7 +628,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = alloc((void **)&plan->d_rowmax, rowmax_b, "gp row max")) != hipSuccess ||
         (e = alloc((void **)&plan->d_adjr, adjr_b, "G^T calibration")) != hipSuccess ||
         (e = alloc((void **)&plan->d_fbp_thr, thr_b, "FBP floor thresholds")) != hipSuccess ||
-        (e = alloc((void **)&plan->d_segref, segref_b, "segment references")) != hipSuccess) {
+        (e = alloc((void **)&plan->d_segref, segref_b, "segment references")) != hipSuccess ||
+        (e = alloc((void **)&plan->d_sph_pts, faces_b, "transducer faces")) != hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMalloc");
         oat_plan_destroy(plan);
         (void)hipSetDevice(prev);
@@ -582,6 +641,8 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
         (e = hipMemcpy(plan->d_fbp_thr, fbp_thr.data(), thr_b, hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(plan->d_segref, segref.data(), segref_b, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(plan->d_sph_pts, faces.data(), faces_b, hipMemcpyHostToDevice)) !=
             hipSuccess) {
         int code = fail_hip(e, "oat_plan_create: hipMemcpy");
         oat_plan_destroy(plan);
@@ -596,6 +657,9 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.segref = plan->d_segref;
     P.n_rings = (int)ring.size();
     P.n_segref = (int)segref.size();
+    P.sph_pts = plan->d_sph_pts;
+    P.sph_ns = 1;
+    plan->det = det;
     P.adj_r = nullptr;
     P.tab_off = nullptr;
     P.tab_run = nullptr;
@@ -607,7 +671,7 @@ int oat_plan_create_ex(const oat_geometry *g, int device, const oat_plan_options
     P.seg_hist = nullptr;
     P.seg_flag = nullptr;
     plan->ws_bytes = (int64_t)(part_b + klo_b + gp_b + acc_b + rowmax_b);
-    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b + thr_b + segref_b);
+    plan->table_bytes = (int64_t)(det_b + sh_b + ring_b + adjr_b + thr_b + segref_b + faces_b);
     {
         // The segment table if it fits, else the arc table if that fits,
         // else neither (the kernels then bound the arcs themselves).
@@ -876,6 +940,50 @@ int oat_sph_backproject(oat_plan *plan, const void *u, int n_f, double f_min, do
                                           (hipStream_t)stream);
     (void)hipSetDevice(prev);
     if (e != hipSuccess) return fail_hip(e, "oat_sph_backproject: launch");
+    return OAT_OK;
+}
+
+int oat_plan_set_aperture(oat_plan *plan, double width, double height, int m)
+{
+    if (!plan) return fail(OAT_ERR_ARG, "oat_plan_set_aperture: null plan");
+    if (!(width >= 0.0) || !(height >= 0.0) || !std::isfinite(width) || !std::isfinite(height))
+        return fail(OAT_ERR_ARG, "oat_plan_set_aperture: width and height must be finite and >= 0");
+    const bool point = width == 0.0 && height == 0.0;
+    if (!point && (width <= 0.0 || height <= 0.0 || m < 1 || m > OAT_APERTURE_MAX_ORDER))
+        return fail(OAT_ERR_ARG, "oat_plan_set_aperture: need width, height > 0 and 1 <= m <= 8");
+    const double R = std::sqrt(0.25 * (width * width + height * height));
+    for (const DetRec &d : plan->det)
+        if (!point && !(R < std::sqrt(d.r[0] * d.r[0] + d.r[1] * d.r[1] + d.r[2] * d.r[2]) -
+                               (double)plan->P.r_sup * plan->P.dxd))
+            return fail(OAT_ERR_GEOMETRY,
+                        "oat_plan_set_aperture: a face reaches into the image support sphere");
+    const int mm = point ? 0 : m;
+    const std::vector<double4> faces = face_nodes(plan->det, width, height, mm);
+    int prev;
+    int rc = with_device(plan, prev);
+    if (rc) return rc;
+    // earlier calls may still read the old table
+    hipError_t e = hipDeviceSynchronize();
+    double4 *buf = nullptr;
+    if (e == hipSuccess) e = hipMalloc((void **)&buf, sizeof(double4) * faces.size());
+    if (e == hipSuccess)
+        e = hipMemcpy(buf, faces.data(), sizeof(double4) * faces.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (buf) (void)hipFree(buf);
+        (void)hipGetLastError();
+        (void)hipSetDevice(prev);
+        return fail_hip(e, "oat_plan_set_aperture");
+    }
+    (void)hipFree(plan->d_sph_pts);
+    plan->table_bytes += (int64_t)(sizeof(double4) * faces.size()) -
+                         (int64_t)(sizeof(double4) * plan->det.size() * (size_t)plan->P.sph_ns);
+    plan->d_sph_pts = buf;
+    plan->P.sph_pts = buf;
+    plan->P.sph_ns = point ? 1 : m * m;
+    plan->ap_w = point ? 0.0 : width;
+    plan->ap_h = point ? 0.0 : height;
+    plan->ap_m = mm;
+    (void)hipSetDevice(prev);
     return OAT_OK;
 }
 

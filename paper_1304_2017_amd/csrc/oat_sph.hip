@@ -96,25 +96,28 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
             sz[pos] = z;
             sa[pos] = a_n;
         }
-        // Per (transducer, voxel) values shared by the transducer's LB
-        // threads, formed once for SUB voxels at a time: tau = d/c0, the
-        // weight a/(2 pi d) and the frequency step exp(-j 2 pi df tau).
-        const int SUB = min(SPH_TILE, SPH_SHARE / QB);
-        for (int s0 = 0; s0 < cnt; s0 += SUB) {
-            const int m = min(SUB, cnt - s0);
+        // Per (transducer, voxel, face node) values shared by the
+        // transducer's LB threads, formed once for SUB (voxel, node) items at
+        // a time: tau = d/c0, the weight a w_node/(2 pi d) and the frequency
+        // step exp(-j 2 pi df tau); items run voxel-major.
+        const int NS = P.sph_ns;
+        const int SUB = min(SPH_TILE * NS, SPH_SHARE / QB);
+        for (int s0 = 0; s0 < cnt * NS; s0 += SUB) {
+            const int m = min(SUB, cnt * NS - s0);
             __syncthreads();
             for (int idx = t; idx < QB * m; idx += SPH_THREADS) {
-                const int ql = idx / m, jj = idx % m;
+                // item (voxel jj, face node fs) of transducer qq
+                const int ql = idx / m, it = s0 + idx % m;
+                const int jj = it / NS, fs = it - jj * NS;
                 const int qq = blockIdx.x * QB + ql;
                 double tq = 0.0, wq = 0.0;
                 float cz = 1.f, szs = 0.f;
                 if (qq < P.nq) {
-                    const DetRec &d = P.det[qq];
-                    const double vx = sx[s0 + jj] - d.r[0], vy = sy[s0 + jj] - d.r[1],
-                                 vz = sz[s0 + jj] - d.r[2];
+                    const double4 fp = P.sph_pts[(size_t)qq * NS + fs];
+                    const double vx = sx[jj] - fp.x, vy = sy[jj] - fp.y, vz = sz[jj] - fp.z;
                     const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
                     tq = dd * inv_c0;
-                    wq = (double)sa[s0 + jj] / (6.283185307179586 * dd);
+                    wq = (double)sa[jj] * fp.w / (6.283185307179586 * dd);
                     sincos_turns((float)frac_turn(df * tq), cz, szs);
                 }
                 stau[idx] = tq;
@@ -205,6 +208,7 @@ sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, d
     const double dfa = df * SPH_ANCHOR;
     const int n_fp = (n_f + SPH_ANCHOR - 1) / SPH_ANCHOR * SPH_ANCHOR;
     const int qt = max(1, SPH_VQ / n_fp);   // transducers per LDS tile (32 KB)
+    const int NS = P.sph_ns;                // face nodes per transducer
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
@@ -225,19 +229,21 @@ sph_adj_kernel(Problem P, const float2 *__restrict__ u, int n_f, double f_min, d
         }
         __syncthreads();
         if (nb >= N) continue;
-        for (int j = 0; j < nq; ++j) {
-            const DetRec &d = P.det[q0 + j];
+        for (int jf = 0; jf < nq * NS; ++jf) {
+            // transducer j, face node fs
+            const int j = jf / NS, fs = jf - j * NS;
+            const double4 fp = P.sph_pts[(size_t)(q0 + j) * NS + fs];
             float zr[NV], zi[NV];
             double ar[NV], ai[NV], gr[NV], gi[NV], rd[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double vx = x[v] - d.r[0], vy = y[v] - d.r[1], vz = z[v] - d.r[2];
+                const double vx = x[v] - fp.x, vy = y[v] - fp.y, vz = z[v] - fp.z;
                 const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
                 const double tau = dd * inv_c0;
                 sincos_turns((float)frac_turn(df * tau), zr[v], zi[v]);
                 sincos_turns_d(frac_turn(f_min * tau), ar[v], ai[v]);
                 sincos_turns_d(frac_turn(dfa * tau), gr[v], gi[v]);
-                rd[v] = 1.0 / (6.283185307179586 * dd);
+                rd[v] = fp.w / (6.283185307179586 * dd);
             }
             const float2 *vq = sv + j * n_fp;
             double part[NV];

@@ -31,7 +31,7 @@ OAT_FLAG_DETERMINISTIC = 2
 EXPORTED = ("oat_plan_create", "oat_plan_create_ex", "oat_plan_destroy", "oat_project",
             "oat_backproject", "oat_fbp", "oat_last_error", "oat_plan_stats",
             "oat_plan_set_eir", "oat_deconvolve", "oat_sph_project", "oat_sph_backproject",
-            "oat_sph_backproject_noalloc",
+            "oat_sph_backproject_noalloc", "oat_plan_set_aperture",
             # include/oat_cnn.h
             "oat_conv3d_forward", "oat_conv3d_backward_weight_workspace",
             "oat_conv3d_backward_weight", "oat_adam_step", "oat_mse_workspace", "oat_mse")
@@ -102,6 +102,8 @@ def lib():
         L.oat_sph_backproject.argtypes = [vp, vp, ctypes.c_int, d, d, vp, ctypes.c_int,
                                           ctypes.c_uint32, vp]
         L.oat_sph_backproject.restype = ctypes.c_int
+        L.oat_plan_set_aperture.argtypes = [vp, d, d, ctypes.c_int]
+        L.oat_plan_set_aperture.restype = ctypes.c_int
         L.oat_sph_backproject_noalloc.argtypes = L.oat_sph_backproject.argtypes
         L.oat_sph_backproject_noalloc.restype = ctypes.c_int
         L.oat_last_error.argtypes = []
@@ -294,6 +296,11 @@ class Plan:
                                          float(f_min), float(df), ctypes.c_void_p(out.data_ptr()),
                                          _dtype_code(out), 0, self._stream(stream)))
         return out
+
+    def set_aperture(self, width: float = 0.0, height: float = 0.0, m: int = 4):
+        """Finite width x height (mm) transducer faces for the spherical-voxel
+        model, m x m Gauss-Legendre nodes; (0, 0) restores point-like ones."""
+        _check(lib().oat_plan_set_aperture(self._h, float(width), float(height), int(m)))
 
     def sph_backproject_noalloc(self, u, f_min: float, df: float, out, stream=None):
         """Eq. (sphbwd) into the caller's `out` through the entry point that

@@ -330,3 +330,79 @@ def test_sph_adjoint_without_slices():
          f"adjoint {abs(lhs - rhs) / scale:.3e}")
     assert eT < 1e-5
     assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+@gpu
+@pytest.mark.parametrize("ap", [(2.0, 2.0, 4), (2.0, 1.2, 3), (0.5, 0.5, 1)])
+def test_sph_finite_faces(ap):
+    """H_sph and H_sph^T with flat rectangular faces (m x m Gauss-Legendre
+    nodes) against the oracle's face quadrature, the adjoint identity, and
+    the return to point-like transducers."""
+    from paper_1304_2017_amd.oat import Plan
+    geom = _small_geom()
+    plan = Plan(geom, 0, arc_table=False, segment_table=False)
+    gd = geom.as_dict()
+    n_f, f0, df = 40, 0.1, 0.12
+    rng = np.random.default_rng(int(ap[2]) * 10 + int(ap[1] * 10))
+    a = rng.uniform(0, 1, size=geom.shape).astype(np.float32).astype(np.float64)
+    a[rng.uniform(size=geom.shape) < 0.3] = 0.0
+    plan.set_aperture(*ap)
+    x = torch.from_numpy(a).float().cuda()
+    u = plan.sph_project(x, n_f, f0, df)
+    y = (rng.normal(size=(geom.n_det, n_f)) + 1j * rng.normal(size=(geom.n_det, n_f)))
+    y = y.astype(np.complex64)
+    yd = torch.from_numpy(y).cuda()
+    b = plan.sph_backproject(yd, f0, df)
+    torch.cuda.synchronize()
+    e = rel(u.cpu().numpy(), ref.sph_project(gd, a, n_f, f0, df, aperture=ap))
+    eT = rel(b.double().cpu().numpy(),
+             ref.sph_backproject(gd, y.astype(np.complex128), n_f, f0, df, aperture=ap))
+    lhs = float(np.real(np.vdot(y.astype(np.complex128), u.cpu().numpy().astype(np.complex128))))
+    rhs = float(np.dot(a.ravel(), b.double().cpu().numpy().ravel()))
+    scale = float(np.linalg.norm(u.cpu().numpy()) * np.linalg.norm(y))
+    # the faces change the model: compare with point-like transducers
+    plan.set_aperture(0.0, 0.0)
+    u0 = plan.sph_project(x, n_f, f0, df)
+    torch.cuda.synchronize()
+    e0 = rel(u0.cpu().numpy(), ref.sph_project(gd, a, n_f, f0, df))
+    d0 = rel(u.cpu().numpy(), u0.cpu().numpy())
+    _say(f"[gpu] H_sph faces {ap}: rel {e:.3e}, H_sph^T rel {eT:.3e}, adjoint "
+         f"{abs(lhs - rhs) / scale:.3e}; point-like again rel {e0:.3e} (faces vs point {d0:.2e})")
+    assert e < 1e-5 and eT < 1e-5 and e0 < 1e-5
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    if ap[2] == 1:
+        assert d0 == 0.0      # one Gauss node is the face centre: the point-like model
+    else:
+        assert d0 > 1e-4
+
+
+@gpu
+def test_sph_faces_without_slices_and_arguments():
+    """Faces on the single-pass adjoint (2^19 voxels, no slices): sampled
+    voxels against the oracle; and the argument checks."""
+    from paper_1304_2017_amd import oat
+    from paper_1304_2017_amd.oat import Plan
+    nx, ny, nz, dx = 128, 64, 64, 0.4
+    geom = synth.Geometry(nx, ny, nz, dx, synth.centred_origin(nx, dx), synth.centred_origin(ny, dx),
+                          synth.centred_origin(nz, dx), synth.fibonacci_sphere(48, 40.0), 256, 0.05,
+                          0.0, 1.5, 1.0)
+    plan = Plan(geom, 0, arc_table=False, segment_table=False)
+    L = oat.lib()
+    assert L.oat_plan_set_aperture(plan._h, -1.0, 1.0, 2) == oat.OAT_ERR_ARG
+    assert L.oat_plan_set_aperture(plan._h, 1.0, 0.0, 2) == oat.OAT_ERR_ARG
+    assert L.oat_plan_set_aperture(plan._h, 1.0, 1.0, 0) == oat.OAT_ERR_ARG
+    assert L.oat_plan_set_aperture(plan._h, 1.0, 1.0, 9) == oat.OAT_ERR_ARG
+    assert L.oat_plan_set_aperture(plan._h, 30.0, 30.0, 2) == oat.OAT_ERR_GEOMETRY
+    ap = (2.0, 2.0, 2)
+    plan.set_aperture(*ap)
+    n_f, f0, df = 24, 0.2, 0.2
+    rng = np.random.default_rng(9)
+    y = (rng.normal(size=(geom.n_det, n_f)) + 1j * rng.normal(size=(geom.n_det, n_f))).astype(np.complex64)
+    b = plan.sph_backproject(torch.from_numpy(y).cuda(), f0, df)
+    torch.cuda.synchronize()
+    vox = rng.choice(geom.n_vox, 40, replace=False)
+    eT = rel(b.double().cpu().numpy().ravel()[vox],
+             ref.sph_backproject(geom.as_dict(), y.astype(np.complex128), n_f, f0, df, voxels=vox,
+                                 aperture=ap))
+    _say(f"[gpu] H_sph^T faces 128x64x64 (one slice) voxels rel {eT:.3e}")
+    assert eT < 1e-5
