@@ -383,31 +383,43 @@ def eir_run(reps):
 
 
 def sph_run(reps):
-    """The spherical-voxel model at its workload (64^3, 2048 transducers,
-    256 frequencies in (0, 5] MHz): H_sph and H_sph^T times, terms per
-    second, and the fraction of the VALU peak at 6 operations per term (a
-    complex rotation and a weighted complex add); one JSON line."""
+    """The spherical-voxel model (25.6 mm field of view, 2048 hemisphere
+    transducers, 256 frequencies in (0, 5] MHz) at 64^3 and 128^3, with
+    point-like transducers and with 2 x 2 mm faces (4 x 4 Gauss-Legendre
+    nodes, Sec. IV.B's transducer size): H_sph and H_sph^T times, terms per
+    second (one term = one (voxel, frequency, face node) of one transducer)
+    and the fraction of the VALU peak at 6 operations per term (a complex
+    rotation and a weighted complex add).  One JSON line per case."""
     import torch
     from paper_1304_2017_amd import synth
     from paper_1304_2017_amd.oat import Plan
-    geom, img = synth.config_sph()
-    plan = Plan(geom, 0)
     n_f, df = 256, 5.0 / 256
-    x = torch.from_numpy(img).cuda()
-    u = torch.empty((geom.n_det, n_f), device="cuda", dtype=torch.complex64)
-    a = torch.empty(plan.image_shape, device="cuda")
-    t_f = time_op(lambda: plan.sph_project(x, n_f, df, df, out=u), reps)
-    t_b = time_op(lambda: plan.sph_backproject(u, df, df, out=a), reps)
-    nnz = int(np.count_nonzero(img))
-    terms_f = float(nnz) * geom.n_det * n_f
-    terms_b = float(geom.n_vox) * geom.n_det * n_f
-    peak = VALU_PEAK
-    print(json.dumps(dict(
-        workload="64^3 (0.4 mm), 2048 hemisphere transducers, 256 frequencies f_l = (l+1) * 5/256 MHz",
-        H_sph_ms=t_f * 1e3, H_sph_T_ms=t_b * 1e3, nonzero_voxels=nnz, voxels=geom.n_vox,
-        H_sph_terms_per_s=terms_f / t_f, H_sph_T_terms_per_s=terms_b / t_b,
-        H_sph_valu_frac=6 * terms_f / t_f / peak, H_sph_T_valu_frac=6 * terms_b / t_b / peak,
-        reps=reps)), flush=True)
+    for n in (64, 128):
+        geom, img = synth.config_sph(n=n)
+        plan = Plan(geom, 0, arc_table=False, segment_table=False)
+        x = torch.from_numpy(img).cuda()
+        u = torch.empty((geom.n_det, n_f), device="cuda", dtype=torch.complex64)
+        a = torch.empty(plan.image_shape, device="cuda")
+        nnz = int(np.count_nonzero(img))
+        for face in ((0.0, 0.0, 1), (2.0, 2.0, 4)):
+            plan.set_aperture(*face)
+            nodes = face[2] ** 2 if face[0] > 0 else 1
+            t_f = time_op(lambda: plan.sph_project(x, n_f, df, df, out=u), reps)
+            t_b = time_op(lambda: plan.sph_backproject(u, df, df, out=a), reps)
+            terms_f = float(nnz) * geom.n_det * n_f * nodes
+            terms_b = float(geom.n_vox) * geom.n_det * n_f * nodes
+            print(json.dumps(dict(
+                workload=f"{n}^3 ({25.6 / n:.2f} mm), 2048 hemisphere transducers, 256 frequencies "
+                         "f_l = (l+1) * 5/256 MHz",
+                faces="point-like" if nodes == 1 else f"{face[0]} x {face[1]} mm, {face[2]}x{face[2]} nodes",
+                H_sph_ms=t_f * 1e3, H_sph_T_ms=t_b * 1e3, nonzero_voxels=nnz, voxels=geom.n_vox,
+                H_sph_terms_per_s=terms_f / t_f, H_sph_T_terms_per_s=terms_b / t_b,
+                H_sph_valu_frac=6 * terms_f / t_f / VALU_PEAK,
+                H_sph_T_valu_frac=6 * terms_b / t_b / VALU_PEAK, reps=reps)), flush=True)
+            log(f"[sph] {n}^3 faces {face}: H_sph {t_f * 1e3:.1f} ms, H_sph^T {t_b * 1e3:.1f} ms")
+        plan.close()
+        del plan, x, u, a
+        torch.cuda.empty_cache()
 
 
 def cnn_run(reps):

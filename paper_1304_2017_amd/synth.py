@@ -287,18 +287,18 @@ def config_large(seed: int = 0, dtype=np.float32):
     return geom, ells, voxelise_ellipsoids(geom, ells, dtype=dtype)
 
 
-def config_sph(seed: int = 0, dtype=np.float32):
+def config_sph(seed: int = 0, dtype=np.float32, n: int = 64):
     """The spherical-voxel model's workload: the 25.6 mm field of view and
-    2048-transducer hemisphere of config_large_geometry at 64^3 nodes
-    (0.4 mm voxels), 40 seeded ellipsoids as in config_large.  (The dense
-    frequency-domain sum costs n_det x n_f x voxels terms, so the voxel
-    count is kept moderate.)"""
-    n, dx = 64, 0.4
+    2048-transducer hemisphere of config_large_geometry at n^3 nodes
+    (0.4 mm voxels at the default 64^3), 40 seeded ellipsoids as in
+    config_large.  (The dense frequency-domain sum costs
+    n_det x n_f x voxels terms, so the voxel count is kept moderate.)"""
+    dx = 25.6 / n
     o = centred_origin(n, dx)
     Q, Rs = 2048, 40.0
     geom = Geometry(n, n, n, dx, o, o, o, fibonacci_hemisphere(Q, Rs), 1024, 0.05, 0.0, 1.5, 1.0,
                     np.full(Q, 2.0 * math.pi * Rs * Rs / Q),
-                    name="64^3 / 2048 transducers (spherical voxels)")
+                    name=f"{n}^3 / 2048 transducers (spherical voxels)")
     rng = np.random.default_rng(seed)
     ells = random_ellipsoids(rng, 40, geom, 0.3, 3.0, 0.0, 1.0)
     return geom, voxelise_ellipsoids(geom, ells, dtype=dtype)
