@@ -179,35 +179,61 @@ conv16_mfma_kernel(const unsigned short *__restrict__ x, int D, int H, int W,
 {
     // halo tile, channel-last: [z][y][x][ci], 32 bytes per voxel
     __shared__ __attribute__((aligned(16))) unsigned short xs[TI3 * 16];
+    // B fragments of the 14 steps, one 16-byte entry per lane: [step][lane]
+    __shared__ __attribute__((aligned(16))) unsigned bfrag[MF_KSTEPS][64][4];
     const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
     const size_t plane = (size_t)H * W, vol = plane * D;
-    for (int i = threadIdx.x; i < 16 * TI3; i += MF_THREADS) {
-        const int ci = i / TI3, r = i - ci * TI3;
-        const int zz = r / (TI * TI), yy = (r / TI) % TI, xx = r % TI;
-        const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-        unsigned short v = 0;
-        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = x[ci * vol + gz * plane + (size_t)gy * W + gx];
-        xs[r * 16 + ci] = v;
+    // Weights: entry (s, lane, e) holds the BF16 pair of channels
+    // ci0 + 2e, ci0 + 2e + 1 of column co = lane % 16, tap 2 s + (lane / 16 >> 1),
+    // ci0 = ((lane / 16) & 1) 8.
+    for (int i = threadIdx.x; i < MF_KSTEPS * 64 * 4; i += MF_THREADS) {
+        const int e = i & 3, ln = (i >> 2) & 63, st = i >> 8;
+        const int co = ln & 15, g = ln >> 4;
+        const int tap = 2 * st + (g >> 1), ci = (g & 1) * 8 + 2 * e;
+        const float lo = tap < 27 ? wt[(co * 16 + ci) * 27 + tap] : 0.f;
+        const float hi = tap < 27 ? wt[(co * 16 + ci + 1) * 27 + tap] : 0.f;
+        bfrag[st][ln][e] = bf16_bits(lo) | (bf16_bits(hi) << 16);
+    }
+    // Halo rows (ci, z, y): x0 - 1 .. x0 + 8.  The middle 8 come in one
+    // 16-byte load when the row lies inside the volume and is 16-byte
+    // aligned; the two ends and edge rows element by element.
+    const bool vec_ok = x0 + TT <= W && (W % 8) == 0 && ((uintptr_t)x % 16) == 0;
+    for (int r = threadIdx.x; r < 16 * TI * TI; r += MF_THREADS) {
+        const int ci = r / (TI * TI), zy = r - ci * TI * TI;
+        const int zz = zy / TI, yy = zy - zz * TI;
+        const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
+        unsigned short v[TI];
+#pragma unroll
+        for (int k = 0; k < TI; ++k) v[k] = 0;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H) {
+            const unsigned short *row = x + ci * vol + gz * plane + (size_t)gy * W;
+            if (vec_ok) {
+                const u32x4 mid = *reinterpret_cast<const u32x4 *>(row + x0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v[1 + 2 * k] = (unsigned short)(mid[k] & 0xffffu);
+                    v[2 + 2 * k] = (unsigned short)(mid[k] >> 16);
+                }
+                if (x0 > 0) v[0] = row[x0 - 1];
+                if (x0 + TT < W) v[TI - 1] = row[x0 + TT];
+            } else {
+#pragma unroll
+                for (int k = 0; k < TI; ++k) {
+                    const int gx = x0 - 1 + k;
+                    if (gx >= 0 && gx < W) v[k] = row[gx];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TI; ++k) xs[(zy * TI + k) * 16 + ci] = v[k];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, g = lane >> 4;
-    // B fragments: column co = col, k = 8 g .. 8 g + 7 of each step, i.e.
-    // tap 2 s + (g >> 1), channels (g & 1) 8 .. + 7.
+    __syncthreads();
     bf16x8 bw[MF_KSTEPS];
 #pragma unroll
-    for (int s = 0; s < MF_KSTEPS; ++s) {
-        const int tap = 2 * s + (g >> 1), ci0 = (g & 1) * 8;
-        u32x4 pk;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float lo = tap < 27 ? wt[(col * 16 + ci0 + 2 * e) * 27 + tap] : 0.f;
-            const float hi = tap < 27 ? wt[(col * 16 + ci0 + 2 * e + 1) * 27 + tap] : 0.f;
-            pk[e] = bf16_bits(lo) | (bf16_bits(hi) << 16);
-        }
-        bw[s] = as_bf16x8(pk);
-    }
-    __syncthreads();
+    for (int s = 0; s < MF_KSTEPS; ++s)
+        bw[s] = as_bf16x8(*reinterpret_cast<const u32x4 *>(&bfrag[s][lane][0]));
     const float bcol = bias ? bias[col] : 0.f;
     for (int m = 0; m < 8; ++m) {
         // A row: voxel v of the tile; k = tap 2 s + (g >> 1), channels (g & 1) 8 ..
@@ -251,15 +277,43 @@ conv16_wgrad_mfma_kernel(const unsigned short *__restrict__ x, const unsigned sh
     __shared__ float bsum[16][16];
     const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
     const size_t plane = (size_t)H * W, vol = plane * D;
-    for (int i = threadIdx.x; i < 3 * 16 * TI * TI * TT; i += MF_THREADS) {
-        const int xx = i % TT, r = i / TT;
-        const int zy = r % (TI * TI), r2 = r / (TI * TI);
-        const int ci = r2 % 16, dx = r2 / 16;
-        const int gz = z0 - 1 + zy / TI, gy = y0 - 1 + zy % TI, gx = x0 - 1 + xx + dx;
-        unsigned short v = 0;
-        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = x[ci * vol + gz * plane + (size_t)gy * W + gx];
-        xs3[dx][ci][zy][xx] = v;
+    // Rows (ci, z, y) of the halo, x0 - 1 .. x0 + 8; copy dx holds
+    // x0 - 1 + dx .. x0 + 6 + dx.  The middle 8 come in one 16-byte load when
+    // the row lies inside the volume and is 16-byte aligned.
+    const bool vec_ok = x0 + TT <= W && (W % 8) == 0 && ((uintptr_t)x % 16) == 0;
+    for (int r = threadIdx.x; r < 16 * TI * TI; r += MF_THREADS) {
+        const int ci = r / (TI * TI), zy = r - ci * TI * TI;
+        const int gz = z0 - 1 + zy / TI, gy = y0 - 1 + zy % TI;
+        unsigned short v[TI];
+#pragma unroll
+        for (int k = 0; k < TI; ++k) v[k] = 0;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H) {
+            const unsigned short *row = x + ci * vol + gz * plane + (size_t)gy * W;
+            if (vec_ok) {
+                const u32x4 mid = *reinterpret_cast<const u32x4 *>(row + x0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v[1 + 2 * k] = (unsigned short)(mid[k] & 0xffffu);
+                    v[2 + 2 * k] = (unsigned short)(mid[k] >> 16);
+                }
+                if (x0 > 0) v[0] = row[x0 - 1];
+                if (x0 + TT < W) v[TI - 1] = row[x0 + TT];
+            } else {
+#pragma unroll
+                for (int k = 0; k < TI; ++k) {
+                    const int gx = x0 - 1 + k;
+                    if (gx >= 0 && gx < W) v[k] = row[gx];
+                }
+            }
+        }
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            u32x4 pk;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                pk[k] = (unsigned)v[dx + 2 * k] | ((unsigned)v[dx + 2 * k + 1] << 16);
+            *reinterpret_cast<u32x4 *>(&xs3[dx][ci][zy][0]) = pk;
+        }
     }
     for (int i = threadIdx.x; i < 16 * TT3; i += MF_THREADS) {
         const int co = i / TT3, v = i - co * TT3;
@@ -308,14 +362,28 @@ conv16_wgrad_mfma_kernel(const unsigned short *__restrict__ x, const unsigned sh
     }
 }
 
-// Sum the per-tile partials in tile order (deterministic).
-__global__ void sum_tiles_kernel(const float *__restrict__ part, int ntiles, int nj, int nw,
+// Partials per tile are summed in two fixed-order stages (deterministic):
+// groups of SUM_GROUP consecutive tiles, then the groups.
+constexpr int SUM_GROUP = 64;
+
+__global__ void sum_tile_groups_kernel(const float *__restrict__ part, int ntiles, int nj,
+                                       float *__restrict__ gsum)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nj) return;
+    const int t0 = blockIdx.y * SUM_GROUP, t1 = min(ntiles, t0 + SUM_GROUP);
+    float s = 0.f;
+    for (int t = t0; t < t1; ++t) s += part[(size_t)t * nj + j];
+    gsum[(size_t)blockIdx.y * nj + j] = s;
+}
+
+__global__ void sum_tiles_kernel(const float *__restrict__ gsum, int ngroups, int nj, int nw,
                                  float *__restrict__ dw, float *__restrict__ db)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nj) return;
     float s = 0.f;
-    for (int t = 0; t < ntiles; ++t) s += part[(size_t)t * nj + j];
+    for (int t = 0; t < ngroups; ++t) s += gsum[(size_t)t * nj + j];
     if (j < nw)
         dw[j] = s;
     else if (db)
@@ -421,7 +489,8 @@ size_t oat_conv3d_backward_weight_workspace(int c_in, int c_out, int d, int h, i
 {
     if (!ch_ok(c_in) || !ch_ok(c_out) || d < 1 || h < 1 || w < 1) return 0;
     dim3 g = tiles(d, h, w);
-    return sizeof(float) * (size_t)g.x * g.y * g.z * (size_t)(c_out * c_in * 27 + c_out);
+    const size_t nt = (size_t)g.x * g.y * g.z, ng = (nt + SUM_GROUP - 1) / SUM_GROUP;
+    return sizeof(float) * (nt + ng) * (size_t)(c_out * c_in * 27 + c_out);
 }
 
 int oat_conv3d_backward_weight(const void *x, oat_dtype xdt, const void *dy, oat_dtype dydt,
@@ -452,7 +521,13 @@ int oat_conv3d_backward_weight(const void *x, oat_dtype xdt, const void *dy, oat
     int rc = launched("oat_conv3d_backward_weight");
     if (rc) return rc;
     const int nw = c_out * c_in * 27, nj = nw + c_out, ntiles = (int)(g.x * g.y * g.z);
-    hipLaunchKernelGGL(sum_tiles_kernel, dim3((nj + 255) / 256), dim3(256), 0, s, part, ntiles, nj,
+    const int ngroups = (ntiles + SUM_GROUP - 1) / SUM_GROUP;
+    float *gsum = part + (size_t)ntiles * nj;
+    hipLaunchKernelGGL(sum_tile_groups_kernel, dim3((nj + 255) / 256, ngroups), dim3(256), 0, s,
+                       part, ntiles, nj, gsum);
+    rc = launched("oat_conv3d_backward_weight");
+    if (rc) return rc;
+    hipLaunchKernelGGL(sum_tiles_kernel, dim3((nj + 255) / 256), dim3(256), 0, s, gsum, ngroups, nj,
                        nw, dweight, dbias);
     return launched("oat_conv3d_backward_weight");
 }

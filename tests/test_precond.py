@@ -49,7 +49,7 @@ def test_cnn_abi_rejects_bad_arguments():
         == oat.OAT_ERR_ARG
     assert L.oat_conv3d_backward_weight_workspace(3, 16, 4, 4, 4) == 0
     need = L.oat_conv3d_backward_weight_workspace(16, 16, 9, 9, 9)
-    assert need == 4 * 8 * (16 * 16 * 27 + 16)           # 2^3 tiles
+    assert need == 4 * (8 + 1) * (16 * 16 * 27 + 16)     # 2^3 tiles and one group of them
     assert L.oat_conv3d_backward_weight(dummy, 0, dummy, 0, 16, 16, 9, 9, 9, dummy, None, dummy,
                                         need - 1, None) == oat.OAT_ERR_ARG
     assert L.oat_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None) \
