@@ -301,53 +301,79 @@ def learned_run(n_phantoms, epochs, iters):
     u = clean + 0.01 * float(clean.abs().max()) * torch.randn(clean.shape, device="cuda", generator=gen)
     eps = 1e-3
     mu = 1e-3 * float(u.double().pow(2).sum()) / (geom.n_vox * eps)
+    phantom = torch.from_numpy(img).cuda()
     recon.pls_tv(plan, u, mu=mu, eps=eps, iters=1)          # warm-up
     torch.cuda.synchronize()
-    plain = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters)
+    # image RMSE of every iterate, taken after its time is recorded
+    rmse_plain, rmse_learned = [], []
+    plain = recon.pls_tv(plan, u, mu=mu, eps=eps, iters=iters,
+                         observe=lambda k, a: rmse_plain.append(recon.rmse(a, phantom)))
     torch.cuda.synchronize()
     # targets: the plain residual after 5, 10, 20 and `iters` iterations
     marks = sorted({k for k in (5, 10, 20, iters) if k <= iters})
     targets = {k: plain.residuals[k] for k in marks}
     r_star = targets[iters]
     log(f"[learned] plain {iters} iterations {plain.times[-1]:.1f} s, r* = {r_star:.5f}")
-    learned = precond.pls_tv_learned(plan, u, model, mu=mu, eps=eps, iters=iters, target=r_star)
+    # The learned iteration runs `iters` iterations too (no early stop): its
+    # time to each target is the time of the first iterate below it, as if it
+    # had stopped there, and the later iterates show where it goes on to.
+    learned = precond.pls_tv_learned(plan, u, model, mu=mu, eps=eps, iters=iters,
+                                     observe=lambda k, a: rmse_learned.append(recon.rmse(a, phantom)))
     torch.cuda.synchronize()
 
-    def first(res, r):
-        k = next((i for i, v in enumerate(res.residuals) if v <= r), None)
-        return (k, res.times[k] if k is not None else None)
+    def first(vals, times, r):
+        k = next((i for i, v in enumerate(vals) if v <= r), None)
+        return (k, times[k] if k is not None else None)
 
-    per_target = []
-    for k, r in targets.items():
-        kp, tp = first(plain, r)
-        kl, tl_ = first(learned, r)
-        per_target.append(dict(plain_iterations_for_target=k, target=r, plain_iterations=kp,
-                               plain_s=tp, learned_iterations=kl, learned_s=tl_,
-                               speedup=(tp / tl_) if (tp and tl_) else None))
+    def compare(vals_p, vals_l, key):
+        out = []
+        for k in marks:
+            r = vals_p[k]
+            kp, tp = first(vals_p, plain.times, r)
+            kl, tl_ = first(vals_l, learned.times, r)
+            out.append({"plain_iterations_for_target": k, "target": r, "plain_iterations": kp,
+                        "plain_s": tp, "learned_iterations": kl, "learned_s": tl_,
+                        "speedup": (tp / tl_) if (tp and tl_) else None,
+                        "plain_rmse": rmse_plain[kp] if kp is not None else None,
+                        "learned_rmse": rmse_learned[kl] if kl is not None else None,
+                        "key": key})
+        return out
+
+    per_target = compare(plain.residuals, learned.residuals, "residual")
+    log(f"[learned] r* reached by the learned iteration at iterate "
+        f"{per_target[-1]['learned_iterations']} ({per_target[-1]['learned_s']} s)")
+    # the same comparison on the PLS-TV objective ||u - H a||^2 + mu TV_eps(a)
+    per_objective = compare(plain.objective, learned.objective, "objective")
     # the recursive residual checked by one fresh H on each final image
     unorm = float(u.double().norm())
 
     def fresh(a):
         return float((u - plan.project(a.float().contiguous())).double().norm()) / unorm
 
-    phantom = torch.from_numpy(img).cuda()
     f_fbp = plan.fbp(u)
 
     print(json.dumps(dict(
         workload=geom.name, data="H a_true + 1% noise, 60 seeded ellipsoids", mu=mu, eps=eps,
         plan=dict(segment_table_bytes=st["segment_table_bytes"],
                   arc_table_bytes=st["arc_table_bytes"]),
-        r_star=r_star, targets=per_target,
+        r_star=r_star, targets=per_target, objective_targets=per_objective,
         rmse=dict(plain=recon.rmse(plain.image, phantom), learned=recon.rmse(learned.image, phantom),
                   fbp=recon.rmse(f_fbp, phantom),
                   phantom_rms=recon.rmse(torch.zeros_like(phantom), phantom)),
         plain=dict(iterations=len(plain.residuals) - 1, seconds=plain.times[-1],
                    fresh_residual=fresh(plain.image),
                    residuals=[round(v, 6) for v in plain.residuals],
+                   objective=[float(v) for v in plain.objective],
+                   rmse=[round(v, 6) for v in rmse_plain],
                    times=[round(v, 4) for v in plain.times]),
         learned=dict(iterations=len(learned.residuals) - 1, seconds=learned.times[-1],
-                     reached=learned.residuals[-1] <= r_star, fresh_residual=fresh(learned.image),
+                     directions=[(k, round(c, 4)) for k, c in learned.directions],
+                     reached=min(learned.residuals) <= r_star,
+                     seconds_to_r_star=per_target[-1]["learned_s"],
+                     fresh_residual=fresh(learned.image),
                      residuals=[round(v, 6) for v in learned.residuals],
+                     objective=[float(v) for v in learned.objective],
+                     rmse=[round(v, 6) for v in rmse_learned],
                      times=[round(v, 4) for v in learned.times]),
         training=dict(workload=gd.name, phantoms=n_phantoms, pairs=n, epochs=epochs,
                       phantom_s=t_phantoms, pairs_s=t_pairs, train_s=t_train,

@@ -20,7 +20,7 @@ import ctypes
 import math
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import torch
 
@@ -201,10 +201,37 @@ def train(model: Preconditioner, pairs, epochs: int = 5, lr: float = 1e-3, seed:
     return log
 
 
+def _direction(cands, s: torch.Tensor, angle: float):
+    """The first candidate direction c (name, tensor) whose angle with the
+    steepest-descent direction s = -g is small enough,
+    <c, s> >= angle ||c|| ||s||, else s itself (a plain step).  Returns
+    (name, direction, cosine)."""
+    ss = recon._dot(s, s) ** 0.5
+    for name, c in cands:
+        cn = recon._dot(c, c) ** 0.5
+        cos = recon._dot(c, s) / max(cn * ss, 1e-300)
+        if cos >= angle:
+            return name, c, cos
+    return "plain", s, 1.0
+
+
 def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps: float,
-                   iters: int = 20, storage=torch.float32, target: Optional[float] = None):
-    """PLS-TV with the learned direction.  Stops after `iters` iterations or
-    once ||u - H a|| / ||u|| <= target.  Returns a recon.PLSResult."""
+                   iters: int = 20, storage=torch.float32, target: Optional[float] = None,
+                   observe: Optional[Callable[[int, torch.Tensor], None]] = None,
+                   switch: float = 0.4, powell: float = 0.2):
+    """PLS-TV with the learned direction: nonlinear CG on the same objective
+    and with the same line search as recon.pls_tv.  Its direction is
+    z + beta d, with z = the network applied to -g (scaled to unit RMS and
+    back) and beta = max(0, <z, s - s_prev> / <z_prev, s_prev>) (s = -g);
+    beta = 0 when successive gradients are far from orthogonal
+    (|<s, s_prev>| >= powell ||s||^2, Powell's restart).  A direction whose
+    cosine with -g is below `switch` is replaced by z alone; once z also
+    falls below it, the run goes on as the plain iteration (recon.pls_tv's
+    directions, beta of Polak-Ribiere, clipped at 0) to the end.  Stops after
+    `iters` iterations or once ||u - H a|| / ||u|| <= target.
+    `observe(k, a)` is called with every iterate; the recorded times leave
+    out its calls.  Returns a recon.PLSResult whose `directions` give each
+    step's direction ("cg", "learned" or "plain") and its cosine with -g."""
     t0 = time.perf_counter()
     u = u.float().contiguous()
     unorm = max(recon._dot(u, u) ** 0.5, 1e-300)
@@ -215,21 +242,28 @@ def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps:
     def HT(y):
         return plan.backproject(y.to(storage).contiguous(), out_dtype=storage).float()
 
+    def net(v):
+        sc = _rms(v)
+        return model.forward(v / sc).float() * sc
+
     a = torch.zeros(plan.image_shape, device=u.device, dtype=torch.float32)
     r = u.clone()
     tv, tg, w = recon.tv_eps(a, eps)
     g = -2.0 * HT(r) + mu * tg
     s = -g
-    zf = model.forward(s / _rms(s)).float() * _rms(s)
-    d = zf
+    z = net(s)
+    kind, d, cos = _direction([("learned", z)], s, switch)
     res = recon.PLSResult(a)
     res.residuals.append(1.0)
     res.objective.append(unorm ** 2 + mu * tv)
     res.times.append(time.perf_counter() - t0)
-    zs = recon._dot(zf, s)
+    if observe is not None:                           # not counted in the times
+        t_obs = time.perf_counter()
+        observe(0, a)
+        t0 += time.perf_counter() - t_obs
+    zs = recon._dot(z, s)
     for _ in range(iters):
-        if recon._dot(g, d) >= 0.0:
-            d = -g                                     # not a descent direction: plain step
+        res.directions.append((kind, cos))
         Hd = H(d)
         dx, dy, dz = recon.forward_diff(d)
         curv = float((w.double() * (dx * dx + dy * dy + dz * dz).double()).sum())
@@ -243,14 +277,30 @@ def pls_tv_learned(plan, u: torch.Tensor, model: Preconditioner, mu: float, eps:
         tv, tg, w = recon.tv_eps(a, eps)
         g = -2.0 * HT(r) + mu * tg
         s_new = -g
-        z_new = model.forward(s_new / _rms(s_new)).float() * _rms(s_new)
-        beta = max(0.0, recon._dot(z_new, s_new - s) / zs) if zs > 0 else 0.0
-        d = z_new + beta * d
-        s, zf, zs = s_new, z_new, recon._dot(z_new, s_new)
+        ss_new = recon._dot(s_new, s_new)
+        if kind == "plain":
+            ss = recon._dot(s, s)
+            beta = max(0.0, (ss_new - recon._dot(s_new, s)) / ss) if ss > 0 else 0.0
+            d = s_new + beta * d
+            if recon._dot(s_new, d) <= 0.0:
+                d = s_new
+            cos = recon._dot(d, s_new) / max((recon._dot(d, d) * ss_new) ** 0.5, 1e-300)
+        else:
+            z_new = net(s_new)
+            restart = abs(recon._dot(s_new, s)) >= powell * ss_new
+            beta = max(0.0, recon._dot(z_new, s_new - s) / zs) if zs > 0 and not restart else 0.0
+            cands = [("cg", z_new + beta * d)] if beta > 0.0 else []
+            kind, d, cos = _direction(cands + [("learned", z_new)], s_new, switch)
+            zs = recon._dot(z_new, s_new)
+        s = s_new
         rn = recon._dot(r, r)
         res.residuals.append(rn ** 0.5 / unorm)
         res.objective.append(rn + mu * tv)
         res.times.append(time.perf_counter() - t0)   # after FP64 dots: the device is synced
+        if observe is not None:
+            t_obs = time.perf_counter()
+            observe(len(res.residuals) - 1, a)
+            t0 += time.perf_counter() - t_obs
         if target is not None and res.residuals[-1] <= target:
             break
     res.image = a

@@ -32,7 +32,7 @@ from __future__ import annotations
 import os
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import torch
 
@@ -129,6 +129,7 @@ class PLSResult:
     residuals: List[float] = field(default_factory=list)    # ||u - H a_i|| / ||u||
     objective: List[float] = field(default_factory=list)    # ||u - H a_i||^2 + mu R(a_i)
     times: List[float] = field(default_factory=list)        # wall seconds to a_i (device synced)
+    directions: List[tuple] = field(default_factory=list)   # learned PLS-TV: (kind, cosine) per step
 
 
 def pls_cg(plan, u: torch.Tensor, mu: float = 0.0, iters: int = 20, track: bool = True,
@@ -281,13 +282,15 @@ def _pls_tv_steps(plan, u: torch.Tensor, mu: float, eps: float, iters: int, stor
 
 def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
            storage=torch.float32, track: bool = True, checkpoint: Optional[str] = None,
-           every: int = 0, resume: Optional[str] = None) -> PLSResult:
+           every: int = 0, resume: Optional[str] = None,
+           observe: Optional[Callable[[int, torch.Tensor], None]] = None) -> PLSResult:
     """Nonlinear CG for min ||u - H a||^2 + mu TV_eps(a) from a = 0.
     `storage` is the dtype of the operator inputs and outputs (FP32 or BF16);
     iterates and residuals are kept in FP32 and every inner product in FP64.
     With `checkpoint` and `every` > 0 the state is saved after every
     `every`-th iteration; `resume` continues from such a file up to `iters`
-    iterations in all."""
+    iterations in all.  `observe(k, a)` is called with every iterate; the
+    recorded times leave out its calls."""
     t0 = time.perf_counter()
     u = u.float().contiguous()
     unorm = max(_dot(u, u) ** 0.5, 1e-300)
@@ -305,6 +308,10 @@ def pls_tv(plan, u: torch.Tensor, mu: float, eps: float, iters: int = 20,
             res.residuals.append(rn ** 0.5 / unorm)
             res.objective.append(rn + mu * tv)
             res.times.append(time.perf_counter() - t0)   # rn is an FP64 dot: the device is synced
+        if observe is not None:                       # not counted in the times
+            t_obs = time.perf_counter()
+            observe(k, a)
+            t0 += time.perf_counter() - t_obs
         if checkpoint and every > 0 and k > 0 and k % every == 0:
             save_state(checkpoint, dict(k=k, a=a, r=r, g=g, d=d, gg=gg, residuals=res.residuals,
                                         objective=res.objective, times=res.times))

@@ -68,6 +68,97 @@ def test_adjoint_weights_give_the_transposed_convolution():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+class _DenseCG:
+    """A dense random H on the CPU with the Plan interface (solver tests)."""
+
+    def __init__(self, shape, m, seed):
+        g = torch.Generator().manual_seed(seed)
+        self.image_shape = shape
+        self.data_shape = (m, 1)
+        self.A = torch.randn((m, int(np.prod(shape))), generator=g, dtype=torch.float64) / m ** 0.5
+
+    def project(self, x, out_dtype=None):
+        return (self.A @ x.double().reshape(-1)).reshape(self.data_shape).to(x.dtype)
+
+    def backproject(self, y, out_dtype=None):
+        return (self.A.T @ y.double().reshape(-1)).reshape(self.image_shape).to(y.dtype)
+
+
+class _MapModel:
+    """Stands in for the network: z = f(x)."""
+
+    def __init__(self, f):
+        self.f = f
+
+    def forward(self, x):
+        return self.f(x)
+
+
+def _dense_problem():
+    shape = (4, 5, 6)
+    plan = _DenseCG(shape, 150, 11)
+    g = torch.Generator().manual_seed(12)
+    truth = torch.zeros(shape, dtype=torch.float64)
+    truth[1:3, 1:4, 2:5] = 1.0
+    u = plan.A @ truth.reshape(-1) + 0.01 * torch.randn(150, generator=g, dtype=torch.float64)
+    return plan, u.reshape(150, 1).float()
+
+
+def test_learned_iteration_with_switch_above_one_is_the_plain_iteration():
+    """No direction has a cosine above 1 with -g, so every step is the plain
+    one: the iterates are recon.pls_tv's, bit for bit."""
+    plan, u = _dense_problem()
+    model = _MapModel(lambda x: torch.flip(x, dims=[0]))
+    plain = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=15)
+    res = precond.pls_tv_learned(plan, u, model, mu=0.05, eps=0.1, iters=15, switch=1.5)
+    assert res.residuals == plain.residuals and res.objective == plain.objective
+    assert torch.equal(res.image, plain.image)
+    assert {k for k, _ in res.directions} == {"plain"}
+
+
+def test_learned_iteration_with_the_identity_network_is_polak_ribiere_cg():
+    """z = -g makes the learned beta <z, s - s_prev> / <z_prev, s_prev> the
+    Polak-Ribiere beta of the plain iteration; with no restarts and any
+    descent direction accepted the two runs agree to rounding."""
+    plan, u = _dense_problem()
+    model = _MapModel(lambda x: x.clone())
+    plain = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=15)
+    res = precond.pls_tv_learned(plan, u, model, mu=0.05, eps=0.1, iters=15, switch=1e-12,
+                                 powell=1e30)
+    assert len(res.objective) == len(plain.objective)
+    np.testing.assert_allclose(res.objective, plain.objective, rtol=1e-5)
+    assert _rel(res.image, plain.image) < 1e-4
+
+
+def test_learned_iteration_switches_to_plain_for_good():
+    """A network whose output drifts away from -g: the learned and CG steps
+    all keep a cosine of at least `switch` with -g, the first step below it
+    turns the run into the plain iteration to the end, and the objective
+    never rises."""
+    plan, u = _dense_problem()
+    g = torch.Generator().manual_seed(13)
+    fixed = torch.randn(plan.image_shape, generator=g)
+    fixed = fixed / fixed.pow(2).mean().sqrt()
+    model = _MapModel(lambda x: 0.3 * x + fixed)
+    res = precond.pls_tv_learned(plan, u, model, mu=0.05, eps=0.1, iters=20, switch=0.3)
+    kinds = [k for k, _ in res.directions]
+    assert "plain" in kinds and kinds[0] != "plain"
+    first = kinds.index("plain")
+    assert all(k == "plain" for k in kinds[first:])
+    assert all(c >= 0.3 for k, c in res.directions[:first])
+    obj = res.objective
+    assert all(obj[i + 1] <= obj[i] * (1 + 1e-6) for i in range(len(obj) - 1))
+
+
+def test_direction_takes_the_first_candidate_close_enough_to_steepest_descent():
+    s = torch.tensor([1.0, 0.0, 0.0])
+    far, near = torch.tensor([0.1, 1.0, 0.0]), torch.tensor([1.0, 1.0, 0.0])
+    name, d, cos = precond._direction([("cg", far), ("learned", near)], s, 0.5)
+    assert name == "learned" and torch.equal(d, near) and cos == pytest.approx(2 ** -0.5)
+    name, d, cos = precond._direction([("cg", far)], s, 0.5)
+    assert name == "plain" and torch.equal(d, s) and cos == 1.0
+
+
 gpu = pytest.mark.gpu
 
 
@@ -226,7 +317,7 @@ def test_training_lowers_the_loss():
 @gpu
 def test_learned_pls_tv_descends():
     """With any network the learned iteration keeps the objective decreasing
-    (non-descent directions fall back to the gradient)."""
+    (directions far from -g hand the run to the plain iteration)."""
     from paper_1304_2017_amd.oat import Plan
     _say("[gpu] learned PLS-TV")
     geom, balls, _ = synth.config_small(2)

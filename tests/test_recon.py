@@ -238,7 +238,11 @@ def test_checkpoint_resume_takes_the_same_steps(tmp_path):
     assert torch.equal(cont.image, full.image)
     assert cont.residuals == full.residuals and cont.objective == full.objective
     ck2 = str(tmp_path / "tv.pt")
-    full = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=12)
+    seen = []
+    full = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=12,
+                        observe=lambda k, a: seen.append((k, a.clone())))
+    assert [k for k, _ in seen] == list(range(13)) and torch.equal(seen[-1][1], full.image)
+    assert not seen[0][1].any()                       # the start a = 0
     recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=8, checkpoint=ck2, every=4)
     assert torch.load(ck2, weights_only=True)["k"] == 8
     cont = recon.pls_tv(plan, u, mu=0.05, eps=0.1, iters=12, resume=ck2)
