@@ -899,9 +899,20 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         }
         return v;
     };
-    for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
-        const int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
-        box[z * BOX_SZ + y * BOX_SY + x] = node(x, y, z);
+    // FP32 images: one node per word.  BF16 images: word x holds the BF16
+    // pair (node x, node x + 1), so a point's 8 corners are 4 words (2 reads).
+    if constexpr (IMG_DT == 0) {
+        for (int t = threadIdx.x; t < BOX * BOX * BOX; t += blockDim.x) {
+            const int x = t % BOX, y = (t / BOX) % BOX, z = t / (BOX * BOX);
+            box[z * BOX_SZ + y * BOX_SY + x] = node(x, y, z);
+        }
+    } else {
+        unsigned *bw = reinterpret_cast<unsigned *>(box);
+        for (int t = threadIdx.x; t < (BOX - 1) * BOX * BOX; t += blockDim.x) {
+            const int x = t % (BOX - 1), y = (t / (BOX - 1)) % BOX, z = t / ((BOX - 1) * BOX);
+            bw[z * BOX_SZ + y * BOX_SY + x] =
+                (__float_as_uint(node(x, y, z)) >> 16) | (__float_as_uint(node(x + 1, y, z)) & 0xffff0000u);
+        }
     }
     const int wave = threadIdx.x / WAVE;
     const int lane = lane_id();
@@ -918,11 +929,23 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         int klo = 0;
         float racc = 0.f;
         auto point = [&](const Pt &t, float) {
-            const float *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
-                              __umul24((unsigned)t.cy, BOX_SY) + t.cx;
-            const float *pz = pb + BOX_SZ;
-            const float v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
-            const float v100 = pz[0], v101 = pz[1], v110 = pz[BOX_SY], v111 = pz[BOX_SY + 1];
+            float v000, v001, v010, v011, v100, v101, v110, v111;
+            const unsigned off = __umul24((unsigned)t.cz, BOX_SZ) +
+                                 __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+            if constexpr (IMG_DT == 0) {
+                const float *pb = box + off;
+                const float *pz = pb + BOX_SZ;
+                v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
+                v100 = pz[0], v101 = pz[1], v110 = pz[BOX_SY], v111 = pz[BOX_SY + 1];
+            } else {
+                const unsigned *pb = reinterpret_cast<const unsigned *>(box) + off;
+                const unsigned *pz = pb + BOX_SZ;
+                const unsigned w00 = pb[0], w01 = pb[BOX_SY], w10 = pz[0], w11 = pz[BOX_SY];
+                v000 = __uint_as_float(w00 << 16), v001 = __uint_as_float(w00 & 0xffff0000u);
+                v010 = __uint_as_float(w01 << 16), v011 = __uint_as_float(w01 & 0xffff0000u);
+                v100 = __uint_as_float(w10 << 16), v101 = __uint_as_float(w10 & 0xffff0000u);
+                v110 = __uint_as_float(w11 << 16), v111 = __uint_as_float(w11 & 0xffff0000u);
+            }
             const float c00 = fmaf(t.fx, v001 - v000, v000), c01 = fmaf(t.fx, v011 - v010, v010);
             const float c10 = fmaf(t.fx, v101 - v100, v100), c11 = fmaf(t.fx, v111 - v110, v110);
             const float c0 = fmaf(t.fy, c01 - c00, c00), c1 = fmaf(t.fy, c11 - c10, c10);
