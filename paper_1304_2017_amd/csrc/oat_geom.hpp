@@ -230,15 +230,11 @@ OAT_HD void sincos_turns(float x, float &c, float &s)
                                       8.3333333e-3f), -1.6666667e-1f), 1.0f) * z;
     float cp = fmaf(z2, fmaf(z2, fmaf(z2, fmaf(z2, fmaf(z2, -2.7557319e-7f, 2.4801587e-5f),
                                                 -1.3888889e-3f), 4.1666667e-2f), -0.5f), 1.0f);
-    float cc, ss;
-    switch (q) {
-        case 0: cc = cp; ss = sp; break;
-        case 1: cc = -sp; ss = cp; break;
-        case 2: cc = -cp; ss = -sp; break;
-        default: cc = sp; ss = -cp; break;
-    }
-    c = cc;
-    s = ss;
+    // Quadrant q: (cp, sp) turned by q quarter turns (selects only).
+    const bool odd = (q & 1) != 0, neg = (q & 2) != 0;
+    const float cc = odd ? -sp : cp, ss = odd ? cp : sp;
+    c = neg ? -cc : cc;
+    s = neg ? -ss : ss;
 }
 
 // FP64 cos and sin of 2 pi x for x in [0, 1), to a few units in the last

@@ -132,14 +132,15 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
                 const float2 zs = sstep[row + jj];
                 float c, sn;
                 sincos_turns((float)frac_turn(fa * tau), c, sn);
-                // exp(-j theta) = (c, -sn)
-                float er = c, ei = -sn;
-                const float zr = zs.x, zi = zs.y;
+                // w exp(-j theta) = w (c, -sn), stepped by exp(-j dtheta) in
+                // FP64 (as fast as FP32 here, and no conversions per term)
+                double er = w * (double)c, ei = -(w * (double)sn);
+                const double zr = zs.x, zi = zs.y;
 #pragma unroll
                 for (int i = 0; i < SPH_FB; ++i) {
-                    ar[i] = fma(w, (double)er, ar[i]);
-                    ai[i] = fma(w, (double)ei, ai[i]);
-                    const float nr = er * zr - ei * zi, ni = er * zi + ei * zr;
+                    ar[i] += er;
+                    ai[i] += ei;
+                    const double nr = fma(er, zr, -(ei * zi)), ni = fma(er, zi, ei * zr);
                     er = nr;
                     ei = ni;
                 }

@@ -71,6 +71,18 @@ def small_bf16(request, Plan):
     return _small_case(request.param, Plan)
 
 
+def test_bf16_image_box_gives_the_fp32_result(small_bf16):
+    """G with a BF16 image keeps BF16 node pairs in its LDS box; the values
+    are the image's own, so G equals G of the same values stored in FP32,
+    bit for bit (both with the segment table, ragged bricks included)."""
+    geom, _, img, plan, seed = small_bf16
+    _say(f"[gpu] G bf16 pair box 32^3 seed {seed}")
+    xb = _t(img, torch.bfloat16)
+    gb = plan.project(xb, srt_only=True, out_dtype=torch.float32)
+    gf = plan.project(xb.float().contiguous(), srt_only=True, out_dtype=torch.float32)
+    assert torch.equal(gb, gf)
+
+
 def test_srt_only_matches_oracle(small):
     geom, _, img, plan, seed = small
     _say(f"[gpu] G 32^3 seed {seed}")
