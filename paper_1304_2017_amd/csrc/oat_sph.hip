@@ -24,7 +24,7 @@ namespace oat {
 namespace {
 
 constexpr int SPH_THREADS = 256;
-constexpr int SPH_FB = 16;       // frequencies per thread (forward)
+constexpr int SPH_FB = 32;       // frequencies per thread (forward)
 constexpr int SPH_TILE = 256;    // voxels staged per LDS tile (forward)
 constexpr int SPH_SHARE = 1024;  // (transducer, voxel) values shared per step (forward)
 constexpr int SPH_ANCHOR = 16;   // frequencies per Horner block (adjoint)
@@ -55,7 +55,7 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
     __shared__ float sa[SPH_TILE];
     __shared__ int wcnt[SPH_THREADS / 64];
     __shared__ double stau[SPH_SHARE], sw[SPH_SHARE];
-    __shared__ float2 sstep[SPH_SHARE];
+    __shared__ double2 sstep[SPH_SHARE];
     const int QB = SPH_THREADS / LB;
     const int t = threadIdx.x;
     const int q = blockIdx.x * QB + t / LB;
@@ -110,26 +110,25 @@ sph_fwd_kernel(Problem P, const void *__restrict__ img, int img_dt, int n_f, dou
                 const int ql = idx / m, it = s0 + idx % m;
                 const int jj = it / NS, fs = it - jj * NS;
                 const int qq = blockIdx.x * QB + ql;
-                double tq = 0.0, wq = 0.0;
-                float cz = 1.f, szs = 0.f;
+                double tq = 0.0, wq = 0.0, cz = 1.0, szs = 0.0;
                 if (qq < P.nq) {
                     const double4 fp = P.sph_pts[(size_t)qq * NS + fs];
                     const double vx = sx[jj] - fp.x, vy = sy[jj] - fp.y, vz = sz[jj] - fp.z;
                     const double dd = sqrt(fma(vz, vz, fma(vy, vy, vx * vx)));
                     tq = dd * inv_c0;
                     wq = (double)sa[jj] * fp.w / (6.283185307179586 * dd);
-                    sincos_turns((float)frac_turn(df * tq), cz, szs);
+                    sincos_turns_d(frac_turn(df * tq), cz, szs);
                 }
                 stau[idx] = tq;
                 sw[idx] = wq;
-                sstep[idx] = make_float2(cz, -szs);   // exp(-j dtheta)
+                sstep[idx] = make_double2(cz, -szs);   // exp(-j dtheta)
             }
             __syncthreads();
             if (!active) continue;
             const int row = (t / LB) * m;
             for (int jj = 0; jj < m; ++jj) {
                 const double tau = stau[row + jj], w = sw[row + jj];
-                const float2 zs = sstep[row + jj];
+                const double2 zs = sstep[row + jj];
                 float c, sn;
                 sincos_turns((float)frac_turn(fa * tau), c, sn);
                 // w exp(-j theta) = w (c, -sn), stepped by exp(-j dtheta) in
