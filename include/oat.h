@@ -221,7 +221,9 @@ int oat_deconvolve(oat_plan *plan, const void *u, oat_dtype u_dtype, void *p, oa
  * alpha_n is the voxel's absorbed-energy density; r_n are the plan's nodes.
  * img: device [nz][ny][nx] (oat_dtype); u: device [n_det][n_f] complex FP32,
  * interleaved (re, im).  Every term is evaluated (a dense sum); phases and
- * sums are FP64, exponentials FP32.  1 <= n_f <= 4096, f_min >= 0, df > 0,
+ * sums are FP64; each run of frequencies starts from an FP32 exponential
+ * (about 1 ulp) and steps it in FP64 (H_sph) or in FP32 (H_sph^T).
+ * 1 <= n_f <= 4096, f_min >= 0, df > 0,
  * flags: 0 or OAT_FLAG_DETERMINISTIC.  The two calls share a workspace in
  * the plan and may allocate or grow it: oat_sph_project for a larger n_f,
  * oat_sph_backproject for an image of fewer than 512K voxels, whose

@@ -7,9 +7,9 @@
 // Every (transducer, frequency, voxel) term is evaluated: a dense sum, bound
 // by the VALU.  Distances and phases are FP64 (a phase of hundreds of turns
 // must keep ~1e-7 turn); the complex exponentials are an accurate sincos of
-// the phase's fractional turn followed by short FP32 recurrences along l (a
-// rotation in the forward kernel, Horner's rule in the adjoint); sums are
-// FP64.
+// the phase's fractional turn followed by short recurrences along l (an FP64
+// rotation by an FP64 step in the forward kernel, FP32 Horner's rule in the
+// adjoint); sums are FP64.
 #include <mutex>
 #include <vector>
 
