@@ -172,94 +172,173 @@ __host__ __device__ constexpr int tap_off(int t) { return ((t / 9) * TI + (t / 3
 // Forward (and data backward) of a 16 -> 16 layer on BF16 activations.  A
 // workgroup owns an 8^3 output tile; each wave 128 of its voxels (8 row
 // blocks of 16), all 16 output channels.
+constexpr int MF_XS_BYTES = TI3 * 16 * 2;                  // halo tile, channel-last BF16
+constexpr int MF_BF_BYTES = MF_KSTEPS * 64 * 16;           // B fragments
+constexpr int MF_OS_BYTES = TT3 * 16 * 4;                  // output tile, FP32 [co][voxel]
+constexpr int MF_SMEM = MF_XS_BYTES + MF_BF_BYTES > MF_OS_BYTES ? MF_XS_BYTES + MF_BF_BYTES
+                                                                : MF_OS_BYTES;
+
 __global__ void __launch_bounds__(MF_THREADS)
 conv16_mfma_kernel(const unsigned short *__restrict__ x, int D, int H, int W,
                    const float *__restrict__ wt, const float *__restrict__ bias,
                    void *__restrict__ y, int ydt, int relu, const void *__restrict__ mask)
 {
-    // halo tile, channel-last: [z][y][x][ci], 32 bytes per voxel
-    __shared__ __attribute__((aligned(16))) unsigned short xs[TI3 * 16];
-    // B fragments of the 14 steps, one 16-byte entry per lane: [step][lane]
-    __shared__ __attribute__((aligned(16))) unsigned bfrag[MF_KSTEPS][64][4];
+    // halo tile, channel-last: [z][y][x][ci], 32 bytes per voxel, then the B
+    // fragments of the 14 steps, one 16-byte entry per lane: [step][lane];
+    // after the products, the output tile [co][voxel] in FP32 over both
+    __shared__ __attribute__((aligned(16))) unsigned char smem[MF_SMEM];
+    unsigned short *xs = reinterpret_cast<unsigned short *>(smem);
+    u32x4 *bfrag = reinterpret_cast<u32x4 *>(smem + MF_XS_BYTES);
+    float *os = reinterpret_cast<float *>(smem);
     const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
     const size_t plane = (size_t)H * W, vol = plane * D;
-    // Weights: entry (s, lane, e) holds the BF16 pair of channels
+    // Weights: entry (s, lane) holds in word e the BF16 pair of channels
     // ci0 + 2e, ci0 + 2e + 1 of column co = lane % 16, tap 2 s + (lane / 16 >> 1),
     // ci0 = ((lane / 16) & 1) 8.
-    for (int i = threadIdx.x; i < MF_KSTEPS * 64 * 4; i += MF_THREADS) {
-        const int e = i & 3, ln = (i >> 2) & 63, st = i >> 8;
+    for (int i = threadIdx.x; i < MF_KSTEPS * 64; i += MF_THREADS) {
+        const int ln = i & 63, st = i >> 6;
         const int co = ln & 15, g = ln >> 4;
-        const int tap = 2 * st + (g >> 1), ci = (g & 1) * 8 + 2 * e;
-        const float lo = tap < 27 ? wt[(co * 16 + ci) * 27 + tap] : 0.f;
-        const float hi = tap < 27 ? wt[(co * 16 + ci + 1) * 27 + tap] : 0.f;
-        bfrag[st][ln][e] = bf16_bits(lo) | (bf16_bits(hi) << 16);
+        const int tap = 2 * st + (g >> 1);
+        u32x4 f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ci = (g & 1) * 8 + 2 * e;
+            const float lo = tap < 27 ? wt[(co * 16 + ci) * 27 + tap] : 0.f;
+            const float hi = tap < 27 ? wt[(co * 16 + ci + 1) * 27 + tap] : 0.f;
+            f[e] = bf16_bits(lo) | (bf16_bits(hi) << 16);
+        }
+        bfrag[st * 64 + ln] = f;
     }
-    // Halo rows (ci, z, y): x0 - 1 .. x0 + 8.  The middle 8 come in one
-    // 16-byte load when the row lies inside the volume and is 16-byte
-    // aligned; the two ends and edge rows element by element.
+    // Halo rows (z, y), x0 - 1 .. x0 + 8, of a group of 8 channels: a
+    // thread reads the group's 8 rows (the middle 8 voxels in one 16-byte
+    // load when the row lies inside the volume and is 16-byte aligned, the
+    // two ends and edge rows element by element) and writes each of the 10
+    // voxels' 8 channels as one 16-byte word.
     const bool vec_ok = x0 + TT <= W && (W % 8) == 0 && ((uintptr_t)x % 16) == 0;
-    for (int r = threadIdx.x; r < 16 * TI * TI; r += MF_THREADS) {
-        const int ci = r / (TI * TI), zy = r - ci * TI * TI;
+    for (int r = threadIdx.x; r < 2 * TI * TI; r += MF_THREADS) {
+        const int cg = r / (TI * TI), zy = r - cg * TI * TI;
         const int zz = zy / TI, yy = zy - zz * TI;
         const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
-        unsigned short v[TI];
+        u32x4 w[TI];
 #pragma unroll
-        for (int k = 0; k < TI; ++k) v[k] = 0;
+        for (int k = 0; k < TI; ++k) w[k] = u32x4{0u, 0u, 0u, 0u};
         if (gz >= 0 && gz < D && gy >= 0 && gy < H) {
-            const unsigned short *row = x + ci * vol + gz * plane + (size_t)gy * W;
-            if (vec_ok) {
-                const u32x4 mid = *reinterpret_cast<const u32x4 *>(row + x0);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    v[1 + 2 * k] = (unsigned short)(mid[k] & 0xffffu);
-                    v[2 + 2 * k] = (unsigned short)(mid[k] >> 16);
-                }
-                if (x0 > 0) v[0] = row[x0 - 1];
-                if (x0 + TT < W) v[TI - 1] = row[x0 + TT];
-            } else {
+            for (int c = 0; c < 8; ++c) {
+                const unsigned short *row =
+                    x + (size_t)(cg * 8 + c) * vol + gz * plane + (size_t)gy * W;
+                unsigned v[TI];
 #pragma unroll
-                for (int k = 0; k < TI; ++k) {
-                    const int gx = x0 - 1 + k;
-                    if (gx >= 0 && gx < W) v[k] = row[gx];
+                for (int k = 0; k < TI; ++k) v[k] = 0u;
+                if (vec_ok) {
+                    const u32x4 mid = *reinterpret_cast<const u32x4 *>(row + x0);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        v[1 + 2 * k] = mid[k] & 0xffffu;
+                        v[2 + 2 * k] = mid[k] >> 16;
+                    }
+                    if (x0 > 0) v[0] = row[x0 - 1];
+                    if (x0 + TT < W) v[TI - 1] = row[x0 + TT];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < TI; ++k) {
+                        const int gx = x0 - 1 + k;
+                        if (gx >= 0 && gx < W) v[k] = row[gx];
+                    }
                 }
+#pragma unroll
+                for (int k = 0; k < TI; ++k) w[k][c >> 1] |= v[k] << (16 * (c & 1));
             }
         }
 #pragma unroll
-        for (int k = 0; k < TI; ++k) xs[(zy * TI + k) * 16 + ci] = v[k];
+        for (int k = 0; k < TI; ++k)
+            *reinterpret_cast<u32x4 *>(xs + (zy * TI + k) * 16 + cg * 8) = w[k];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, g = lane >> 4;
     __syncthreads();
     bf16x8 bw[MF_KSTEPS];
 #pragma unroll
-    for (int s = 0; s < MF_KSTEPS; ++s)
-        bw[s] = as_bf16x8(*reinterpret_cast<const u32x4 *>(&bfrag[s][lane][0]));
-    const float bcol = bias ? bias[col] : 0.f;
+    for (int s = 0; s < MF_KSTEPS; ++s) bw[s] = as_bf16x8(bfrag[s * 64 + lane]);
+    floatx4 acc[8];
+#pragma unroll
     for (int m = 0; m < 8; ++m) {
         // A row: voxel v of the tile; k = tap 2 s + (g >> 1), channels (g & 1) 8 ..
         const int v = wave * 128 + m * 16 + col;
         const int lx = v & 7, ly = (v >> 3) & 7, lz = v >> 6;
         const unsigned short *base = xs + ((lz * TI + ly) * TI + lx) * 16 + (g & 1) * 8;
-        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < MF_KSTEPS; ++s) {
             const int t0 = 2 * s, t1 = 2 * s + 1;
             const int tap = (g >> 1) ? t1 : t0;
             u32x4 av = {0u, 0u, 0u, 0u};
             if (tap < 27) av = *reinterpret_cast<const u32x4 *>(base + ((g >> 1) ? tap_off(t1 < 27 ? t1 : 0) : tap_off(t0)) * 16);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), bw[s], acc, 0, 0, 0);
+            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), bw[s], acc[m], 0, 0, 0);
         }
-        // result: column co = col, rows (voxels) m 16 + 4 g + r
+    }
+    // results: column co = col, rows (voxels) m 16 + 4 g + r, through LDS
+    // [co][voxel] to rows of 8 voxels along x per (co, z, y)
+    __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int vv = wave * 128 + m * 16 + 4 * g + r;
-            const int gx = x0 + (vv & 7), gy = y0 + ((vv >> 3) & 7), gz = z0 + (vv >> 6);
-            if (gx >= W || gy >= H || gz >= D) continue;
-            const size_t off = col * vol + gz * plane + (size_t)gy * W + gx;
-            float o = acc[r] + bcol;
-            if (relu) o = fmaxf(o, 0.f);
-            if (mask && !(ldv(mask, off, ydt) > 0.f)) o = 0.f;
-            stv(y, off, ydt, o);
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) os[col * TT3 + wave * 128 + m * 16 + 4 * g + r] = acc[m][r];
+    __syncthreads();
+    const bool row_ok = x0 + TT <= W && (W % 8) == 0 && ((uintptr_t)y % 32) == 0 &&
+                        (!mask || ((uintptr_t)mask % 32) == 0);
+    for (int rr = threadIdx.x; rr < 16 * TT * TT; rr += MF_THREADS) {
+        const int co = rr / (TT * TT), zy = rr - co * TT * TT;
+        const int lz = zy / TT, ly = zy - lz * TT;
+        const int gz = z0 + lz, gy = y0 + ly;
+        if (gz >= D || gy >= H) continue;
+        const float bcol = bias ? bias[co] : 0.f;
+        const float *src = os + co * TT3 + zy * TT;
+        float o[TT];
+#pragma unroll
+        for (int k = 0; k < TT; ++k) {
+            o[k] = src[k] + bcol;
+            if (relu) o[k] = fmaxf(o[k], 0.f);
+        }
+        const size_t off = (size_t)co * vol + gz * plane + (size_t)gy * W + x0;
+        if (row_ok) {
+            if (mask) {
+                float mv[TT];
+                if (ydt == 0) {
+                    const floatx4 a = *reinterpret_cast<const floatx4 *>((const float *)mask + off);
+                    const floatx4 b = *reinterpret_cast<const floatx4 *>((const float *)mask + off + 4);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) mv[k] = a[k], mv[4 + k] = b[k];
+                } else {
+                    const u32x4 a = *reinterpret_cast<const u32x4 *>((const unsigned short *)mask + off);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        mv[2 * k] = __uint_as_float(a[k] << 16);
+                        mv[2 * k + 1] = __uint_as_float(a[k] & 0xffff0000u);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < TT; ++k)
+                    if (!(mv[k] > 0.f)) o[k] = 0.f;
+            }
+            if (ydt == 0) {
+                float *dst = (float *)y + off;
+                *reinterpret_cast<floatx4 *>(dst) = floatx4{o[0], o[1], o[2], o[3]};
+                *reinterpret_cast<floatx4 *>(dst + 4) = floatx4{o[4], o[5], o[6], o[7]};
+            } else {
+                u32x4 b;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) b[k] = bf16_bits(o[2 * k]) | (bf16_bits(o[2 * k + 1]) << 16);
+                *reinterpret_cast<u32x4 *>((unsigned short *)y + off) = b;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < TT; ++k) {
+                if (x0 + k >= W) break;
+                float v = o[k];
+                if (mask && !(ldv(mask, off + k, ydt) > 0.f)) v = 0.f;
+                stv(y, off + k, ydt, v);
+            }
         }
     }
 }
