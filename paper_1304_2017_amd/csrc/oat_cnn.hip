@@ -394,12 +394,24 @@ conv16_wgrad_mfma_kernel(const unsigned short *__restrict__ x, const unsigned sh
             *reinterpret_cast<u32x4 *>(&xs3[dx][ci][zy][0]) = pk;
         }
     }
-    for (int i = threadIdx.x; i < 16 * TT3; i += MF_THREADS) {
-        const int co = i / TT3, v = i - co * TT3;
-        const int gz = z0 + v / (TT * TT), gy = y0 + (v / TT) % TT, gx = x0 + v % TT;
-        unsigned short gv = 0;
-        if (gz < D && gy < H && gx < W) gv = dy[co * vol + gz * plane + (size_t)gy * W + gx];
-        gs[co][v] = gv;
+    // dy rows (co, z, y) of the tile, 8 voxels along x: one 16-byte load and
+    // one 16-byte LDS word when the row lies inside the volume and is aligned
+    const bool dvec_ok = x0 + TT <= W && (W % 8) == 0 && ((uintptr_t)dy % 16) == 0;
+    for (int r = threadIdx.x; r < 16 * TT * TT; r += MF_THREADS) {
+        const int co = r / (TT * TT), zy = r - co * TT * TT;
+        const int gz = z0 + zy / TT, gy = y0 + zy % TT;
+        u32x4 pk = {0u, 0u, 0u, 0u};
+        if (gz < D && gy < H) {
+            const unsigned short *row = dy + co * vol + gz * plane + (size_t)gy * W;
+            if (dvec_ok) {
+                pk = *reinterpret_cast<const u32x4 *>(row + x0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < TT; ++k)
+                    if (x0 + k < W) pk[k >> 1] |= (unsigned)row[x0 + k] << (16 * (k & 1));
+            }
+        }
+        *reinterpret_cast<u32x4 *>(&gs[co][zy * TT]) = pk;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
