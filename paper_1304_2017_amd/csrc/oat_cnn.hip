@@ -55,7 +55,19 @@ __device__ __forceinline__ void load_tile(float (*xs)[TI3], const void *x, int x
     }
 }
 
-// One output voxel per thread, all CO channels; 8^3 voxels per workgroup.
+// Tile of the VALU forward: FX x FY x FZ = 512 output voxels.  With one
+// input channel it is 64 x 4 x 2, so a wave's 64 consecutive voxels write
+// whole cache lines of each of its output channels; 16 -> 1 takes 32 x 4 x 4
+// (a halo tile of 78 KB of FP32 values), 16 -> 16 an 8^3 cube (the smallest
+// halo: its cost is the 6912 products per voxel, not the stores).
+template <int CI, int CO> struct FwdTile {
+    static constexpr int FX = CI == 1 ? 64 : (CO == 1 ? 32 : 8);
+    static constexpr int FY = CI == 1 ? 4 : (CO == 1 ? 4 : 8);
+    static constexpr int FZ = CI == 1 ? 2 : (CO == 1 ? 4 : 8);
+    static constexpr int HX = FX + 2, HY = FY + 2, HZ = FZ + 2, HALO = HX * HY * HZ;
+};
+
+// One output voxel per thread, all CO channels; FwdTile<CI, CO> voxels per workgroup.
 template <int CI, int CO>
 __global__ void __launch_bounds__(NT) conv_fwd_kernel(const void *__restrict__ x, int xdt, int D,
                                                       int H, int W, const float *__restrict__ wt,
@@ -63,32 +75,68 @@ __global__ void __launch_bounds__(NT) conv_fwd_kernel(const void *__restrict__ x
                                                       void *__restrict__ y, int ydt, int relu,
                                                       const void *__restrict__ mask)
 {
-    __shared__ float xs[CI][TI3];
+    using T = FwdTile<CI, CO>;
+    static_assert(T::FX * T::FY * T::FZ == NT, "one voxel per thread");
+    __shared__ float xs[CI][T::HALO];
     __shared__ float ws[CI * 27][CO];       // [ci][tap][co]: a broadcast read per (ci, tap)
-    const int x0 = blockIdx.x * TT, y0 = blockIdx.y * TT, z0 = blockIdx.z * TT;
-    for (int i = threadIdx.x; i < CI * 27 * CO; i += NT) {
-        const int co = i % CO, r = i / CO, ci = r / 27, t = r % 27;
-        ws[r][co] = wt[(co * CI + ci) * 27 + t];
+    const int x0 = blockIdx.x * T::FX, y0 = blockIdx.y * T::FY, z0 = blockIdx.z * T::FZ;
+    const size_t plane = (size_t)H * W, vol = plane * D;
+    if constexpr (CO != 1)
+        for (int i = threadIdx.x; i < CI * 27 * CO; i += NT) {
+            const int co = i % CO, r = i / CO, ci = r / 27, t = r % 27;
+            ws[r][co] = wt[(co * CI + ci) * 27 + t];
+        }
+    // halo tile, zero outside the volume; consecutive threads take
+    // consecutive x, so the loads of a row are coalesced
+    for (int i = threadIdx.x; i < CI * T::HALO; i += NT) {
+        const int ci = i / T::HALO, r = i - ci * T::HALO;
+        const int zz = r / (T::HX * T::HY), yy = (r / T::HX) % T::HY, xx = r % T::HX;
+        const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+        float v = 0.f;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = ldv(x, ci * vol + gz * plane + (size_t)gy * W + gx, xdt);
+        xs[ci][r] = v;
     }
-    load_tile<CI>(xs, x, xdt, D, H, W, x0, y0, z0);
     __syncthreads();
-    const int lx = threadIdx.x % TT, ly = (threadIdx.x / TT) % TT, lz = threadIdx.x / (TT * TT);
+    const int lx = threadIdx.x % T::FX, ly = (threadIdx.x / T::FX) % T::FY,
+              lz = threadIdx.x / (T::FX * T::FY);
     float acc[CO];
 #pragma unroll
     for (int co = 0; co < CO; ++co) acc[co] = bias ? bias[co] : 0.f;
-    for (int ci = 0; ci < CI; ++ci) {
+    if constexpr (CO == 1) {
+        // One output channel: the weights are the same for every thread, so
+        // a channel's 27 come through the scalar cache, and the LDS serves
+        // only the voxel values.
+        for (int ci = 0; ci < CI; ++ci) {
+            const float *wc = wt + ci * 27;
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const float v = xs[ci][((lz + dz) * TI + ly + dy) * TI + lx + dx];
-            const float *wr = ws[ci * 27 + t];
-#pragma unroll
-            for (int co = 0; co < CO; ++co) acc[co] = fmaf(wr[co], v, acc[co]);
+            for (int t = 0; t < 27; ++t) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                const float v = xs[ci][((lz + dz) * T::HY + ly + dy) * T::HX + lx + dx];
+                acc[0] = fmaf(wc[t], v, acc[0]);
+            }
         }
+    } else {
+    // Taps in rows of 3 along x: a row's weights are read when it runs (a
+    // fully unrolled loop would hold all CI x 27 x CO weights in registers).
+    for (int ci = 0; ci < CI; ++ci) {
+#pragma unroll 1
+        for (int r = 0; r < 9; ++r) {
+            const int dz = r / 3, dy = r % 3;
+            const float *xr = &xs[ci][((lz + dz) * T::HY + ly + dy) * T::HX + lx];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const float v = xr[dx];
+                const float *wr = ws[ci * 27 + r * 3 + dx];
+#pragma unroll
+                for (int co = 0; co < CO; ++co) acc[co] = fmaf(wr[co], v, acc[co]);
+            }
+        }
+    }
     }
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
     if (gx >= W || gy >= H || gz >= D) return;
-    const size_t plane = (size_t)H * W, vol = plane * D, off = gz * plane + (size_t)gy * W + gx;
+    const size_t off = gz * plane + (size_t)gy * W + gx;
 #pragma unroll
     for (int co = 0; co < CO; ++co) {
         float r = acc[co];
@@ -546,6 +594,12 @@ bool dt_ok(int d) { return d == OAT_F32 || d == OAT_BF16; }
 
 dim3 tiles(int d, int h, int w) { return dim3((w + TT - 1) / TT, (h + TT - 1) / TT, (d + TT - 1) / TT); }
 
+template <int CI, int CO> dim3 fwd_tiles(int d, int h, int w)
+{
+    using T = FwdTile<CI, CO>;
+    return dim3((w + T::FX - 1) / T::FX, (h + T::FY - 1) / T::FY, (d + T::FZ - 1) / T::FZ);
+}
+
 }  // namespace
 
 extern "C" {
@@ -562,8 +616,8 @@ int oat_conv3d_forward(const void *x, oat_dtype xdt, int c_in, int d, int h, int
     hipStream_t s = (hipStream_t)stream;
     dim3 g = tiles(d, h, w), b(NT);
 #define FWD(CI, CO)                                                                                 \
-    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), g, b, 0, s, x, (int)xdt, d, h, w, weight, bias, y, \
-                       (int)ydt, relu, mask)
+    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), (fwd_tiles<CI, CO>(d, h, w)), b, 0, s, x, (int)xdt, \
+                       d, h, w, weight, bias, y, (int)ydt, relu, mask)
     if (c_in == 16 && c_out == 16 && xdt == OAT_BF16)
         hipLaunchKernelGGL(conv16_mfma_kernel, g, dim3(MF_THREADS), 0, s,
                            (const unsigned short *)x, d, h, w, weight, bias, y, (int)ydt, relu,
