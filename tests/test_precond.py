@@ -165,10 +165,13 @@ gpu = pytest.mark.gpu
 @gpu
 @pytest.mark.parametrize("ci,co", [(1, 16), (16, 16), (16, 1), (1, 1)])
 @pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16])
-def test_conv3d_forward_matches_reference(ci, co, dt):
-    _say(f"[gpu] conv3d {ci}->{co} {dt}")
+@pytest.mark.parametrize("shape", [(13, 11, 9), (5, 7, 70)])
+def test_conv3d_forward_matches_reference(ci, co, dt, shape):
+    """Every layer shape against a PyTorch FP64 convolution; (5, 7, 70) spans
+    several tiles along x (64 or 32 voxels wide) with ragged ends on all axes."""
+    _say(f"[gpu] conv3d {ci}->{co} {dt} {shape}")
     g = torch.Generator().manual_seed(ci * 100 + co)
-    x = torch.randn((ci, 13, 11, 9), generator=g).to(dt)
+    x = torch.randn((ci,) + shape, generator=g).to(dt)
     w = torch.randn((co, ci, 27), generator=g) * 0.2
     b = torch.randn((co,), generator=g)
     y = precond.conv3d(x.cuda(), w.cuda(), b.cuda())
@@ -180,7 +183,7 @@ def test_conv3d_forward_matches_reference(ci, co, dt):
     # ReLU, then an output mask
     yr = precond.conv3d(x.cuda(), w.cuda(), b.cuda(), relu=True)
     assert _rel(yr, ref.clamp(min=0)) < tol
-    m = torch.randn((co, 13, 11, 9), generator=g).to(dt)
+    m = torch.randn((co,) + shape, generator=g).to(dt)
     ym = precond.conv3d(x.cuda(), w.cuda(), b.cuda(), mask=m.cuda())
     assert _rel(ym, ref * (m.double() > 0)) < tol
 
