@@ -44,16 +44,25 @@ def log(msg):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cube.txt")
 
 
+# Sources of the kernels the default line measures (G, G^T, FBP, D, D^T, the
+# brick-sum gather and the plan's tables), with the headers they include.
+SRT_SOURCES = ("oat_srt.hip", "oat_aux.hip", "oat_plan.cpp", "oat_internal.hpp", "oat_geom.hpp",
+               "oat_dtype.hpp", "oat_fbp_window.hpp", "oat_fbp_floor.hpp")
+
+
 def kernel_sources_sha256():
-    """Hash of the HIP/C++ sources the kernels are built from."""
+    """Hash of the HIP/C++ sources of the measured kernels (SRT_SOURCES and
+    include/oat.h): a counter summary taken with other sources no longer
+    describes them."""
     import hashlib
     d = os.path.join(ROOT, "paper_1304_2017_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in sorted(SRT_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(ROOT, "include", "oat.h"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()
 
 

@@ -117,22 +117,23 @@ __global__ void __launch_bounds__(NT) conv_fwd_kernel(const void *__restrict__ x
             }
         }
     } else {
-    // Taps in rows of 3 along x: a row's weights are read when it runs (a
-    // fully unrolled loop would hold all CI x 27 x CO weights in registers).
-    for (int ci = 0; ci < CI; ++ci) {
+        // Taps in rows of 3 along x: a row's weights are read when it runs
+        // (a fully unrolled loop would hold all CI x 27 x CO weights in
+        // registers).
+        for (int ci = 0; ci < CI; ++ci) {
 #pragma unroll 1
-        for (int r = 0; r < 9; ++r) {
-            const int dz = r / 3, dy = r % 3;
-            const float *xr = &xs[ci][((lz + dz) * T::HY + ly + dy) * T::HX + lx];
+            for (int r = 0; r < 9; ++r) {
+                const int dz = r / 3, dy = r % 3;
+                const float *xr = &xs[ci][((lz + dz) * T::HY + ly + dy) * T::HX + lx];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const float v = xr[dx];
-                const float *wr = ws[ci * 27 + r * 3 + dx];
+                for (int dx = 0; dx < 3; ++dx) {
+                    const float v = xr[dx];
+                    const float *wr = ws[ci * 27 + r * 3 + dx];
 #pragma unroll
-                for (int co = 0; co < CO; ++co) acc[co] = fmaf(wr[co], v, acc[co]);
+                    for (int co = 0; co < CO; ++co) acc[co] = fmaf(wr[co], v, acc[co]);
+                }
             }
         }
-    }
     }
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
     if (gx >= W || gy >= H || gz >= D) return;
