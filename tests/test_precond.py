@@ -31,7 +31,8 @@ def _ref_conv(x, w, b=None):
 
 
 def _rel(a, b):
-    a, b = a.double().cpu().reshape(-1), b.double().cpu().reshape(-1)
+    a = a.detach().double().cpu().reshape(-1)
+    b = b.detach().double().cpu().reshape(-1)
     return float((a - b).norm() / b.norm())
 
 
