@@ -268,10 +268,10 @@ __device__ __forceinline__ SegAxes seg_axes(float xa, float xb, const float e1[3
 }
 
 __device__ __forceinline__ Pt seg_point(const float Pl[3], const int dc[3], const SegAxes &ax,
-                                        float dd, int dj, const int lo[3], const int hi[3])
+                                        float dd, float dj, const int lo[3], const int hi[3])
 {
     float cm1, sn;
-    small_rot((float)dj * dd, cm1, sn);
+    small_rot(dj * dd, cm1, sn);
     const float ux = fmaf(sn, ax.B[0], fmaf(cm1, ax.A[0], Pl[0]));
     const float uy = fmaf(sn, ax.B[1], fmaf(cm1, ax.A[1], Pl[1]));
     const float uz = fmaf(sn, ax.B[2], fmaf(cm1, ax.A[2], Pl[2]));
@@ -358,7 +358,7 @@ __device__ __forceinline__ void segment_points(const Problem &P, SegLds &W, Buil
         const SegAxes ax = seg_axes(qa, qb, e1, e2);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            pt[h] = seg_point(p3, d3, ax, dd, djA + h, lo, hi);
+            pt[h] = seg_point(p3, d3, ax, dd, (float)(djA + h), lo, hi);
             pt[h].own = pt[h].own && v3 && 2 * pr + h < npp;
         }
         if (MODE == WALK_POINTS) {
@@ -761,9 +761,11 @@ __device__ __forceinline__ void walk_seg(const Problem &P, int q, size_t unit, c
         if (ADJ && v) w = w * ((gp[(size_t)q * P.nt + klo + so] * gscale) * gscale2);
         const SegAxes ax = seg_axes(xa, xb, e1, e2);
         const int nmax = wave_max_i(np);
-        for (int t = 0; t < nmax; ++t) {
+        // dj0 + t as an FP32 counter (exact: |dj| < 2^24), one add per point
+        float fdj = (float)dj0;
+        for (int t = 0; t < nmax; ++t, fdj += 1.f) {
             if (t < np) {
-                const Pt pt = seg_point(Pl, dc, ax, rr.delta, dj0 + t, lo, hi);
+                const Pt pt = seg_point(Pl, dc, ax, rr.delta, fdj, lo, hi);
                 if (pt.own) pfn(pt, w);
             }
         }
@@ -1156,18 +1158,24 @@ srt_adj_kernel(Problem P, const float *__restrict__ gp, double *__restrict__ acc
                 }
             } else {
                 auto scatter1 = [&](const Pt &t, float wv) {
-                    unsigned long long *pb = box + __umul24((unsigned)t.cz, BOX_SZ) +
-                                             __umul24((unsigned)t.cy, BOX_SY) + t.cx;
+                    // word index, then bytes (one multiply-add fewer than
+                    // scaling each term)
+                    const unsigned wi = __umul24((unsigned)t.cz, BOX_SZ) +
+                                        (__umul24((unsigned)t.cy, BOX_SY) + (unsigned)t.cx);
+                    unsigned long long *pb = reinterpret_cast<unsigned long long *>(
+                        reinterpret_cast<char *>(box) + (wi << 3));
                     unsigned long long *pz = pb + BOX_SZ;
                     // trilinear corner weights, (1 - f) v formed as v - f v
                     const float a = fmaf(-t.fz, wv, wv), c = t.fz * wv;
                     const float w00 = fmaf(-t.fy, a, a), w01 = t.fy * a, w10 = fmaf(-t.fy, c, c),
                                 w11 = t.fy * c;
-                    // fields (node x, node x + 1) of one word
+                    // fields (node x, node x + 1) of one word: the 64-bit
+                    // integer l + h 2^32 (l sign-extended), formed with 32-bit
+                    // operations: high word h + (l >> 31)
                     auto add2 = [&](unsigned long long *p, float wyz) {
                         const int l = cvt_rne(fmaf(-t.fx, wyz, wyz)), h = cvt_rne(t.fx * wyz);
-                        atomicAdd(p, (unsigned long long)(long long)l +
-                                         ((unsigned long long)(unsigned)h << 32));
+                        const unsigned hw = (unsigned)h + (unsigned)(l >> 31);
+                        atomicAdd(p, ((unsigned long long)hw << 32) | (unsigned)l);
                     };
                     add2(pb, w00);
                     add2(pb + BOX_SY, w01);

@@ -180,3 +180,46 @@ def test_host_fbp_window_bounds(tmp_path):
         pairs, lo_m, hi_m = map(int, r.stdout.split()[1:4])
         print(f"{geom.name or geom.shape}: {pairs} tile-transducer pairs, margins {lo_m} / {hi_m}")
         assert pairs > 0 and lo_m >= 0 and hi_m >= 0
+
+
+def _fit_small_rot():
+    import importlib.util
+    path = os.path.join(ROOT, "paper_1304_2017_amd", "csrc", "fit_small_rot.py")
+    spec = importlib.util.spec_from_file_location("fit_small_rot", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_small_rot_coefficients_match_their_fit():
+    """The ring-point rotation's sin d and cos d - 1 polynomials (|d| <= pi/8)
+    carry the coefficients that fit_small_rot.py derives (to 1 FP32 ulp), and
+    their relative errors bound the position error: a point at ring radius r
+    moves by r |d| err, at most 16 err cells for rings of 256 points or more
+    (|d| <= 16 2 pi / N_j, r = N_j / 2 pi) and 40 (pi/8) err below that."""
+    fit = _fit_small_rot()
+    want = np.array(fit.coefficients(), dtype=np.float32)
+    text = open(os.path.join(ROOT, "paper_1304_2017_amd", "csrc", "oat_geom.hpp")).read()
+    body = text[text.index("OAT_HD void small_rot"):]
+    body = body[:body.index("}")]
+    lits = [float(v) for v in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
+    # order in the source: a2, a1, 1.0, b2, b1, -0.5
+    assert len(lits) == 6 and lits[2] == 1.0 and lits[5] == -0.5, lits
+    got = np.array([lits[1], lits[0], lits[4], lits[3]], dtype=np.float32)
+    ulp = np.spacing(np.abs(want))
+    assert np.all(np.abs(got - want) <= ulp), (got, want)
+    es, ec = fit.max_relative_errors(tuple(float(x) for x in got))
+    assert es < 3e-8 and ec < 1e-8, (es, ec)
+    assert 16 * es < 5e-7 and 40 * (np.pi / 8) * es < 5e-7
+    # FP32 evaluation as the kernel does it (fmaf emulated in FP64, rounded)
+    d = np.linspace(-np.pi / 8, np.pi / 8, 20001).astype(np.float32)
+    f32 = np.float32
+
+    def fma(a, b, c):
+        return f32(np.float64(a) * np.float64(b) + np.float64(c))
+    d2 = (d * d).astype(np.float32)
+    sn = fma(d2, fma(d2, got[1], got[0]), f32(1.0)) * d
+    cm1 = fma(d2, fma(d2, got[3], got[2]), f32(-0.5)) * d2
+    dd = d.astype(np.float64)
+    assert np.max(np.abs(sn - np.sin(dd))) < 1.5e-7 * np.pi / 8
+    assert np.max(np.abs(cm1 + 2 * np.sin(dd / 2) ** 2)) < 2e-8
