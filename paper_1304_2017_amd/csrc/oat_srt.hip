@@ -930,15 +930,25 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         wave_sync();
         int klo = 0;
         float racc = 0.f;
+        // FP32 images: a point in the same cell as the lane's previous point
+        // reuses its corners without reading LDS (BF16 images, with half the
+        // reads, are faster without the test).
+        unsigned prev = 0xffffffffu;
+        float c8[8] = {};
         auto point = [&](const Pt &t, float) {
             float v000, v001, v010, v011, v100, v101, v110, v111;
             const unsigned off = __umul24((unsigned)t.cz, BOX_SZ) +
                                  __umul24((unsigned)t.cy, BOX_SY) + t.cx;
             if constexpr (IMG_DT == 0) {
-                const float *pb = box + off;
-                const float *pz = pb + BOX_SZ;
-                v000 = pb[0], v001 = pb[1], v010 = pb[BOX_SY], v011 = pb[BOX_SY + 1];
-                v100 = pz[0], v101 = pz[1], v110 = pz[BOX_SY], v111 = pz[BOX_SY + 1];
+                if (off != prev) {
+                    prev = off;
+                    const float *pb = box + off;
+                    const float *pz = pb + BOX_SZ;
+                    c8[0] = pb[0], c8[1] = pb[1], c8[2] = pb[BOX_SY], c8[3] = pb[BOX_SY + 1];
+                    c8[4] = pz[0], c8[5] = pz[1], c8[6] = pz[BOX_SY], c8[7] = pz[BOX_SY + 1];
+                }
+                v000 = c8[0], v001 = c8[1], v010 = c8[2], v011 = c8[3];
+                v100 = c8[4], v101 = c8[5], v110 = c8[6], v111 = c8[7];
             } else {
                 const unsigned *pb = reinterpret_cast<const unsigned *>(box) + off;
                 const unsigned *pz = pb + BOX_SZ;
@@ -958,6 +968,7 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         auto segment = [&](int np, int so, float wv) {
             if (np > 0) atomicAdd(gw + so, (double)racc * (double)wv);
             racc = 0.f;
+            prev = 0xffffffffu;
         };
         walk_seg<false>(P, q, (size_t)b * P.nq + q, lo, hi, gbase, nullptr, 1.f, 1.f, klo, point,
                         segment);
