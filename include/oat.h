@@ -102,10 +102,12 @@ typedef struct oat_plan oat_plan;
 #define OAT_FLAG_SRT_ONLY 1u
 
 /* Ask for bit-stable output (ordered reductions).  Every operator of this
- * library already gives bit-identical results for identical inputs (G sums
- * its partials in a fixed order, G^T adds exact fixed-point integers, FBP
- * and the EIR and deconvolution kernels have no atomics), so the flag is
- * accepted and changes nothing. */
+ * library already gives bit-identical results for identical inputs (G's
+ * shell sums are fixed-point integers on the segment-table path and FP64 sums
+ * formed by one wave in program order on the others, and its brick partials
+ * are summed in a fixed order; G^T adds exact fixed-point integers; FBP and
+ * the EIR and deconvolution kernels have no atomics), so the flag is accepted
+ * and changes nothing. */
 #define OAT_FLAG_DETERMINISTIC 2u
 
 /* Validate the geometry, build the quadrature tables in FP64 on the host,

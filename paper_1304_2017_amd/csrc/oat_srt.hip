@@ -871,7 +871,8 @@ srt_fwd_kernel(Problem P, const void *__restrict__ img, float *__restrict__ part
 // G on the segment table: one segment per lane (walk_seg), FWD_SEG_WAVES
 // waves per workgroup and two workgroups per CU (at most 64 VGPRs, the LDS
 // of two boxes).  Per wave, dynamic LDS holds the unit's first candidate
-// ring per shell (window ints) and its FP64 shell sums (window doubles).
+// ring per shell (window ints) and its fixed-point shell sums (window
+// 64-bit integers).
 constexpr int FWD_SEG_WAVES = 16;
 
 template <int IMG_DT>
@@ -882,6 +883,9 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
     constexpr int NW = FWD_SEG_WAVES;
     __shared__ float box[BOX_WORDS];
     __shared__ int q_next;
+    __shared__ float wmax[NW];
+    __shared__ int wbad[NW];
+    __shared__ double fx_scale;
     extern __shared__ double dyn_lds[];
     const int win = P.window;
     const int b = blockIdx.x;
@@ -889,6 +893,10 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
     brick_box(P, b, lo, hi, n0, n1);
     const int qb = (int)blockIdx.y * q_per_slice, qe = min(P.nq, qb + q_per_slice);
     if (threadIdx.x == 0) q_next = qb;
+    // the box's largest |node| (and whether any node is not finite) sets
+    // the fixed-point scale of the shell sums below
+    float amax = 0.f;
+    int abad = 0;
     auto node = [&](int x, int y, int z) {
         const int gx = lo[0] + x, gy = lo[1] + y, gz = lo[2] + z;
         float v = 0.f;
@@ -899,6 +907,9 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
             else
                 v = __uint_as_float(((unsigned)((const unsigned short *)img)[n]) << 16);
         }
+        const float a = fabsf(v);
+        abad |= !(a <= 3.4028235e38f);
+        amax = fmaxf(amax, a);
         return v;
     };
     // FP32 images: one node per word.  BF16 images: word x holds the BF16
@@ -918,15 +929,47 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
     }
     const int wave = threadIdx.x / WAVE;
     const int lane = lane_id();
-    double *gw = dyn_lds + (size_t)wave * win;
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = fmaxf(amax, __shfl_xor(amax, o));
+        abad |= __shfl_xor(abad, o);
+    }
+    if (lane == 0) {
+        wmax[wave] = amax;
+        wbad[wave] = abad;
+    }
+    // Shell sums in 64-bit fixed point (order-independent, and the integer
+    // LDS add is cheaper than the FP64 one).  A unit's shell holds at most
+    // 2^19 points (63 rings x 256 segments x 32 points: the entry's fields),
+    // each adding |psi-interpolated node| w <= M w_max, so with
+    // M w_max < 2^e a scale of 2^(43 - e) keeps every sum below 2^62.  A box
+    // with a non-finite node gives NaN sums.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.f;
+        int bad = 0;
+        for (int w = 0; w < NW; ++w) {
+            m = fmaxf(m, wmax[w]);
+            bad |= wbad[w];
+        }
+        int e = 0;
+        frexp((double)m * (double)P.w_max, &e);
+        fx_scale = bad ? __longlong_as_double(0x7ff8000000000000ll) : (m > 0.f ? ldexp(1.0, 43 - e) : 1.0);
+    }
+    unsigned long long *gw = reinterpret_cast<unsigned long long *>(dyn_lds) + (size_t)wave * win;
     int *gbase = reinterpret_cast<int *>(dyn_lds + (size_t)NW * win) + wave * win;
     __syncthreads();
+    // (uniform: kept in scalar registers)
+    const long long fxb = __double_as_longlong(fx_scale);
+    const double fxs = __longlong_as_double(
+        ((long long)__builtin_amdgcn_readfirstlane((int)(fxb >> 32)) << 32) |
+        (unsigned)__builtin_amdgcn_readfirstlane((int)fxb));
+    const double fxi = 1.0 / fxs;
     for (;;) {
         int q = 0;
         if (lane == 0) q = atomicAdd(&q_next, 1);
         q = __builtin_amdgcn_readfirstlane(q);
         if (q >= qe) break;
-        for (int j = lane; j < win; j += WAVE) gw[j] = 0.0;
+        for (int j = lane; j < win; j += WAVE) gw[j] = 0ull;
         wave_sync();
         int klo = 0;
         float racc = 0.f;
@@ -934,7 +977,7 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         // reuses its corners without reading LDS (BF16 images, with half the
         // reads, are faster without the test).
         unsigned prev = 0xffffffffu;
-        float c8[8] = {};
+        float c8[8];   // loaded before any use: prev starts out unmatched
         auto point = [&](const Pt &t, float) {
             float v000, v001, v010, v011, v100, v101, v110, v111;
             const unsigned off = __umul24((unsigned)t.cz, BOX_SZ) +
@@ -963,10 +1006,17 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
             const float c0 = fmaf(t.fy, c01 - c00, c00), c1 = fmaf(t.fy, c11 - c10, c10);
             racc += fmaf(t.fz, c1 - c0, c0);
         };
-        // one segment (one shell) per lane: the weighted sum of its points
-        // goes to the shell's FP64 entry
+        // one segment (one shell) per lane: the weighted sum of its points,
+        // racc w (exact in FP64) times the power-of-two scale, rounded to an
+        // integer and split into 32-bit halves exactly, goes to the shell's
+        // fixed-point entry
         auto segment = [&](int np, int so, float wv) {
-            if (np > 0) atomicAdd(gw + so, (double)racc * (double)wv);
+            if (np > 0) {
+                const double v = rint((double)racc * (double)wv * fxs);
+                const double hi = floor(v * 0x1p-32);
+                const double lo = fma(-hi, 0x1p32, v);
+                atomicAdd(gw + so, ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned)lo);
+            }
             racc = 0.f;
             prev = 0xffffffffu;
         };
@@ -974,7 +1024,10 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
                         segment);
         wave_sync();
         float *dst = part + ((size_t)b * P.nq + q) * win;
-        for (int j = lane; j < win; j += WAVE) dst[j] = (float)gw[j];
+        for (int j = lane; j < win; j += WAVE) {
+            const long long sj = (long long)gw[j];
+            dst[j] = (float)(fma((double)(int)(sj >> 32), 0x1p32, (double)(unsigned)sj) * fxi);
+        }
         if (lane == 0) klo_out[(size_t)b * P.nq + q] = klo;
         wave_sync();
     }

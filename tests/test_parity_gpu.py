@@ -342,6 +342,25 @@ def test_backproject_with_wide_dynamic_range(Plan):
     check("H^T 1e-30", _np(plan.backproject(_t(tiny))), ref.backproject(gd, tiny), 1e-5)
 
 
+def test_project_with_wide_dynamic_range(Plan):
+    """G's shell sums are 64-bit fixed point with a power-of-two scale from
+    each brick's largest |node|: images of magnitude 1e-30 and 1e30 still
+    match the oracle, and a NaN node turns sums into NaN rather than into
+    finite values."""
+    geom, _, img = synth.config_small(2)
+    plan = Plan(geom, 0)
+    gd = geom.as_dict()
+    for s in (1e-30, 1e30):
+        x = (img * s).astype(np.float32).astype(np.float64)
+        _say(f"[gpu] G with the image times {s:g}")
+        check(f"G x{s:g}", _np(plan.project(_t(x), srt_only=True)), ref.srt(gd, x), 5e-7)
+    x = img.astype(np.float32).copy()
+    x[geom.nz // 2, geom.ny // 2, geom.nx // 2] = np.nan
+    _say("[gpu] G with one NaN node")
+    g = _np(plan.project(_t(x), srt_only=True))
+    assert np.isnan(g).any()
+
+
 @pytest.fixture(scope="module")
 def small1_plan(Plan):
     """config_small's grid with 200 transducers: three windows of 96."""
