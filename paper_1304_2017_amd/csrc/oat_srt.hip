@@ -885,7 +885,7 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
     __shared__ int q_next;
     __shared__ float wmax[NW];
     __shared__ int wbad[NW];
-    __shared__ double fx_scale;
+    __shared__ double fx_scale, fx_unscale;
     extern __shared__ double dyn_lds[];
     const int win = P.window;
     const int b = blockIdx.x;
@@ -953,17 +953,21 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
         }
         int e = 0;
         frexp((double)m * (double)P.w_max, &e);
-        fx_scale = bad ? __longlong_as_double(0x7ff8000000000000ll) : (m > 0.f ? ldexp(1.0, 43 - e) : 1.0);
+        if (!(m > 0.f)) e = 43;
+        fx_scale = bad ? __longlong_as_double(0x7ff8000000000000ll) : ldexp(1.0, 43 - e);
+        fx_unscale = bad ? fx_scale : ldexp(1.0, e - 43);
     }
     unsigned long long *gw = reinterpret_cast<unsigned long long *>(dyn_lds) + (size_t)wave * win;
     int *gbase = reinterpret_cast<int *>(dyn_lds + (size_t)NW * win) + wave * win;
     __syncthreads();
     // (uniform: kept in scalar registers)
-    const long long fxb = __double_as_longlong(fx_scale);
-    const double fxs = __longlong_as_double(
-        ((long long)__builtin_amdgcn_readfirstlane((int)(fxb >> 32)) << 32) |
-        (unsigned)__builtin_amdgcn_readfirstlane((int)fxb));
-    const double fxi = 1.0 / fxs;
+    auto uniform = [](double x) {
+        const long long b = __double_as_longlong(x);
+        return __longlong_as_double(
+            ((long long)__builtin_amdgcn_readfirstlane((int)(b >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((int)b));
+    };
+    const double fxs = uniform(fx_scale), fxi = uniform(fx_unscale);
     for (;;) {
         int q = 0;
         if (lane == 0) q = atomicAdd(&q_next, 1);
@@ -1007,15 +1011,15 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
             racc += fmaf(t.fz, c1 - c0, c0);
         };
         // one segment (one shell) per lane: the weighted sum of its points,
-        // racc w (exact in FP64) times the power-of-two scale, rounded to an
-        // integer and split into 32-bit halves exactly, goes to the shell's
-        // fixed-point entry
+        // racc w (exact in FP64) times the power-of-two scale, goes to the
+        // shell's fixed-point entry.  The term is below 2^48 (at most 32
+        // points), so adding 1.5 2^52 rounds it to an integer that the low
+        // bits of the sum hold exactly, offset by the constant's bits.
         auto segment = [&](int np, int so, float wv) {
             if (np > 0) {
-                const double v = rint((double)racc * (double)wv * fxs);
-                const double hi = floor(v * 0x1p-32);
-                const double lo = fma(-hi, 0x1p32, v);
-                atomicAdd(gw + so, ((unsigned long long)(unsigned)(int)hi << 32) + (unsigned)lo);
+                const double t = fma((double)racc * (double)wv, fxs, 0x1.8p52);
+                atomicAdd(gw + so, (unsigned long long)(__double_as_longlong(t) -
+                                                        __double_as_longlong(0x1.8p52)));
             }
             racc = 0.f;
             prev = 0xffffffffu;
