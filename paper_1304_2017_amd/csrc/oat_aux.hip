@@ -39,14 +39,36 @@ srt_reduce_kernel(Problem P, const float *__restrict__ part, const int *__restri
     __syncthreads();
     const int nb = P.nbx * P.nby * P.nbz;
     float *mine = sg + wave * K;
-    for (int b = wave; b < nb; b += RED_WAVES) {
-        const size_t row = (size_t)b * P.nq + q;
-        const int kl = klo[row];
-        const float *src = part + row * P.window;
-        for (int j = lane; j < P.window; j += WAVE) {
-            int k = kl + j;
-            if (k < K) mine[k] += src[j];
+    // Four of the wave's bricks per pass, all their loads issued before
+    // the adds, which keep the brick order (the sums do not change).
+    constexpr int U = 4, H = WMAX / WAVE;
+    for (int b0 = wave; b0 < nb; b0 += U * RED_WAVES) {
+        int kl[U];
+        float v[U][H];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * RED_WAVES;
+            kl[u] = K;
+#pragma unroll
+            for (int h = 0; h < H; ++h) v[u][h] = 0.f;
+            if (b < nb) {
+                const size_t row = (size_t)b * P.nq + q;
+                kl[u] = klo[row];
+                const float *src = part + row * P.window;
+#pragma unroll
+                for (int h = 0; h < H; ++h) {
+                    const int j = lane + h * WAVE;
+                    if (j < P.window) v[u][h] = src[j];
+                }
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int j = lane + h * WAVE, k = kl[u] + j;
+                if (j < P.window && k < K) mine[k] += v[u][h];
+            }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
