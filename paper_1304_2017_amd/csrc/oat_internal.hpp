@@ -52,6 +52,26 @@ inline int brick_slices(int nbricks, int items, int min_items)
 // keeps its own FP64 brick sums ([slice][brick][BOX3]; the same slicing for
 // every table mode).
 inline int fwd_slices(int nbricks, int nq) { return brick_slices(nbricks, nq, 64); }
+// G on the segment table runs two workgroups per CU, so its grid runs in
+// rounds of 512: among 1..8 slices of at least 64 transducers, the count
+// whose grid fills its rounds best, a larger count winning ties within 0.5%
+// (shorter workgroups leave a shorter tail when the last ones finish).
+inline int seg_fwd_slices(int nbricks, int nq)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int sl = 1; sl <= 8; ++sl) {
+        if (sl > 1 && nq / sl < 64) break;
+        const long long g = (long long)nbricks * sl;
+        const double eff = (double)g / (double)(((g + 511) / 512) * 512);
+        if (eff >= best_eff - 0.005) {
+            best = sl;
+            best_eff = eff > best_eff ? eff : best_eff;
+        }
+    }
+    const int per = (nq + best - 1) / best;
+    return (nq + per - 1) / per;
+}
 inline int adj_slices(int nbricks, int nq) { return brick_slices(nbricks, adj_windows(nq), 4); }
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).

@@ -1336,7 +1336,9 @@ template <int TM>
 static void fwd_launch(const Problem &P, const void *img, int img_dtype, float *part, int *klo,
                        hipStream_t s)
 {
-    const int sl = fwd_slices(P.nbx * P.nby * P.nbz, P.nq), qps = (P.nq + sl - 1) / sl;
+    const int nb = P.nbx * P.nby * P.nbz;
+    const int sl = TM == TM_SEG ? seg_fwd_slices(nb, P.nq) : fwd_slices(nb, P.nq);
+    const int qps = (P.nq + sl - 1) / sl;
     if constexpr (TM == TM_SEG) {
         dim3 grid(P.nbx * P.nby * P.nbz, sl), block(FWD_SEG_WAVES * WAVE);
         const size_t dyn = (size_t)FWD_SEG_WAVES * P.window * (sizeof(double) + sizeof(int));
