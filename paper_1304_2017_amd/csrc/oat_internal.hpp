@@ -27,11 +27,12 @@ constexpr int SPH_CHUNKS = 64;
 __host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }
 
 // Slices of a brick's work (G: transducers, G^T: transducer windows) as
-// separate workgroups.  G and G^T run one workgroup per CU, so the grid runs
-// in rounds of 256 workgroups and a partly empty last round leaves CUs idle:
-// take the count (1..4, at least min_items items per slice) whose grid fills
-// its last round best, a smaller count winning ties within 0.5%, and return
-// the number of non-empty slices of ceil(items / count) items.
+// separate workgroups.  A kernel that runs one workgroup per CU runs its grid
+// in rounds of 256 workgroups, and a partly empty last round leaves CUs idle:
+// brick_slices takes the count (1..4, at least min_items items per slice)
+// whose grid fills its last round best, a smaller count winning ties within
+// 0.5%, and returns the number of non-empty slices of ceil(items / count)
+// items.
 inline int brick_slices(int nbricks, int items, int min_items)
 {
     int best = 1;
@@ -48,31 +49,36 @@ inline int brick_slices(int nbricks, int items, int min_items)
     const int per = (items + best - 1) / best;
     return (items + per - 1) / per;
 }
-// G: transducers per slice >= 64.  G^T: windows per slice >= 4; each slice
-// keeps its own FP64 brick sums ([slice][brick][BOX3]; the same slicing for
-// every table mode).
-inline int fwd_slices(int nbricks, int nq) { return brick_slices(nbricks, nq, 64); }
-// G on the segment table runs two workgroups per CU, so its grid runs in
-// rounds of 512: among 1..8 slices of at least 64 transducers, the count
-// whose grid fills its rounds best, a larger count winning ties within 0.5%
-// (shorter workgroups leave a shorter tail when the last ones finish).
-inline int seg_fwd_slices(int nbricks, int nq)
+// Slice counts for the kernels whose grids run in rounds of `round`
+// workgroups: among 1..max_slices slices of at least min_items items, the
+// count whose grid fills its rounds best, a larger count winning ties within
+// 0.5% (shorter workgroups leave a shorter tail when the last ones finish).
+inline int fill_slices(int nbricks, int items, int min_items, int max_slices, int round)
 {
     int best = 1;
     double best_eff = 0.0;
-    for (int sl = 1; sl <= 8; ++sl) {
-        if (sl > 1 && nq / sl < 64) break;
-        const long long g = (long long)nbricks * sl;
-        const double eff = (double)g / (double)(((g + 511) / 512) * 512);
+    for (int c = 1; c <= max_slices; ++c) {
+        if (c > 1 && items / c < min_items) break;
+        const int per = (items + c - 1) / c, n = (items + per - 1) / per;
+        const long long g = (long long)nbricks * n;
+        const double eff = (double)g / (double)(((g + round - 1) / round) * round);
         if (eff >= best_eff - 0.005) {
-            best = sl;
+            best = n;
             best_eff = eff > best_eff ? eff : best_eff;
         }
     }
-    const int per = (nq + best - 1) / best;
-    return (nq + per - 1) / per;
+    return best;
 }
-inline int adj_slices(int nbricks, int nq) { return brick_slices(nbricks, adj_windows(nq), 4); }
+// G on the arc-table and bounds paths (one workgroup per CU): transducers
+// per slice >= 64.
+inline int fwd_slices(int nbricks, int nq) { return brick_slices(nbricks, nq, 64); }
+// G on the segment table runs two workgroups per CU (rounds of 512): up to 8
+// slices of at least 64 transducers.
+inline int seg_fwd_slices(int nbricks, int nq) { return fill_slices(nbricks, nq, 64, 8, 512); }
+// G^T (one workgroup per CU): up to 8 slices of at least 2 windows; each
+// slice keeps its own FP64 brick sums ([slice][brick][BOX3]; the same slicing
+// for every table mode).
+inline int adj_slices(int nbricks, int nq) { return fill_slices(nbricks, adj_windows(nq), 2, 8, 256); }
 
 // Per-transducer record (grid units: positions are (r - r_0)/dx).
 struct alignas(16) DetRec {

@@ -400,17 +400,36 @@ def _brick_slices(nbricks, items, min_items):
     return (items + per - 1) // per
 
 
+def _fill_slices(nbricks, items, min_items, max_slices, rnd):
+    """The library's slice count for G on the segment table (rounds of 512)
+    and for G^T (rounds of 256), restated: the best-filling count of up to
+    max_slices, a larger count winning ties within 0.5%."""
+    best, best_eff = 1, 0.0
+    for c in range(1, max_slices + 1):
+        if c > 1 and items // c < min_items:
+            break
+        per = (items + c - 1) // c
+        n = (items + per - 1) // per
+        g = nbricks * n
+        eff = g / (((g + rnd - 1) // rnd) * rnd)
+        if eff >= best_eff - 0.005:
+            best, best_eff = n, max(eff, best_eff)
+    return best
+
+
 @pytest.mark.parametrize("table", list(TABLES))
 def test_transducer_slices(table, Plan):
-    """8 bricks and 768 transducers: G takes each brick's transducers in 4
-    workgroups and G^T its 8 windows (of 96) in 2, each with its own FP64
-    brick sums added in slice order.  Parity with the oracle, and G^T
-    bit-identical across the table paths."""
+    """8 bricks and 768 transducers: G takes each brick's transducers in 8
+    workgroups on the segment table and 4 on the other paths, and G^T its 8
+    windows (of 96) in 4, each with its own FP64 brick sums added in slice
+    order.  Parity with the oracle, and G^T bit-identical across the table
+    paths."""
     geom0 = synth.config_small(1)[0]
     det = synth.fibonacci_sphere(768, 25.0)
     geom = synth.Geometry(geom0.nx, geom0.ny, geom0.nz, geom0.dx, geom0.x0, geom0.y0, geom0.z0,
                           det, geom0.n_t, geom0.dt, geom0.t0, geom0.c0, 1.0)
-    assert _brick_slices(8, 768, 64) == 4 and _brick_slices(8, 768 // 96, 4) == 2
+    assert _fill_slices(8, 768, 64, 8, 512) == 8 and _brick_slices(8, 768, 64) == 4
+    assert _fill_slices(8, 768 // 96, 2, 8, 256) == 4
     _say(f"[gpu] transducer slices, tables {table}")
     gd = geom.as_dict()
     rng = np.random.default_rng(21)
