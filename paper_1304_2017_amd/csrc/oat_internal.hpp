@@ -21,7 +21,7 @@ constexpr int WAVE = 64;
 constexpr int WMAX = 256;                    // largest shell window per (brick, transducer)
 // G^T takes the transducers in windows of ADJ_WINDOW, with one fixed-point
 // scale and one flush of its LDS box per window.
-constexpr int ADJ_WINDOW = 96;
+constexpr int ADJ_WINDOW = 128;
 // Spherical-voxel forward: voxel chunks summed separately, then in order.
 constexpr int SPH_CHUNKS = 64;
 __host__ __device__ inline int adj_windows(int nq) { return (nq + ADJ_WINDOW - 1) / ADJ_WINDOW; }

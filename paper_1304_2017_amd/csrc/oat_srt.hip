@@ -1051,7 +1051,7 @@ srt_fwd_seg_kernel(Problem P, const void *__restrict__ img, float *__restrict__ 
 // range the word decodes exactly: lo = low 32 bits (signed), hi = (word - lo)
 // >> 32 (arithmetic).
 //
-// The transducers are taken in windows of ADJ_WINDOW = 96 (the NW waves
+// The transducers are taken in windows of ADJ_WINDOW = 128 (the NW waves
 // take a window's transducers one at a time from an LDS counter).  A window's
 // weights are multiplied by S = 0.99 * 2^31 / (R G) and rounded to the nearest
 // integer (v_cvt_rpi_i32_f32), where

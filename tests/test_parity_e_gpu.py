@@ -1,7 +1,7 @@
 """Parity on the 256^3 / 8192-sphere-transducer plan (45 mm, 1024 samples)
 with the library's default table budget, which holds its ~82 GB segment
 table: the plan behind the reconstruction and time-to-residual
-measurements.  86 windows of 96 transducers for G^T.
+measurements.  64 windows of 128 transducers for G^T.
 
 - H and G rows of transducers spread over the sphere;
 - H^T for data on one transducer in every tenth window (the whole image);
@@ -47,8 +47,8 @@ def test_sphere_8192_full_plan():
         _say(f"[gpu-e] G and H rows {rows.tolist()}")
         check("G rows", g.double().cpu().numpy()[rows], ref.srt(gd, img64, rows=rows), 5e-7)
         check("H rows", p.double().cpu().numpy()[rows], ref.project(gd, img64, rows=rows), 1e-5)
-        wins = np.arange(0, 86, 10)
-        rows_t = np.array([w * 96 + (w * 37) % 96 for w in wins], dtype=np.int32)
+        wins = np.arange(0, 64, 7)
+        rows_t = np.array([w * 128 + (w * 37) % 128 for w in wins], dtype=np.int32)
         _say(f"[gpu-e] H^T with data on transducers {rows_t.tolist()}")
         rng = np.random.default_rng(16)
         y = np.zeros((geom.n_det, geom.n_t), dtype=np.float32)

@@ -5,7 +5,7 @@ FP64 oracle can compute one by one:
 - H and G: whole rows of a few transducers (the oracle evaluates rows);
 - H^T: the full image for data that is nonzero on a few transducers (the
   kernel still walks every transducer's points), among them one transducer
-  in each of G^T's 22 windows of 96, so every window's fixed-point scale,
+  in each of G^T's 16 windows of 128, so every window's fixed-point scale,
   the FP64 sums of all windows and every slice of a brick's windows carry
   data;
 - the adjoint identity <Hx, y> = <x, H^T y> with random x and y on every
@@ -89,7 +89,7 @@ def test_full_size_backproject_two_transducers(large):
     check("H^T", a, want, 1e-5)
 
 
-def window_rows(n_det, window=96):
+def window_rows(n_det, window=128):
     """One transducer in every window of `window`, at a position within the
     window that moves from window to window (first, last and in between)."""
     rows = []
@@ -100,12 +100,12 @@ def window_rows(n_det, window=96):
 
 
 def test_full_size_backproject_one_row_per_window(large):
-    """Seeded data on one transducer in each of the 22 windows (and so in
-    all three brick slices), zero elsewhere: the whole H^T image against the
+    """Seeded data on one transducer in each of the 16 windows (and so in
+    every brick slice), zero elsewhere: the whole H^T image against the
     oracle's sum over those rows."""
     geom, img, plan = large
     rows = window_rows(geom.n_det)
-    assert rows.size == 22
+    assert rows.size == 16
     _say(f"[gpu-full] H^T with data on one transducer per window: {rows.tolist()}")
     rng = np.random.default_rng(14)
     y = np.zeros((geom.n_det, geom.n_t), dtype=np.float32)
@@ -115,8 +115,8 @@ def test_full_size_backproject_one_row_per_window(large):
     torch.cuda.synchronize()
     gd = geom.as_dict()
     y64 = y[rows].astype(np.float64)
-    check("H^T 22 windows", a.double().cpu().numpy(), ref.backproject(gd, y64, rows=rows), 1e-5)
-    check("G^T 22 windows", g.double().cpu().numpy(), ref.srt_adj(gd, y64, rows=rows), 1e-5)
+    check("H^T 16 windows", a.double().cpu().numpy(), ref.backproject(gd, y64, rows=rows), 1e-5)
+    check("G^T 16 windows", g.double().cpu().numpy(), ref.srt_adj(gd, y64, rows=rows), 1e-5)
 
 
 def test_full_size_adjoint_identity(large):

@@ -363,17 +363,17 @@ def test_project_with_wide_dynamic_range(Plan):
 
 @pytest.fixture(scope="module")
 def small1_plan(Plan):
-    """config_small's grid with 200 transducers: three windows of 96."""
+    """config_small's grid with 300 transducers: three windows of 128."""
     g = synth.config_small(1)[0]
     geom = synth.Geometry(g.nx, g.ny, g.nz, g.dx, g.x0, g.y0, g.z0,
-                          synth.fibonacci_sphere(200, 25.0), g.n_t, g.dt, g.t0, g.c0, g.gamma)
+                          synth.fibonacci_sphere(300, 25.0), g.n_t, g.dt, g.t0, g.c0, g.gamma)
     return geom, Plan(geom, 0)
 
 
-@pytest.mark.parametrize("q", [0, 15, 16, 95, 96, 191, 192, 199])
+@pytest.mark.parametrize("q", [0, 15, 16, 127, 128, 255, 256, 299])
 def test_backproject_single_transducer(q, small1_plan):
     """Data on one transducer only, at every position class of G^T's
-    transducer windows of 96 (first transducer, the ends of the first 16
+    transducer windows of 128 (first transducer, the ends of the first 16
     that the waves take, last of a window, first of the next, the partial
     last window): each window's scale must see that transducer's data."""
     geom, plan = small1_plan
@@ -387,7 +387,7 @@ def test_backproject_single_transducer(q, small1_plan):
 
 def _brick_slices(nbricks, items, min_items):
     """The library's slice count for a brick's work (G: transducers, G^T:
-    windows of 96 transducers), restated to check that a case uses slices."""
+    windows of 128 transducers), restated to check that a case uses slices."""
     best, best_eff = 1, 0.0
     for sl in range(1, 5):
         if sl > 1 and items // sl < min_items:
@@ -420,8 +420,8 @@ def _fill_slices(nbricks, items, min_items, max_slices, rnd):
 @pytest.mark.parametrize("table", list(TABLES))
 def test_transducer_slices(table, Plan):
     """8 bricks and 768 transducers: G takes each brick's transducers in 8
-    workgroups on the segment table and 4 on the other paths, and G^T its 8
-    windows (of 96) in 4, each with its own FP64 brick sums added in slice
+    workgroups on the segment table and 4 on the other paths, and G^T its 6
+    windows (of 128) in 3, each with its own FP64 brick sums added in slice
     order.  Parity with the oracle, and G^T bit-identical across the table
     paths."""
     geom0 = synth.config_small(1)[0]
@@ -429,7 +429,7 @@ def test_transducer_slices(table, Plan):
     geom = synth.Geometry(geom0.nx, geom0.ny, geom0.nz, geom0.dx, geom0.x0, geom0.y0, geom0.z0,
                           det, geom0.n_t, geom0.dt, geom0.t0, geom0.c0, 1.0)
     assert _fill_slices(8, 768, 64, 8, 512) == 8 and _brick_slices(8, 768, 64) == 4
-    assert _fill_slices(8, 768 // 96, 2, 8, 256) == 4
+    assert _fill_slices(8, 768 // 128, 2, 8, 256) == 3
     _say(f"[gpu] transducer slices, tables {table}")
     gd = geom.as_dict()
     rng = np.random.default_rng(21)
